@@ -1,0 +1,217 @@
+/*
+ * fmd.h — C ABI of fmdet, conditional flow-matching detector simulation on MI355X.
+ *
+ * The library computes  simulate(truth particle sets, seed, step schedule) -> reco sets.
+ * This is the problem the paper states for its detector backends (arXiv 2606.26089,
+ * program summary and Sec. 1): truth-level particles go in, detector-level
+ * reconstructed particles come out. The method is the neural backend (Sec. 2.2): a
+ * continuous-time model trained by conditional flow matching and conditioned on the
+ * event's truth particles. It is sampled by integrating its vector field from Gaussian
+ * noise with a run-time number of steps (App. C, generator block: num_steps,
+ * batch_size). The velocity network is a stand-in with caller-supplied weights.
+ *
+ * Conventions for every call:
+ *  - Every function returns an fmd_status. On a non-OK status, fmd_last_error() gives a
+ *    message for the calling thread, and no output buffer has been written.
+ *  - Nothing aborts, and no C++ exception crosses this interface.
+ *  - hip_stream is a hipStream_t, or NULL for the null stream. Work is enqueued
+ *    asynchronously on that stream. Device inputs are borrowed until that work
+ *    completes, and device outputs are valid only after it completes.
+ *  - Host arrays passed in are consumed before the call returns. For calls whose results
+ *    go to host memory, the call synchronises the stream before returning.
+ *  - A model is bound to the HIP device that was current at fmd_model_create(). Calls on
+ *    one model share its workspace, so they must be issued on one stream or serialised
+ *    by the caller.
+ *  - Particle sets are CSR. `offsets` is int64[n_events + 1], offsets[0] = 0,
+ *    non-decreasing, always in HOST memory. `feat` is float32
+ *    [offsets[n_events], n_feat], row-major, in host or device memory as `on_device`
+ *    says. Event e owns rows [offsets[e], offsets[e+1]). Empty events are legal and
+ *    produce no rows.
+ *  - There is one reco particle slot per truth particle, so reco sets use the truth
+ *    offsets.
+ */
+#ifndef FMD_H
+#define FMD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FMD_OK = 0,
+  FMD_PENDING = 1,          /* server: request not finished yet */
+  FMD_E_INVALID = -1,       /* bad argument (null pointer, bad offsets, bad config) */
+  FMD_E_NOMEM = -2,         /* device or host allocation failed */
+  FMD_E_BUDGET = -3,        /* server: request can never fit the HBM budget */
+  FMD_E_UNSUPPORTED = -4,   /* valid but unsupported (event larger than n_max, head dim) */
+  FMD_E_DEVICE = -5,        /* HIP runtime error */
+  FMD_E_STATE = -6          /* wrong object state (destroyed server, unknown request) */
+} fmd_status;
+
+typedef struct fmd_model fmd_model;     /* opaque */
+
+enum { FMD_FP32 = 0, FMD_BF16 = 1 };   /* precision of GEMM / attention operands */
+enum { FMD_EULER = 0, FMD_RK4 = 1 };   /* integration scheme */
+
+/* Network shape. Supported: d_model = n_heads * dh with dh in {16, 32, 64}; d_model a
+ * multiple of 64; mlp_ratio = 4; t_embed_dim = 32; f_truth = f_reco = 9; 1 <= n_max <= 4096.
+ * precision FMD_FP32 runs every GEMM and attention product as FP32 MFMA. FMD_BF16 feeds
+ * BF16 operands to the MFMA with FP32 accumulation. In both, the residual stream,
+ * LayerNorm and softmax statistics, the output head and the ODE state stay FP32. */
+typedef struct {
+  int32_t d_model, n_blocks, n_heads, mlp_ratio, t_embed_dim, f_truth, f_reco, n_max, precision;
+} fmd_model_config;
+
+typedef struct {
+  int64_t n_events;
+  const int64_t* offsets;   /* host, [n_events + 1] */
+  const float* feat;        /* [offsets[n_events], f_truth] FP32 */
+  int32_t on_device;        /* 1: feat is device memory, 0: host memory */
+} fmd_events_in;
+
+typedef struct {
+  float* feat;              /* [offsets[n_events], f_reco] FP32, caller-allocated */
+  int32_t on_device;
+} fmd_events_out;
+
+/* Uniform grid t_k = t0 + k h, h = (t1 - t0) / n_steps. Noise sits at t0, data at t1.
+ * The paper uses Euler with n_steps = 50 by default (Sec. 2.2, App. C). Classic RK4
+ * evaluates the field at t_k, t_k + h/2 (twice) and t_k + h. */
+typedef struct {
+  int32_t scheme, n_steps;
+  double t0, t1;
+} fmd_schedule;
+
+/* ---- model ------------------------------------------------------------------------ */
+
+/* Number of FP32 parameters of a config, in the flat order below. Returns 0 for an
+ * invalid config.
+ * Flat order (every matrix is [in, out] row-major, applied as y = x W + b; d = d_model,
+ * F = 9, E = t_embed_dim, R = mlp_ratio):
+ *   W_tin[F,d] b_tin[d] g_t[d] s_t[d]  W_xin[F,d] b_xin[d]  W_time[E,d] b_time[d]
+ *   per block: g1 s1 W_qkv[d,3d] b_qkv[3d] W_o[d,d] b_o  g2 s2 W_qc[d,d] b_qc W_kc[d,d] b_kc
+ *              W_vc[d,d] b_vc W_oc[d,d] b_oc  g3 s3 W_up[d,Rd] b_up[Rd] W_dn[Rd,d] b_dn
+ *   g_f s_f W_out[d,F] b_out[F]
+ * The columns of W_qkv are [Q | K | V]; head h owns columns [h dh, (h+1) dh) of each.
+ * The network:
+ *   c  = LN_t(u W_tin + b_tin)                                   (truth encoding)
+ *   H  = x W_xin + b_xin + phi(t) W_time + b_time,   phi(t) = [sin(w_k t) | cos(w_k t)],
+ *        w_k = 10000^(-k/(E/2))
+ *   per block: H += MHA(LN1 H, LN1 H) W_o + b_o; H += MHA(LN2 H, c) W_oc + b_oc;
+ *              H += GELU(LN3(H) W_up + b_up) W_dn + b_dn
+ *   v  = LN_f(H) W_out + b_out
+ * Attention is restricted to the event's own particles. LayerNorm uses eps 1e-5 and the
+ * biased variance. GELU is the exact erf form. */
+size_t fmd_param_count(const fmd_model_config* cfg);
+
+/* Copies `params` (host, n_params FP32 values in the flat order above) to the current
+ * device, repacked for the kernels (BF16 with round-to-nearest-even for FMD_BF16). The
+ * caller keeps ownership of `params`. *out receives a new handle. */
+int fmd_model_create(const fmd_model_config* cfg, const float* params, size_t n_params,
+                     fmd_model** out);
+int fmd_model_destroy(fmd_model* m);
+
+/* Analytic test field v(x, t) = (alpha + beta t) x. The handle runs the same integrator
+ * and state-update kernels as a network model. Its closed-form solution pins them:
+ * Euler gives prod_k (1 + h (alpha + beta t_k)) x0. Creating it touches no device, so
+ * argument validation can be exercised without a GPU. */
+int fmd_linear_field_create(double alpha, double beta, fmd_model** out);
+
+/* ---- sampling ----------------------------------------------------------------------- */
+
+/* Draws x0 ~ N(0, 1) for every reco slot from the seed, integrates the flow over the
+ * schedule, and writes the state at t1 (raw 9-feature rows, same layout as the truth
+ * features) to reco->feat.
+ * The noise of slot i of event e is Philox4x64-10 (Salmon et al., SC'11) of counter
+ * (b, i, e, 0) with key (seed, 0), b = 0, 1, 2 for features 0-3, 4-7, 8. Each 64-bit
+ * word w gives u = ((w >> 41) + 1/2) 2^-23. Box-Muller on word pairs (0,1), (2,3) gives
+ * r = sqrt(-2 ln u_a): z_a = r cos(2 pi u_b), z_b = r sin(2 pi u_b).
+ * e is the event's index within this call, so an event's result does not depend on the
+ * other events of the call.
+ * Errors: FMD_E_INVALID (null pointers, bad offsets, n_steps < 1, unknown scheme,
+ * t1 == t0); FMD_E_UNSUPPORTED (an event with more than n_max particles). */
+int fmd_simulate(fmd_model* m, const fmd_events_in* truth, uint64_t seed,
+                 const fmd_schedule* schedule, fmd_events_out* reco, void* hip_stream);
+
+/* As fmd_simulate, but starts from a given state x0 [offsets[n], f_reco] FP32. x0 lives
+ * where truth->feat lives (on_device). */
+int fmd_simulate_from_state(fmd_model* m, const fmd_events_in* truth, const float* x0,
+                            const fmd_schedule* schedule, fmd_events_out* reco,
+                            void* hip_stream);
+
+/* One evaluation of the velocity field: v = v(x, t_e | truth). x and v are
+ * [offsets[n], f_reco] FP32. t_per_event is [n_events] FP32. All three live where
+ * truth->feat lives. */
+int fmd_velocity(fmd_model* m, const fmd_events_in* truth, const float* x,
+                 const float* t_per_event, float* v, void* hip_stream);
+
+/* The initial noise alone: x0 [offsets[n_events], n_feat] FP32 in DEVICE memory, with
+ * n_feat <= 12 and the law of fmd_simulate. */
+int fmd_noise(uint64_t seed, const int64_t* offsets, int64_t n_events, int32_t n_feat,
+              float* x0_device, void* hip_stream);
+
+/* Ragged packing. `padded` is [n_events, n_max, f] FP32 (device), lengths is int32
+ * [n_events] (device); lengths are clamped to [0, n_max]. The call writes offsets_out
+ * int64[n_events + 1] (device, exclusive prefix sum of the lengths) and feat_out
+ * [sum(lengths), f] (device, rows of each event in order). Pad rows are never read.
+ * The capacity of feat_out is n_events * n_max rows. */
+int fmd_pack_padded(const float* padded, const int32_t* lengths, int64_t n_events,
+                    int32_t n_max, int32_t f, int64_t* offsets_out, float* feat_out,
+                    void* hip_stream);
+
+/* Raw Philox4x64-10 blocks, for bit-exact checks of the noise generator: for i < n,
+ * out[i] = Philox4x64-10(counters[i], key = (key0, key1)). counters and out are uint64
+ * [n, 4] in DEVICE memory. */
+int fmd_debug_philox(uint64_t key0, uint64_t key1, const uint64_t* counters, int64_t n,
+                     uint64_t* out, void* hip_stream);
+
+/* ---- instrumentation ----------------------------------------------------------------- */
+
+/* Kernel classes timed by HIP events on the launch stream when timing is on. */
+enum { FMD_K_GEMM_QKV = 0, FMD_K_GEMM_PROJ = 1, FMD_K_GEMM_UP = 2, FMD_K_GEMM_DOWN = 3,
+       FMD_K_ATTN_SELF = 4, FMD_K_ATTN_CROSS = 5, FMD_K_OTHER = 6, FMD_K_COUNT = 7 };
+
+/* Turns on (1) or off (0) per-launch timing of the kernel classes above and clears the
+ * counters. Timing brackets each launch with events and adds a little host overhead. */
+int fmd_timing_enable(fmd_model* m, int32_t enable);
+
+/* Reads the counters of one class: total device milliseconds, number of launches, and
+ * algorithmic work. The work counts the FLOPs of the method, excluding padding and
+ * recomputation, or the minimal HBM bytes for HBM-bound kernels.
+ * Synchronises the device. */
+int fmd_timing_read(fmd_model* m, int32_t kernel_class, double* total_ms, int64_t* launches,
+                    double* work);
+
+/* Name of the HIP kernel behind a class, as rocprofv3 reports it (static string). */
+const char* fmd_kernel_name(fmd_model* m, int32_t kernel_class);
+
+/* ---- kernel test hooks (used by the parity tests) --------------------------------------- */
+
+/* C[M,N] = epi(pro(A) W + b) with the model's GEMM kernel, all operands DEVICE FP32.
+ * W is [K,N] row-major. With ln != 0, pro(A) = LN(A; g, s) over K features, otherwise
+ * pro(A) = A. epi: 0 = store, 1 = exact GELU, 2 = accumulate (C += ...). For FMD_BF16,
+ * A (after LN), W and the GELU output are rounded to BF16 as in the model.
+ * Requires K % 32 == 0 and N % 64 == 0. */
+int fmd_debug_gemm(int32_t precision, int64_t M, int32_t N, int32_t K, const float* A,
+                   const float* W, const float* bias, int32_t ln, const float* g,
+                   const float* s, int32_t epi, float* C, void* hip_stream);
+
+/* Masked multi-head attention per event with the model's kernel, all operands DEVICE FP32.
+ * Q is [Tq, H*dh] and K, V are [Tk, H*dh] in CSR events (q_offsets, kv_offsets: host
+ * int64 [n_events+1]). O is [Tq, H*dh]. Each query attends to the keys of its own event
+ * only. For FMD_BF16, Q, K, V and the probabilities are rounded to BF16. */
+int fmd_debug_attention(int32_t precision, int64_t n_events, const int64_t* q_offsets,
+                        const int64_t* kv_offsets, int32_t n_heads, int32_t dh,
+                        const float* Q, const float* K, const float* V, float* O,
+                        void* hip_stream);
+
+/* Message for the last non-OK status of the calling thread ("" if none). */
+const char* fmd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FMD_H */

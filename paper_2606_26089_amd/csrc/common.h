@@ -1,0 +1,53 @@
+// Device-side helpers shared by the fmdet kernels (gfx950 / CDNA4, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fmd {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16;
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));   // 16-byte register chunk
+
+constexpr int kWave = 64;
+constexpr int kXcds = 8;          // MI355X: 8 accelerator complex dies, 32 CUs each
+constexpr float kLnEps = 1e-5f;
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, kWave));
+  return v;
+}
+
+// Workgroups of a 1-D launch are dealt round-robin to the XCDs (block b runs on XCD b % 8).
+// Renumber them so that each XCD owns one contiguous range of logical tiles: neighbouring
+// tiles that share an operand then share that XCD's L2. A bijection on [0, n).
+__device__ __forceinline__ int xcd_remap(int b, int n) {
+  const int q = n / kXcds, r = n % kXcds;
+  const int xcd = b % kXcds, local = b / kXcds;
+  return xcd < r ? xcd * (q + 1) + local : r * (q + 1) + (xcd - r) * q + local;
+}
+
+template <typename T> __device__ __forceinline__ T from_f32(float x);
+template <> __device__ __forceinline__ float from_f32<float>(float x) { return x; }
+template <> __device__ __forceinline__ bf16 from_f32<bf16>(float x) { return (bf16)x; }  // RNE
+
+__device__ __forceinline__ float to_f32(float x) { return x; }
+__device__ __forceinline__ float to_f32(bf16 x) { return (float)x; }
+
+// Exact GELU through erf.
+__device__ __forceinline__ float gelu_erf(float z) {
+  return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f));
+}
+
+}  // namespace fmd

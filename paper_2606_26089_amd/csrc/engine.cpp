@@ -1,0 +1,875 @@
+// fmdet engine: model handles, validation, workspace, the ODE stage loop and the C ABI.
+//
+// One velocity evaluation over the packed tokens of all events of a call runs as:
+//   time embedding -> input embedding -> L x [LN1+QKV GEMM -> self attention -> W_o
+//   GEMM (+residual) -> LN2+Q_c GEMM -> cross attention (cached truth K/V) -> W_oc GEMM
+//   (+residual) -> LN3+W_up GEMM+GELU -> W_dn GEMM (+residual)] -> LN_f + head + fused
+//   Euler/RK4 state update.
+// The truth encoding and the per-block cross-attention K/V are constant over the whole
+// integration, so they are computed once per call into a cache.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "engine.h"
+#include "kernels.h"
+
+using namespace fmd;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int status, const char* fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return status;
+}
+
+#define HIP_TRY(expr)                                                                    \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return fail(FMD_E_DEVICE, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, \
+                  __LINE__);                                                             \
+  } while (0)
+
+#define FMD_TRY(expr)              \
+  do {                             \
+    int s_ = (expr);               \
+    if (s_ != FMD_OK) return s_;   \
+  } while (0)
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+
+// ---------------------------------------------------------------------------------------
+// configuration and parameter layout
+
+int check_cfg(const fmd_model_config* c) {
+  if (!c) return fail(FMD_E_INVALID, "null model config");
+  if (c->d_model <= 0 || c->n_blocks <= 0 || c->n_heads <= 0)
+    return fail(FMD_E_INVALID, "d_model, n_blocks and n_heads must be positive");
+  if (c->d_model % c->n_heads)
+    return fail(FMD_E_INVALID, "d_model %d is not a multiple of n_heads %d", c->d_model, c->n_heads);
+  if (c->d_model % 64 || c->d_model > 1024)
+    return fail(FMD_E_UNSUPPORTED, "d_model must be a multiple of 64 and at most 1024");
+  const int dh = c->d_model / c->n_heads;
+  if (dh != 16 && dh != 32 && dh != 64)
+    return fail(FMD_E_UNSUPPORTED, "head dimension %d not in {16, 32, 64}", dh);
+  if (c->mlp_ratio != 4) return fail(FMD_E_UNSUPPORTED, "mlp_ratio must be 4");
+  if (c->t_embed_dim != 32) return fail(FMD_E_UNSUPPORTED, "t_embed_dim must be 32");
+  if (c->f_truth != 9 || c->f_reco != 9) return fail(FMD_E_UNSUPPORTED, "f_truth and f_reco must be 9");
+  if (c->n_max < 1 || c->n_max > 4096) return fail(FMD_E_UNSUPPORTED, "n_max must be in [1, 4096]");
+  if (c->precision != FMD_FP32 && c->precision != FMD_BF16)
+    return fail(FMD_E_INVALID, "unknown precision %d", c->precision);
+  return FMD_OK;
+}
+
+// Walks the flat parameter order, calling f(name_id, offset, rows, cols) per tensor
+// (cols = 0 for vectors). Returns the total count.
+enum PId {
+  P_W_TIN, P_B_TIN, P_G_T, P_S_T, P_W_XIN, P_B_XIN, P_W_TIME, P_B_TIME,
+  P_G1, P_S1, P_W_QKV, P_B_QKV, P_W_O, P_B_O, P_G2, P_S2, P_W_QC, P_B_QC, P_W_KC, P_B_KC,
+  P_W_VC, P_B_VC, P_W_OC, P_B_OC, P_G3, P_S3, P_W_UP, P_B_UP, P_W_DN, P_B_DN,
+  P_G_F, P_S_F, P_W_OUT, P_B_OUT
+};
+
+template <typename F>
+size_t walk_params(const fmd_model_config& c, F&& f) {
+  const int64_t d = c.d_model, F_ = c.f_truth, Fo = c.f_reco, E = c.t_embed_dim, R = c.mlp_ratio;
+  size_t o = 0;
+  auto put = [&](int id, int blk, int64_t rows, int64_t cols) {
+    f(id, blk, o, rows, cols);
+    o += (size_t)(rows * (cols ? cols : 1));
+  };
+  put(P_W_TIN, -1, F_, d); put(P_B_TIN, -1, d, 0); put(P_G_T, -1, d, 0); put(P_S_T, -1, d, 0);
+  put(P_W_XIN, -1, Fo, d); put(P_B_XIN, -1, d, 0); put(P_W_TIME, -1, E, d); put(P_B_TIME, -1, d, 0);
+  for (int l = 0; l < c.n_blocks; ++l) {
+    put(P_G1, l, d, 0); put(P_S1, l, d, 0); put(P_W_QKV, l, d, 3 * d); put(P_B_QKV, l, 3 * d, 0);
+    put(P_W_O, l, d, d); put(P_B_O, l, d, 0);
+    put(P_G2, l, d, 0); put(P_S2, l, d, 0); put(P_W_QC, l, d, d); put(P_B_QC, l, d, 0);
+    put(P_W_KC, l, d, d); put(P_B_KC, l, d, 0); put(P_W_VC, l, d, d); put(P_B_VC, l, d, 0);
+    put(P_W_OC, l, d, d); put(P_B_OC, l, d, 0);
+    put(P_G3, l, d, 0); put(P_S3, l, d, 0); put(P_W_UP, l, d, R * d); put(P_B_UP, l, R * d, 0);
+    put(P_W_DN, l, R * d, d); put(P_B_DN, l, d, 0);
+  }
+  put(P_G_F, -1, d, 0); put(P_S_F, -1, d, 0); put(P_W_OUT, -1, d, Fo); put(P_B_OUT, -1, Fo, 0);
+  return o;
+}
+
+size_t elem_size(const fmd_model_config& c) { return c.precision == FMD_BF16 ? 2 : 4; }
+
+// ---------------------------------------------------------------------------------------
+// workspace
+
+template <typename P>
+int grow(P*& p, size_t bytes) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+  if (bytes == 0) return FMD_OK;
+  if (hipMalloc((void**)&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    p = nullptr;
+    return fail(FMD_E_NOMEM, "device allocation of %zu bytes failed", bytes);
+  }
+  if (hipMemset(p, 0, bytes) != hipSuccess) return fail(FMD_E_DEVICE, "hipMemset failed");
+  return FMD_OK;
+}
+
+template <typename P>
+int grow_host(P*& p, size_t bytes) {
+  if (p) (void)hipHostFree(p);
+  p = nullptr;
+  if (hipHostMalloc((void**)&p, bytes, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    p = nullptr;
+    return fail(FMD_E_NOMEM, "pinned host allocation of %zu bytes failed", bytes);
+  }
+  return FMD_OK;
+}
+
+void free_ws(Workspace& w) {
+  void* dev[] = {w.x, w.acc, w.xs, w.H, w.qkv, w.att, w.qc, w.hid, w.c, w.kv, w.u, w.io,
+                 w.temb, w.tev, w.tok_event, w.off, w.work};
+  for (void* p : dev)
+    if (p) (void)hipFree(p);
+  if (w.h_off) (void)hipHostFree(w.h_off);
+  if (w.h_work) (void)hipHostFree(w.h_work);
+  w = Workspace();
+}
+
+int ensure_ws_alloc(fmd_model* m, int64_t T, int64_t E, int64_t items, bool* grew);
+
+// Grows the workspace; new buffers are zero-filled and the device is synchronised so that
+// no stream can observe them before the fill.
+int ensure_ws(fmd_model* m, int64_t T, int64_t E, int64_t items) {
+  bool grew = false;
+  FMD_TRY(ensure_ws_alloc(m, T, E, items, &grew));
+  if (grew) HIP_TRY(hipDeviceSynchronize());
+  return FMD_OK;
+}
+
+int ensure_ws_alloc(fmd_model* m, int64_t T, int64_t E, int64_t items, bool* grew) {
+  Workspace& w = m->ws;
+  const fmd_model_config& c = m->cfg;
+  const size_t es = m->kind == 0 ? elem_size(c) : 4;
+  const int64_t d = m->kind == 0 ? c.d_model : 64, L = m->kind == 0 ? c.n_blocks : 1;
+  const int64_t Tp = round_up(std::max<int64_t>(T, 1), kGemmBM);
+  if (Tp > w.cap_tok) {
+    const int64_t cap = std::max(Tp, round_up(w.cap_tok + w.cap_tok / 4, kGemmBM));
+    const size_t st = (size_t)cap * kStateLd * 4;
+    FMD_TRY(grow(w.x, st));
+    FMD_TRY(grow(w.acc, st));
+    FMD_TRY(grow(w.xs, st));
+    FMD_TRY(grow(w.u, (size_t)cap * 9 * 4));
+    FMD_TRY(grow(w.io, (size_t)cap * 9 * 4));
+    FMD_TRY(grow(w.tok_event, (size_t)cap * 4));
+    if (m->kind == 0) {
+      FMD_TRY(grow(w.H, (size_t)cap * d * 4));
+      FMD_TRY(grow(w.qkv, (size_t)cap * 3 * d * es));
+      FMD_TRY(grow(w.att, (size_t)cap * d * es));
+      FMD_TRY(grow(w.qc, (size_t)cap * d * es));
+      FMD_TRY(grow(w.hid, (size_t)cap * 4 * d * es));
+      FMD_TRY(grow(w.c, (size_t)cap * d * es));
+      FMD_TRY(grow(w.kv, (size_t)cap * 2 * d * L * es));
+    }
+    w.cap_tok = cap;
+    w.elem = es;
+    *grew = true;
+  }
+  if (E + 1 > w.cap_ev) {
+    const int64_t cap = std::max(E + 1, w.cap_ev + w.cap_ev / 4);
+    FMD_TRY(grow(w.off, (size_t)cap * 8));
+    FMD_TRY(grow(w.tev, (size_t)cap * 4));
+    FMD_TRY(grow(w.temb, (size_t)cap * d * 4));
+    w.cap_ev = cap;
+    *grew = true;
+  }
+  if (E + 1 > w.h_cap_ev) {
+    FMD_TRY(grow_host(w.h_off, (size_t)(E + 1) * 8));
+    w.h_cap_ev = E + 1;
+  }
+  if (items > w.cap_items) {
+    const int64_t cap = std::max(items, w.cap_items + w.cap_items / 4);
+    FMD_TRY(grow(w.work, (size_t)cap * sizeof(int2)));
+    w.cap_items = cap;
+    *grew = true;
+  }
+  if (items > w.h_cap_items) {
+    FMD_TRY(grow_host(w.h_work, (size_t)std::max<int64_t>(items, 1) * sizeof(int2)));
+    w.h_cap_items = items;
+  }
+  return FMD_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// validation
+
+int check_events(const fmd_model* m, const fmd_events_in* ev, int64_t* T_out, int64_t* max_n) {
+  if (!ev) return fail(FMD_E_INVALID, "null event set");
+  if (ev->n_events < 0) return fail(FMD_E_INVALID, "negative n_events");
+  if (!ev->offsets) return fail(FMD_E_INVALID, "null offsets");
+  if (ev->offsets[0] != 0) return fail(FMD_E_INVALID, "offsets[0] must be 0");
+  int64_t mx = 0;
+  for (int64_t e = 0; e < ev->n_events; ++e) {
+    const int64_t n = ev->offsets[e + 1] - ev->offsets[e];
+    if (n < 0) return fail(FMD_E_INVALID, "offsets decrease at event %lld", (long long)e);
+    mx = std::max(mx, n);
+  }
+  if (m && m->kind == 0 && mx > m->cfg.n_max)
+    return fail(FMD_E_UNSUPPORTED, "an event has %lld particles, above n_max %d", (long long)mx,
+                m->cfg.n_max);
+  const int64_t T = ev->offsets[ev->n_events];
+  if (T > ((int64_t)1 << 31) - 4096) return fail(FMD_E_UNSUPPORTED, "too many particles in one call");
+  if (T > 0 && !ev->feat) return fail(FMD_E_INVALID, "null feature array");
+  *T_out = T;
+  if (max_n) *max_n = mx;
+  return FMD_OK;
+}
+
+int check_schedule(const fmd_schedule* s) {
+  if (!s) return fail(FMD_E_INVALID, "null schedule");
+  if (s->scheme != FMD_EULER && s->scheme != FMD_RK4)
+    return fail(FMD_E_INVALID, "unknown scheme %d", s->scheme);
+  if (s->n_steps < 1) return fail(FMD_E_INVALID, "n_steps must be >= 1");
+  if (!std::isfinite(s->t0) || !std::isfinite(s->t1) || s->t0 == s->t1)
+    return fail(FMD_E_INVALID, "t0 and t1 must be finite and different");
+  return FMD_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// timing
+
+hipEvent_t take_event(fmd_model* m) {
+  if (!m->ev_pool.empty()) {
+    hipEvent_t e = m->ev_pool.back();
+    m->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+void flush_timing(fmd_model* m) {
+  for (auto& r : m->trec) {
+    float ms = 0.f;
+    if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      m->t_ms[r.cls] += ms;
+      m->t_n[r.cls] += 1;
+      m->t_work[r.cls] += r.work;
+    }
+    m->ev_pool.push_back(r.a);
+    m->ev_pool.push_back(r.b);
+  }
+  m->trec.clear();
+}
+
+template <typename F>
+int timed(fmd_model* m, hipStream_t st, int cls, double work, F&& launch) {
+  hipEvent_t a = nullptr, b = nullptr;
+  if (m->timing) {
+    if (m->trec.size() > 4096) flush_timing(m);
+    a = take_event(m);
+    b = take_event(m);
+    if (a && b) (void)hipEventRecord(a, st);
+  }
+  const hipError_t e = launch();
+  if (e != hipSuccess) return fail(FMD_E_DEVICE, "kernel launch (class %d): %s", cls, hipGetErrorString(e));
+  if (m->timing && a && b) {
+    (void)hipEventRecord(b, st);
+    m->trec.push_back(TimingRec{cls, work, a, b});
+  }
+  return FMD_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// one call's device state
+
+struct Call {
+  hipStream_t st;
+  int64_t E, T, Tp, items;
+  double sum_n2;        // sum over events of N_e^2 (attention work)
+  const float* u;       // truth features on device [T, 9]
+};
+
+// Uploads offsets and the attention work list; runs the token map.
+int stage_events(fmd_model* m, const fmd_events_in* ev, Call& c) {
+  Workspace& w = m->ws;
+  const int64_t E = ev->n_events;
+  // work items: (event, 64-query tile), longest events first
+  std::vector<int64_t> order;
+  order.reserve(E);
+  int64_t items = 0;
+  double s2 = 0;
+  for (int64_t e = 0; e < E; ++e) {
+    const int64_t n = ev->offsets[e + 1] - ev->offsets[e];
+    if (n > 0) order.push_back(e);
+    items += (n + 63) / 64;
+    s2 += (double)n * (double)n;
+  }
+  std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
+    return ev->offsets[a + 1] - ev->offsets[a] > ev->offsets[b + 1] - ev->offsets[b];
+  });
+  c.items = items;
+  c.sum_n2 = s2;
+  FMD_TRY(ensure_ws(m, c.T, E, items));
+  // The pinned staging buffers may still feed the previous call's copies.
+  HIP_TRY(hipStreamSynchronize(c.st));
+  std::memcpy(w.h_off, ev->offsets, (size_t)(E + 1) * 8);
+  int64_t k = 0;
+  for (int64_t e : order) {
+    const int64_t n = ev->offsets[e + 1] - ev->offsets[e];
+    for (int64_t q = 0; q < (n + 63) / 64; ++q) w.h_work[k++] = make_int2((int)e, (int)q);
+  }
+  HIP_TRY(hipMemcpyAsync(w.off, w.h_off, (size_t)(E + 1) * 8, hipMemcpyHostToDevice, c.st));
+  if (items) HIP_TRY(hipMemcpyAsync(w.work, w.h_work, (size_t)items * sizeof(int2), hipMemcpyHostToDevice, c.st));
+  FMD_TRY(timed(m, c.st, FMD_K_OTHER, 0, [&] { return launch_token_map(c.st, w.off, E, c.T, w.tok_event); }));
+  if (ev->on_device) {
+    c.u = ev->feat;
+  } else {
+    HIP_TRY(hipMemcpyAsync(w.u, ev->feat, (size_t)c.T * 9 * 4, hipMemcpyHostToDevice, c.st));
+    c.u = w.u;
+  }
+  return FMD_OK;
+}
+
+template <typename T>
+int truth_cache(fmd_model* m, Call& c) {
+  Workspace& w = m->ws;
+  const fmd_model_config& cf = m->cfg;
+  const int d = cf.d_model, L = cf.n_blocks;
+  FMD_TRY(timed(m, c.st, FMD_K_OTHER, 0, [&] {
+    return launch_truth_encode<T>(c.st, c.u, 9, 9, c.T, m->W_tin, m->b_tin, m->g_t, m->s_t, d,
+                                  (T*)w.c, d);
+  }));
+  FMD_TRY(timed(m, c.st, FMD_K_OTHER, 2.0 * c.T * d * 2 * d * L, [&] {
+    return launch_gemm<T>(c.st, FMD_K_OTHER, false, EPI_STORE, c.Tp, 2 * d * L, d, w.c, d,
+                          (const T*)m->Wkv, m->bkv, nullptr, nullptr, w.kv, 2 * d * L);
+  }));
+  return FMD_OK;
+}
+
+// One evaluation of the velocity network at xs; leaves the residual stream in w.H.
+template <typename T>
+int net_forward(fmd_model* m, Call& c, const float* t_ev, float t) {
+  Workspace& w = m->ws;
+  const fmd_model_config& cf = m->cfg;
+  const int d = cf.d_model, L = cf.n_blocks, Hh = cf.n_heads, dh = d / Hh;
+  const double Td = (double)c.T;
+  const size_t es = sizeof(T);
+  char* qkv = (char*)w.qkv;
+  char* kv = (char*)w.kv;
+  FMD_TRY(timed(m, c.st, FMD_K_OTHER, 0, [&] {
+    return launch_time_embed(c.st, t_ev, t, t_ev ? (int)c.E : 1, m->W_time, m->b_time, m->b_xin,
+                             cf.t_embed_dim, d, w.temb);
+  }));
+  FMD_TRY(timed(m, c.st, FMD_K_OTHER, 0, [&] {
+    return launch_embed(c.st, w.xs, kStateLd, 9, c.T, t_ev ? w.tok_event : nullptr, w.temb,
+                        m->W_xin, d, w.H, d);
+  }));
+  for (int l = 0; l < L; ++l) {
+    const DevBlock& B = m->blk[l];
+    FMD_TRY(timed(m, c.st, FMD_K_GEMM_QKV, 2.0 * Td * d * 3 * d, [&] {
+      return launch_gemm<T>(c.st, FMD_K_GEMM_QKV, true, EPI_STORE, c.Tp, 3 * d, d, w.H, d,
+                            (const T*)B.Wqkv, B.bqkv, B.g1, B.s1, w.qkv, 3 * d);
+    }));
+    FMD_TRY(timed(m, c.st, FMD_K_ATTN_SELF, 4.0 * c.sum_n2 * d, [&] {
+      return launch_attention<T>(c.st, false, dh, Hh, c.items, w.work, (const T*)qkv, 3 * d,
+                                 (const T*)(qkv + d * es), (const T*)(qkv + 2 * d * es), 3 * d,
+                                 (T*)w.att, d, w.off, w.off);
+    }));
+    FMD_TRY(timed(m, c.st, FMD_K_GEMM_PROJ, 2.0 * Td * d * d, [&] {
+      return launch_gemm<T>(c.st, FMD_K_GEMM_PROJ, false, EPI_RESID, c.Tp, d, d, w.att, d,
+                            (const T*)B.Wo, B.bo, nullptr, nullptr, w.H, d);
+    }));
+    FMD_TRY(timed(m, c.st, FMD_K_GEMM_PROJ, 2.0 * Td * d * d, [&] {
+      return launch_gemm<T>(c.st, FMD_K_GEMM_PROJ, true, EPI_STORE, c.Tp, d, d, w.H, d,
+                            (const T*)B.Wqc, B.bqc, B.g2, B.s2, w.qc, d);
+    }));
+    FMD_TRY(timed(m, c.st, FMD_K_ATTN_CROSS, 4.0 * c.sum_n2 * d, [&] {
+      const size_t o = (size_t)l * 2 * d * es;
+      return launch_attention<T>(c.st, true, dh, Hh, c.items, w.work, (const T*)w.qc, d,
+                                 (const T*)(kv + o), (const T*)(kv + o + d * es), 2 * d * L,
+                                 (T*)w.att, d, w.off, w.off);
+    }));
+    FMD_TRY(timed(m, c.st, FMD_K_GEMM_PROJ, 2.0 * Td * d * d, [&] {
+      return launch_gemm<T>(c.st, FMD_K_GEMM_PROJ, false, EPI_RESID, c.Tp, d, d, w.att, d,
+                            (const T*)B.Woc, B.boc, nullptr, nullptr, w.H, d);
+    }));
+    FMD_TRY(timed(m, c.st, FMD_K_GEMM_UP, 2.0 * Td * d * 4 * d, [&] {
+      return launch_gemm<T>(c.st, FMD_K_GEMM_UP, true, EPI_GELU, c.Tp, 4 * d, d, w.H, d,
+                            (const T*)B.Wup, B.bup, B.g3, B.s3, w.hid, 4 * d);
+    }));
+    FMD_TRY(timed(m, c.st, FMD_K_GEMM_DOWN, 2.0 * Td * 4 * d * d, [&] {
+      return launch_gemm<T>(c.st, FMD_K_GEMM_DOWN, false, EPI_RESID, c.Tp, d, 4 * d, w.hid,
+                            4 * d, (const T*)B.Wdn, B.bdn, nullptr, nullptr, w.H, d);
+    }));
+  }
+  return FMD_OK;
+}
+
+int head(fmd_model* m, Call& c, int mode, float h, float t, float* out, int ldo) {
+  Workspace& w = m->ws;
+  if (m->kind == 1)
+    return timed(m, c.st, FMD_K_OTHER, 0, [&] {
+      return launch_linear_update(c.st, (float)m->alpha, (float)m->beta, t, c.T, 9, mode, h, w.x,
+                                  w.acc, w.xs, kStateLd, out, ldo);
+    });
+  return timed(m, c.st, FMD_K_OTHER, 0, [&] {
+    return launch_head_update(c.st, w.H, m->cfg.d_model, m->cfg.d_model, c.T, m->g_f, m->s_f,
+                              m->W_out, m->b_out, 9, mode, h, w.x, w.acc, w.xs, kStateLd, out, ldo);
+  });
+}
+
+template <typename T>
+int integrate(fmd_model* m, Call& c, const fmd_schedule* s, float* out, int ldo) {
+  const int K = s->n_steps;
+  const double h = (s->t1 - s->t0) / K;
+  static const double c_rk4[4] = {0.0, 0.5, 0.5, 1.0};
+  for (int k = 0; k < K; ++k) {
+    const int S = s->scheme == FMD_EULER ? 1 : 4;
+    for (int st = 0; st < S; ++st) {
+      const double t = s->t0 + (k + (S == 1 ? 0.0 : c_rk4[st])) * h;
+      if (m->kind == 0) FMD_TRY(net_forward<T>(m, c, nullptr, (float)t));
+      const int mode = S == 1 ? UPD_EULER : UPD_RK4_0 + st;
+      const bool last = k == K - 1 && st == S - 1;
+      FMD_TRY(head(m, c, mode, (float)h, (float)t, last ? out : nullptr, ldo));
+    }
+  }
+  return FMD_OK;
+}
+
+int simulate_impl(fmd_model* m, const fmd_events_in* truth, const float* x0, uint64_t seed,
+                  const fmd_schedule* sched, fmd_events_out* reco, void* stream) {
+  if (!m) return fail(FMD_E_INVALID, "null model");
+  Call c{};
+  c.st = (hipStream_t)stream;
+  FMD_TRY(check_events(m, truth, &c.T, nullptr));
+  FMD_TRY(check_schedule(sched));
+  if (!reco) return fail(FMD_E_INVALID, "null reco output");
+  if (c.T > 0 && !reco->feat) return fail(FMD_E_INVALID, "null reco feature array");
+  c.E = truth->n_events;
+  if (c.T == 0) return FMD_OK;
+  DeviceGuard guard(m->device);
+  c.Tp = round_up(c.T, kGemmBM);
+  FMD_TRY(stage_events(m, truth, c));
+  Workspace& w = m->ws;
+  if (x0) {
+    const float* src = x0;
+    if (!truth->on_device) {
+      HIP_TRY(hipMemcpyAsync(w.io, x0, (size_t)c.T * 9 * 4, hipMemcpyHostToDevice, c.st));
+      src = w.io;
+    }
+    FMD_TRY(timed(m, c.st, FMD_K_OTHER, 0, [&] { return launch_load_state(c.st, src, 9, c.T, w.x, w.xs, kStateLd); }));
+  } else {
+    FMD_TRY(timed(m, c.st, FMD_K_OTHER, 0, [&] {
+      return launch_noise(c.st, seed, w.off, w.tok_event, c.T, 9, w.x, w.xs, kStateLd);
+    }));
+  }
+  float* out = reco->on_device ? reco->feat : w.io;
+  if (m->kind == 0) {
+    if (m->cfg.precision == FMD_BF16) {
+      FMD_TRY(truth_cache<bf16>(m, c));
+      FMD_TRY(integrate<bf16>(m, c, sched, out, 9));
+    } else {
+      FMD_TRY(truth_cache<float>(m, c));
+      FMD_TRY(integrate<float>(m, c, sched, out, 9));
+    }
+  } else {
+    FMD_TRY(integrate<float>(m, c, sched, out, 9));
+  }
+  if (!reco->on_device) {
+    HIP_TRY(hipMemcpyAsync(reco->feat, w.io, (size_t)c.T * 9 * 4, hipMemcpyDeviceToHost, c.st));
+    HIP_TRY(hipStreamSynchronize(c.st));
+  }
+  return FMD_OK;
+}
+
+}  // namespace
+
+// =======================================================================================
+// C ABI
+
+extern "C" {
+
+const char* fmd_last_error(void) { return g_err.c_str(); }
+
+size_t fmd_param_count(const fmd_model_config* cfg) {
+  if (check_cfg(cfg) != FMD_OK) return 0;
+  return walk_params(*cfg, [](int, int, size_t, int64_t, int64_t) {});
+}
+
+int fmd_model_create(const fmd_model_config* cfg, const float* params, size_t n_params,
+                     fmd_model** out) {
+  FMD_TRY(check_cfg(cfg));
+  if (!params || !out) return fail(FMD_E_INVALID, "null params or out");
+  const size_t need = fmd_param_count(cfg);
+  if (n_params != need)
+    return fail(FMD_E_INVALID, "parameter vector has %zu values, the config needs %zu", n_params, need);
+  fmd_model* m = new fmd_model();
+  m->cfg = *cfg;
+  auto bail = [&](int s) {
+    fmd_model_destroy(m);
+    return s;
+  };
+  if (hipGetDevice(&m->device) != hipSuccess) return bail(fail(FMD_E_DEVICE, "no HIP device"));
+  if (grow(m->params, need * 4) != FMD_OK) return bail(FMD_E_NOMEM);
+  if (hipMemcpy(m->params, params, need * 4, hipMemcpyHostToDevice) != hipSuccess)
+    return bail(fail(FMD_E_DEVICE, "parameter upload failed"));
+  const int64_t d = cfg->d_model, L = cfg->n_blocks;
+  const size_t es = elem_size(*cfg);
+  const size_t blk_elems = 14 * d * d;
+  if (grow(m->packed, (L * blk_elems) * es) != FMD_OK) return bail(FMD_E_NOMEM);
+  if (grow(m->Wkv, (size_t)(L * 2 * d * d) * es) != FMD_OK) return bail(FMD_E_NOMEM);
+  if (grow(m->bkv, (size_t)(L * 2 * d) * 4) != FMD_OK) return bail(FMD_E_NOMEM);
+  m->blk.assign(L, DevBlock{});
+  char* pk = (char*)m->packed;
+  char* wkv = (char*)m->Wkv;
+  int status = FMD_OK;
+  auto pack = [&](size_t off, int64_t rows, int64_t cols, void* dst) {
+    const float* W = m->params + off;
+    hipError_t e = cfg->precision == FMD_BF16
+                       ? launch_pack_weight<bf16>(nullptr, W, (int)rows, (int)cols, (bf16*)dst)
+                       : launch_pack_weight<float>(nullptr, W, (int)rows, (int)cols, (float*)dst);
+    if (e != hipSuccess && status == FMD_OK) status = fail(FMD_E_DEVICE, "weight packing failed");
+  };
+  walk_params(*cfg, [&](int id, int l, size_t off, int64_t rows, int64_t cols) {
+    const float* p = m->params + off;
+    DevBlock* B = l >= 0 ? &m->blk[l] : nullptr;
+    char* base = l >= 0 ? pk + (size_t)l * blk_elems * es : nullptr;
+    switch (id) {
+      case P_W_TIN: m->W_tin = p; break;
+      case P_B_TIN: m->b_tin = p; break;
+      case P_G_T: m->g_t = p; break;
+      case P_S_T: m->s_t = p; break;
+      case P_W_XIN: m->W_xin = p; break;
+      case P_B_XIN: m->b_xin = p; break;
+      case P_W_TIME: m->W_time = p; break;
+      case P_B_TIME: m->b_time = p; break;
+      case P_G1: B->g1 = p; break;
+      case P_S1: B->s1 = p; break;
+      case P_G2: B->g2 = p; break;
+      case P_S2: B->s2 = p; break;
+      case P_G3: B->g3 = p; break;
+      case P_S3: B->s3 = p; break;
+      case P_B_QKV: B->bqkv = p; break;
+      case P_B_O: B->bo = p; break;
+      case P_B_QC: B->bqc = p; break;
+      case P_B_OC: B->boc = p; break;
+      case P_B_UP: B->bup = p; break;
+      case P_B_DN: B->bdn = p; break;
+      case P_W_QKV: B->Wqkv = base; pack(off, rows, cols, B->Wqkv); break;
+      case P_W_O: B->Wo = base + 3 * d * d * es; pack(off, rows, cols, B->Wo); break;
+      case P_W_QC: B->Wqc = base + 4 * d * d * es; pack(off, rows, cols, B->Wqc); break;
+      case P_W_OC: B->Woc = base + 5 * d * d * es; pack(off, rows, cols, B->Woc); break;
+      case P_W_UP: B->Wup = base + 6 * d * d * es; pack(off, rows, cols, B->Wup); break;
+      case P_W_DN: B->Wdn = base + 10 * d * d * es; pack(off, rows, cols, B->Wdn); break;
+      case P_W_KC: pack(off, rows, cols, wkv + (size_t)l * 2 * d * d * es); break;
+      case P_W_VC: pack(off, rows, cols, wkv + ((size_t)l * 2 * d + d) * d * es); break;
+      case P_B_KC:
+        if (hipMemcpy(m->bkv + l * 2 * d, p, d * 4, hipMemcpyDeviceToDevice) != hipSuccess)
+          status = fail(FMD_E_DEVICE, "bias copy failed");
+        break;
+      case P_B_VC:
+        if (hipMemcpy(m->bkv + l * 2 * d + d, p, d * 4, hipMemcpyDeviceToDevice) != hipSuccess)
+          status = fail(FMD_E_DEVICE, "bias copy failed");
+        break;
+      case P_G_F: m->g_f = p; break;
+      case P_S_F: m->s_f = p; break;
+      case P_W_OUT: m->W_out = p; break;
+      case P_B_OUT: m->b_out = p; break;
+      default: break;
+    }
+  });
+  if (status != FMD_OK) return bail(status);
+  if (hipDeviceSynchronize() != hipSuccess) return bail(fail(FMD_E_DEVICE, "model setup failed"));
+  *out = m;
+  return FMD_OK;
+}
+
+int fmd_linear_field_create(double alpha, double beta, fmd_model** out) {
+  if (!out) return fail(FMD_E_INVALID, "null out");
+  if (!std::isfinite(alpha) || !std::isfinite(beta)) return fail(FMD_E_INVALID, "non-finite coefficients");
+  fmd_model* m = new fmd_model();
+  m->kind = 1;
+  m->alpha = alpha;
+  m->beta = beta;
+  m->cfg.n_max = 1 << 30;
+  m->cfg.f_reco = m->cfg.f_truth = 9;
+  if (hipGetDevice(&m->device) != hipSuccess) {   // bound on first use if no device yet
+    (void)hipGetLastError();
+    m->device = 0;
+  }
+  *out = m;
+  return FMD_OK;
+}
+
+int fmd_model_destroy(fmd_model* m) {
+  if (!m) return FMD_OK;
+  if (m->kind == 1 && m->ws.cap_tok == 0 && m->ev_pool.empty() && m->trec.empty()) {
+    delete m;   // never touched a device
+    return FMD_OK;
+  }
+  DeviceGuard guard(m->device);
+  (void)hipDeviceSynchronize();
+  flush_timing(m);
+  for (hipEvent_t e : m->ev_pool) (void)hipEventDestroy(e);
+  free_ws(m->ws);
+  if (m->params) (void)hipFree(m->params);
+  if (m->packed) (void)hipFree(m->packed);
+  if (m->Wkv) (void)hipFree(m->Wkv);
+  if (m->bkv) (void)hipFree(m->bkv);
+  delete m;
+  return FMD_OK;
+}
+
+int fmd_simulate(fmd_model* m, const fmd_events_in* truth, uint64_t seed,
+                 const fmd_schedule* schedule, fmd_events_out* reco, void* hip_stream) {
+  return simulate_impl(m, truth, nullptr, seed, schedule, reco, hip_stream);
+}
+
+int fmd_simulate_from_state(fmd_model* m, const fmd_events_in* truth, const float* x0,
+                            const fmd_schedule* schedule, fmd_events_out* reco,
+                            void* hip_stream) {
+  if (truth && truth->offsets && truth->n_events >= 0 && truth->offsets[truth->n_events] > 0 && !x0)
+    return fail(FMD_E_INVALID, "null x0");
+  return simulate_impl(m, truth, x0, 0, schedule, reco, hip_stream);
+}
+
+int fmd_velocity(fmd_model* m, const fmd_events_in* truth, const float* x,
+                 const float* t_per_event, float* v, void* hip_stream) {
+  if (!m) return fail(FMD_E_INVALID, "null model");
+  if (m->kind != 0) return fail(FMD_E_UNSUPPORTED, "fmd_velocity needs a network model");
+  Call c{};
+  c.st = (hipStream_t)hip_stream;
+  FMD_TRY(check_events(m, truth, &c.T, nullptr));
+  c.E = truth->n_events;
+  if (c.T == 0) return FMD_OK;
+  if (!x || !v || !t_per_event) return fail(FMD_E_INVALID, "null x, v or t_per_event");
+  DeviceGuard guard(m->device);
+  c.Tp = round_up(c.T, kGemmBM);
+  FMD_TRY(stage_events(m, truth, c));
+  Workspace& w = m->ws;
+  const float* xs = x;
+  const float* tev = t_per_event;
+  if (!truth->on_device) {
+    HIP_TRY(hipMemcpyAsync(w.io, x, (size_t)c.T * 9 * 4, hipMemcpyHostToDevice, c.st));
+    HIP_TRY(hipMemcpyAsync(w.tev, t_per_event, (size_t)c.E * 4, hipMemcpyHostToDevice, c.st));
+    xs = w.io;
+    tev = w.tev;
+  }
+  FMD_TRY(timed(m, c.st, FMD_K_OTHER, 0, [&] { return launch_load_state(c.st, xs, 9, c.T, w.x, w.xs, kStateLd); }));
+  float* out = truth->on_device ? v : w.io;
+  if (m->cfg.precision == FMD_BF16) {
+    FMD_TRY(truth_cache<bf16>(m, c));
+    FMD_TRY(net_forward<bf16>(m, c, tev, 0.f));
+  } else {
+    FMD_TRY(truth_cache<float>(m, c));
+    FMD_TRY(net_forward<float>(m, c, tev, 0.f));
+  }
+  FMD_TRY(head(m, c, UPD_VELOCITY, 0.f, 0.f, out, 9));
+  if (!truth->on_device) {
+    HIP_TRY(hipMemcpyAsync(v, w.io, (size_t)c.T * 9 * 4, hipMemcpyDeviceToHost, c.st));
+    HIP_TRY(hipStreamSynchronize(c.st));
+  }
+  return FMD_OK;
+}
+
+int fmd_noise(uint64_t seed, const int64_t* offsets, int64_t n_events, int32_t n_feat,
+              float* x0_device, void* hip_stream) {
+  if (!offsets || n_events < 0) return fail(FMD_E_INVALID, "bad offsets");
+  if (n_feat < 1 || n_feat > 12) return fail(FMD_E_INVALID, "n_feat must be in [1, 12]");
+  fmd_events_in ev{n_events, offsets, x0_device, 1};
+  int64_t T = 0;
+  FMD_TRY(check_events(nullptr, &ev, &T, nullptr));
+  if (T == 0) return FMD_OK;
+  hipStream_t st = (hipStream_t)hip_stream;
+  int64_t* off = nullptr;
+  int32_t* tok = nullptr;
+  if (hipMalloc((void**)&off, (size_t)(n_events + 1) * 8) != hipSuccess ||
+      hipMalloc((void**)&tok, (size_t)T * 4) != hipSuccess) {
+    if (off) (void)hipFree(off);
+    return fail(FMD_E_NOMEM, "allocation failed");
+  }
+  int status = FMD_OK;
+  if (hipMemcpyAsync(off, offsets, (size_t)(n_events + 1) * 8, hipMemcpyHostToDevice, st) != hipSuccess ||
+      launch_token_map(st, off, n_events, T, tok) != hipSuccess ||
+      launch_noise(st, seed, off, tok, T, n_feat, x0_device, nullptr, n_feat) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    status = fail(FMD_E_DEVICE, "noise kernel failed");
+  (void)hipFree(off);
+  (void)hipFree(tok);
+  return status;
+}
+
+int fmd_debug_philox(uint64_t key0, uint64_t key1, const uint64_t* counters, int64_t n,
+                     uint64_t* out, void* hip_stream) {
+  if (n < 0 || (n > 0 && (!counters || !out))) return fail(FMD_E_INVALID, "bad arguments");
+  const hipError_t e = launch_philox((hipStream_t)hip_stream, key0, key1, counters, n, out);
+  if (e != hipSuccess) return fail(FMD_E_DEVICE, "philox kernel failed: %s", hipGetErrorString(e));
+  return FMD_OK;
+}
+
+int fmd_pack_padded(const float* padded, const int32_t* lengths, int64_t n_events,
+                    int32_t n_max, int32_t f, int64_t* offsets_out, float* feat_out,
+                    void* hip_stream) {
+  if (n_events < 0 || n_max < 1 || f < 1) return fail(FMD_E_INVALID, "bad sizes");
+  if (!offsets_out || (n_events > 0 && (!padded || !lengths || !feat_out)))
+    return fail(FMD_E_INVALID, "null pointer");
+  const hipError_t e = launch_pack_padded((hipStream_t)hip_stream, padded, lengths, n_events,
+                                          n_max, f, offsets_out, feat_out);
+  if (e != hipSuccess) return fail(FMD_E_DEVICE, "pack kernel failed: %s", hipGetErrorString(e));
+  return FMD_OK;
+}
+
+int fmd_timing_enable(fmd_model* m, int32_t enable) {
+  if (!m) return fail(FMD_E_INVALID, "null model");
+  DeviceGuard guard(m->device);
+  flush_timing(m);
+  m->timing = enable != 0;
+  for (int k = 0; k < FMD_K_COUNT; ++k) m->t_ms[k] = 0, m->t_n[k] = 0, m->t_work[k] = 0;
+  return FMD_OK;
+}
+
+int fmd_timing_read(fmd_model* m, int32_t cls, double* total_ms, int64_t* launches, double* work) {
+  if (!m) return fail(FMD_E_INVALID, "null model");
+  if (cls < 0 || cls >= FMD_K_COUNT) return fail(FMD_E_INVALID, "unknown kernel class");
+  DeviceGuard guard(m->device);
+  flush_timing(m);
+  if (total_ms) *total_ms = m->t_ms[cls];
+  if (launches) *launches = m->t_n[cls];
+  if (work) *work = m->t_work[cls];
+  return FMD_OK;
+}
+
+const char* fmd_kernel_name(fmd_model* m, int32_t cls) {
+  (void)m;
+  static const char* names[FMD_K_COUNT] = {"k_gemm_qkv", "k_gemm_proj", "k_gemm_up", "k_gemm_down",
+                                           "k_attn_self", "k_attn_cross", "other"};
+  return cls >= 0 && cls < FMD_K_COUNT ? names[cls] : "";
+}
+
+// ---- test hooks ---------------------------------------------------------------------
+
+int fmd_debug_gemm(int32_t precision, int64_t M, int32_t N, int32_t K, const float* A,
+                   const float* W, const float* bias, int32_t ln, const float* g,
+                   const float* s, int32_t epi, float* C, void* hip_stream) {
+  if (precision != FMD_FP32 && precision != FMD_BF16) return fail(FMD_E_INVALID, "bad precision");
+  if (M < 0 || N <= 0 || K <= 0 || K % 32 || N % 64) return fail(FMD_E_INVALID, "bad GEMM shape");
+  if (epi < 0 || epi > 2) return fail(FMD_E_INVALID, "bad epilogue");
+  if (M == 0) return FMD_OK;
+  if (!A || !W || !C || (ln && (!g || !s))) return fail(FMD_E_INVALID, "null operand");
+  hipStream_t st = (hipStream_t)hip_stream;
+  const int64_t Mp = round_up(M, kGemmBM);
+  const size_t es = precision == FMD_BF16 ? 2 : 4;
+  const size_t a_es = ln ? 4 : es;
+  const size_t c_es = epi == EPI_RESID ? 4 : es;
+  void *Ap = nullptr, *Wt = nullptr, *Cp = nullptr;
+  int status = FMD_OK;
+  if (grow(Ap, (size_t)Mp * K * a_es) || grow(Wt, (size_t)N * K * es) || grow(Cp, (size_t)Mp * N * c_es)) {
+    status = FMD_E_NOMEM;
+  } else {
+    hipError_t e = hipSuccess;
+    if (ln) e = hipMemcpyAsync(Ap, A, (size_t)M * K * 4, hipMemcpyDeviceToDevice, st);
+    else if (precision == FMD_BF16) e = launch_convert<bf16>(st, A, M * K, (bf16*)Ap);
+    else e = hipMemcpyAsync(Ap, A, (size_t)M * K * 4, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess)
+      e = precision == FMD_BF16 ? launch_pack_weight<bf16>(st, W, K, N, (bf16*)Wt)
+                                : launch_pack_weight<float>(st, W, K, N, (float*)Wt);
+    if (e == hipSuccess && epi == EPI_RESID)
+      e = hipMemcpyAsync(Cp, C, (size_t)M * N * 4, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess)
+      e = precision == FMD_BF16
+              ? launch_gemm<bf16>(st, FMD_K_OTHER, ln != 0, epi, Mp, N, K, Ap, K, (const bf16*)Wt, bias, g, s, Cp, N)
+              : launch_gemm<float>(st, FMD_K_OTHER, ln != 0, epi, Mp, N, K, Ap, K, (const float*)Wt, bias, g, s, Cp, N);
+    if (e == hipSuccess) {
+      if (epi == EPI_RESID || precision == FMD_FP32)
+        e = hipMemcpyAsync(C, Cp, (size_t)M * N * 4, hipMemcpyDeviceToDevice, st);
+      else
+        e = launch_to_f32<bf16>(st, (const bf16*)Cp, M * N, C);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) status = fail(FMD_E_DEVICE, "debug gemm: %s", hipGetErrorString(e));
+  }
+  if (Ap) (void)hipFree(Ap);
+  if (Wt) (void)hipFree(Wt);
+  if (Cp) (void)hipFree(Cp);
+  return status;
+}
+
+int fmd_debug_attention(int32_t precision, int64_t n_events, const int64_t* q_offsets,
+                        const int64_t* kv_offsets, int32_t n_heads, int32_t dh,
+                        const float* Q, const float* K, const float* V, float* O,
+                        void* hip_stream) {
+  if (precision != FMD_FP32 && precision != FMD_BF16) return fail(FMD_E_INVALID, "bad precision");
+  if (dh != 16 && dh != 32 && dh != 64) return fail(FMD_E_UNSUPPORTED, "dh must be 16, 32 or 64");
+  if (n_heads < 1 || n_events < 0 || !q_offsets || !kv_offsets) return fail(FMD_E_INVALID, "bad arguments");
+  if (q_offsets[0] != 0 || kv_offsets[0] != 0) return fail(FMD_E_INVALID, "offsets must start at 0");
+  std::vector<int2> work;
+  for (int64_t e = 0; e < n_events; ++e) {
+    const int64_t nq = q_offsets[e + 1] - q_offsets[e], nk = kv_offsets[e + 1] - kv_offsets[e];
+    if (nq < 0 || nk < 0) return fail(FMD_E_INVALID, "offsets decrease");
+    if (nq > 0 && nk == 0) return fail(FMD_E_INVALID, "event %lld has queries but no keys", (long long)e);
+    for (int64_t q = 0; q < (nq + 63) / 64; ++q) work.push_back(make_int2((int)e, (int)q));
+  }
+  const int64_t Tq = q_offsets[n_events], Tk = kv_offsets[n_events];
+  if (work.empty()) return FMD_OK;
+  if (!Q || !K || !V || !O) return fail(FMD_E_INVALID, "null operand");
+  hipStream_t st = (hipStream_t)hip_stream;
+  const int ld = n_heads * dh;
+  const size_t es = precision == FMD_BF16 ? 2 : 4;
+  int64_t *qo = nullptr, *ko = nullptr;
+  int2* wk = nullptr;
+  void *Qp = nullptr, *Kp = nullptr, *Vp = nullptr, *Op = nullptr;
+  int status = FMD_OK;
+  if (grow(qo, (n_events + 1) * 8) || grow(ko, (n_events + 1) * 8) || grow(wk, work.size() * sizeof(int2)) ||
+      grow(Qp, (size_t)Tq * ld * es) || grow(Kp, (size_t)Tk * ld * es) || grow(Vp, (size_t)Tk * ld * es) ||
+      grow(Op, (size_t)Tq * ld * es)) {
+    status = FMD_E_NOMEM;
+  } else {
+    hipError_t e = hipMemcpy(qo, q_offsets, (n_events + 1) * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(ko, kv_offsets, (n_events + 1) * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(wk, work.data(), work.size() * sizeof(int2), hipMemcpyHostToDevice);
+    if (precision == FMD_BF16) {
+      if (e == hipSuccess) e = launch_convert<bf16>(st, Q, Tq * ld, (bf16*)Qp);
+      if (e == hipSuccess) e = launch_convert<bf16>(st, K, Tk * ld, (bf16*)Kp);
+      if (e == hipSuccess) e = launch_convert<bf16>(st, V, Tk * ld, (bf16*)Vp);
+      if (e == hipSuccess)
+        e = launch_attention<bf16>(st, false, dh, n_heads, (int64_t)work.size(), wk, (const bf16*)Qp, ld,
+                                   (const bf16*)Kp, (const bf16*)Vp, ld, (bf16*)Op, ld, qo, ko);
+      if (e == hipSuccess) e = launch_to_f32<bf16>(st, (const bf16*)Op, Tq * ld, O);
+    } else {
+      if (e == hipSuccess)
+        e = launch_attention<float>(st, false, dh, n_heads, (int64_t)work.size(), wk, Q, ld, K, V, ld, O, ld, qo, ko);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) status = fail(FMD_E_DEVICE, "debug attention: %s", hipGetErrorString(e));
+  }
+  void* bufs[] = {qo, ko, wk, Qp, Kp, Vp, Op};
+  for (void* p : bufs)
+    if (p) (void)hipFree(p);
+  return status;
+}
+
+}  // extern "C"

@@ -1,0 +1,72 @@
+// Host-side engine state behind the fmd C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/fmd.h"
+#include "common.h"
+
+namespace fmd {
+
+// Per-block device pointers. Matrices are packed transposed ([N][K]) in the compute type.
+struct DevBlock {
+  const float *g1, *s1, *g2, *s2, *g3, *s3;
+  const float *bqkv, *bo, *bqc, *boc, *bup, *bdn;
+  void *Wqkv, *Wo, *Wqc, *Woc, *Wup, *Wdn;
+};
+
+// Device buffers of one call, grown on demand and reused across calls.
+struct Workspace {
+  int64_t cap_tok = 0, cap_ev = 0, cap_items = 0;
+  size_t elem = 0;                 // bytes per compute-type element
+  float *x = nullptr, *acc = nullptr, *xs = nullptr;    // [Tp, 16] FP32 ODE state
+  float* H = nullptr;              // [Tp, d] FP32 residual stream
+  void* qkv = nullptr;             // [Tp, 3d] T
+  void* att = nullptr;             // [Tp, d] T   attention output
+  void* qc = nullptr;              // [Tp, d] T   cross-attention queries
+  void* hid = nullptr;             // [Tp, 4d] T  MLP hidden
+  void* c = nullptr;               // [Tp, d] T   truth encoding
+  void* kv = nullptr;              // [Tp, L*2d] T cross K/V cache
+  float* u = nullptr;              // [Tp, 9] truth features (host inputs are staged here)
+  float* io = nullptr;             // [Tp, 9] staging of host state / outputs
+  float* temb = nullptr;           // [max(E,1), d] time embedding
+  float* tev = nullptr;            // [E] per-event time
+  int32_t* tok_event = nullptr;    // [Tp]
+  int64_t* off = nullptr;          // [E + 1]
+  int2* work = nullptr;            // attention work list
+  int64_t* h_off = nullptr;        // pinned staging
+  int2* h_work = nullptr;
+  int64_t h_cap_ev = 0, h_cap_items = 0;
+};
+
+struct TimingRec {
+  int cls;
+  double work;
+  hipEvent_t a, b;
+};
+
+}  // namespace fmd
+
+struct fmd_model {
+  int kind = 0;                    // 0 network, 1 linear test field
+  double alpha = 0, beta = 0;
+  fmd_model_config cfg{};
+  int device = 0;
+  float* params = nullptr;         // flat FP32 copy on device
+  void* packed = nullptr;          // packed matrices in the compute type
+  float* bkv = nullptr;            // [L * 2d] cross K/V biases
+  void* Wkv = nullptr;             // [L * 2d][d] cross K/V weights (packed)
+  std::vector<fmd::DevBlock> blk;
+  const float *W_tin, *b_tin, *g_t, *s_t, *W_xin, *b_xin, *W_time, *b_time, *g_f, *s_f, *W_out,
+      *b_out;
+  fmd::Workspace ws;
+  bool timing = false;
+  std::vector<fmd::TimingRec> trec;
+  std::vector<hipEvent_t> ev_pool;
+  double t_ms[FMD_K_COUNT] = {0};
+  int64_t t_n[FMD_K_COUNT] = {0};
+  double t_work[FMD_K_COUNT] = {0};
+};

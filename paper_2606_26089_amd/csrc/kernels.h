@@ -1,0 +1,98 @@
+// Host-side launchers of the fmdet HIP kernels. All pointers are device pointers unless
+// stated; every launcher enqueues on `st` and returns the launch status.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/fmd.h"
+
+namespace fmd {
+
+enum Epi { EPI_STORE = 0, EPI_GELU = 1, EPI_RESID = 2 };
+
+// ODE update modes of the fused head kernel.
+enum UpdMode {
+  UPD_EULER = 0,      // x <- x + h v ; xs <- x
+  UPD_RK4_0 = 1,      // acc <- v ;        xs <- x + h/2 v
+  UPD_RK4_1 = 2,      // acc <- acc + 2v ; xs <- x + h/2 v
+  UPD_RK4_2 = 3,      // acc <- acc + 2v ; xs <- x + h v
+  UPD_RK4_3 = 4,      // x <- x + h/6 (acc + v) ; xs <- x
+  UPD_VELOCITY = 5    // v only, written to `out`
+};
+
+constexpr int kStateLd = 16;       // row stride (floats) of the device ODE state arrays
+constexpr int kGemmBM = 128;       // GEMM row tile; token buffers are padded to this
+
+// C = epi(pro(A) W + b). A: float [Mp, lda] if ln, else T [Mp, lda]. Wt: T [N, K]
+// (the transpose of the [K, N] weight). C: T [Mp, ldc] for STORE/GELU, float for RESID.
+// Requires Mp % 128 == 0, K % 32 == 0, N % 64 == 0.
+// `cls` (an FMD_K_* class) selects the kernel name the launch appears under in profiles.
+template <typename T>
+hipError_t launch_gemm(hipStream_t st, int cls, bool ln, int epi, int64_t Mp, int N, int K,
+                       const void* A, int lda, const T* Wt, const float* bias,
+                       const float* g, const float* s, void* C, int ldc);
+
+// Masked multi-head attention over CSR events. work: int2 (event, 64-query tile) items.
+template <typename T>
+hipError_t launch_attention(hipStream_t st, bool cross, int dh, int n_heads, int64_t n_items,
+                            const int2* work, const T* Q, int ldq, const T* K, const T* V,
+                            int ldkv, T* O, int ldo, const int64_t* q_off,
+                            const int64_t* kv_off);
+
+hipError_t launch_token_map(hipStream_t st, const int64_t* off, int64_t E, int64_t T,
+                            int32_t* tok_event);
+
+// x0 noise into x [T, ldx] (features >= n_feat and < ldx zeroed); also into xs if non-null.
+hipError_t launch_noise(hipStream_t st, uint64_t seed, const int64_t* off,
+                        const int32_t* tok_event, int64_t T, int n_feat, float* x, float* xs,
+                        int ldx);
+
+// Copies a [T, f] state into the padded [T, ldx] arrays x and xs (xs may be null).
+hipError_t launch_load_state(hipStream_t st, const float* src, int f, int64_t T, float* x,
+                             float* xs, int ldx);
+
+template <typename T>
+hipError_t launch_truth_encode(hipStream_t st, const float* u, int ldu, int f, int64_t T_,
+                               const float* W, const float* b, const float* g,
+                               const float* s, int d, T* c, int ldc);
+
+// temb[e, :] = b_xin + b_time + phi(t_e) W_time for e < n (t_e = t_ev[e] or t_uniform).
+hipError_t launch_time_embed(hipStream_t st, const float* t_ev, float t_uniform, int n,
+                             const float* W_time, const float* b_time, const float* b_xin,
+                             int E_dim, int d, float* temb);
+
+// H[r, :] = temb[tok_event[r] or 0, :] + xs[r, :f] W_xin.
+hipError_t launch_embed(hipStream_t st, const float* xs, int ldx, int f, int64_t T,
+                        const int32_t* tok_event, const float* temb, const float* W_xin,
+                        int d, float* H, int ldh);
+
+// v = LN_f(H) W_out + b_out, then the ODE update `mode` with step h. When `out` is
+// non-null the updated x (or v for UPD_VELOCITY) is also written to out [T, ldo].
+hipError_t launch_head_update(hipStream_t st, const float* H, int ldh, int d, int64_t T,
+                              const float* g, const float* s, const float* W_out,
+                              const float* b_out, int f, int mode, float h, float* x,
+                              float* acc, float* xs, int ldx, float* out, int ldo);
+
+// v = (alpha + beta t) xs, then the same ODE update.
+hipError_t launch_linear_update(hipStream_t st, float alpha, float beta, float t, int64_t T,
+                                int f, int mode, float h, float* x, float* acc, float* xs,
+                                int ldx, float* out, int ldo);
+
+// Wt[n, k] = T(W[k, n]) for a [K, N] row-major FP32 matrix.
+template <typename T>
+hipError_t launch_pack_weight(hipStream_t st, const float* W, int K, int N, T* Wt);
+
+// dst[i] = T(src[i]).
+template <typename T>
+hipError_t launch_convert(hipStream_t st, const float* src, int64_t n, T* dst);
+template <typename T>
+hipError_t launch_to_f32(hipStream_t st, const T* src, int64_t n, float* dst);
+
+hipError_t launch_philox(hipStream_t st, uint64_t k0, uint64_t k1, const uint64_t* ctr,
+                         int64_t n, uint64_t* out);
+
+hipError_t launch_pack_padded(hipStream_t st, const float* padded, const int32_t* lengths,
+                              int64_t E, int n_max, int f, int64_t* off_out, float* feat_out);
+
+}  // namespace fmd

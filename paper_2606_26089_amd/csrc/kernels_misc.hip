@@ -1,0 +1,491 @@
+// Bandwidth-bound kernels of the sampling path: CSR token map, Philox noise, truth
+// encoder, time and input embeddings, the fused output head + ODE update, ragged
+// packing and parameter packing.
+#include "common.h"
+#include "kernels.h"
+
+namespace fmd {
+
+// ---------------------------------------------------------------------------------------
+// Token -> event map of a CSR batch: the largest e with off[e] <= r (empty events skipped).
+__global__ void k_token_map(const int64_t* __restrict__ off, int64_t E, int64_t T,
+                            int32_t* __restrict__ tok_event) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= T) return;
+  int64_t lo = 0, hi = E;  // off[lo] <= r < off[hi]
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (off[mid] <= r) lo = mid; else hi = mid;
+  }
+  tok_event[r] = (int32_t)lo;
+}
+
+hipError_t launch_token_map(hipStream_t st, const int64_t* off, int64_t E, int64_t T,
+                            int32_t* tok_event) {
+  if (T <= 0) return hipSuccess;
+  const int64_t blocks = (T + 255) / 256;
+  hipLaunchKernelGGL(k_token_map, dim3((unsigned)blocks), dim3(256), 0, st, off, E, T, tok_event);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): two 64x64->128 multiplies per round,
+// Weyl-sequence key schedule, ten rounds.
+struct Philox4x64 {
+  uint64_t c[4];
+};
+
+__device__ __forceinline__ Philox4x64 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2,
+                                                   uint64_t c3, uint64_t k0, uint64_t k1) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) { k0 += W0; k1 += W1; }
+    const uint64_t hi0 = __umul64hi(M0, c0), lo0 = M0 * c0;
+    const uint64_t hi1 = __umul64hi(M1, c2), lo1 = M1 * c2;
+    const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+  }
+  Philox4x64 o;
+  o.c[0] = c0; o.c[1] = c1; o.c[2] = c2; o.c[3] = c3;
+  return o;
+}
+
+// u = ((w >> 41) + 1/2) 2^-23: exact in FP32, strictly inside (0, 1).
+__device__ __forceinline__ float u23(uint64_t w) {
+  return ((float)(uint32_t)(w >> 41) + 0.5f) * 1.1920928955078125e-07f;
+}
+
+__global__ void k_noise(uint64_t seed, const int64_t* __restrict__ off,
+                        const int32_t* __restrict__ tok_event, int64_t T, int n_feat,
+                        float* __restrict__ x, float* __restrict__ xs, int ldx) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= T) return;
+  const int32_t e = tok_event[r];
+  const uint64_t slot = (uint64_t)(r - off[e]);
+  float z[12];
+  const int nb = (n_feat + 3) >> 2;
+  for (int b = 0; b < 3; ++b) {
+    if (b >= nb) break;
+    const Philox4x64 w = philox4x64_10((uint64_t)b, slot, (uint64_t)e, 0ull, seed, 0ull);
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      const float ua = u23(w.c[2 * p]), ub = u23(w.c[2 * p + 1]);
+      const float rad = sqrtf(-2.0f * logf(ua));
+      float sn, cs;
+      sincospif(2.0f * ub, &sn, &cs);
+      z[4 * b + 2 * p] = rad * cs;
+      z[4 * b + 2 * p + 1] = rad * sn;
+    }
+  }
+  float* xr = x + r * ldx;
+  for (int f = 0; f < ldx; ++f) xr[f] = f < n_feat ? z[f] : 0.0f;
+  if (xs) {
+    float* sr = xs + r * ldx;
+    for (int f = 0; f < ldx; ++f) sr[f] = f < n_feat ? z[f] : 0.0f;
+  }
+}
+
+hipError_t launch_noise(hipStream_t st, uint64_t seed, const int64_t* off,
+                        const int32_t* tok_event, int64_t T, int n_feat, float* x, float* xs,
+                        int ldx) {
+  if (T <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_noise, dim3((unsigned)((T + 255) / 256)), dim3(256), 0, st, seed, off,
+                     tok_event, T, n_feat, x, xs, ldx);
+  return hipGetLastError();
+}
+
+__global__ void k_philox(uint64_t k0, uint64_t k1, const uint64_t* __restrict__ ctr, int64_t n,
+                         uint64_t* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint64_t* c = ctr + 4 * i;
+  const Philox4x64 w = philox4x64_10(c[0], c[1], c[2], c[3], k0, k1);
+  for (int k = 0; k < 4; ++k) out[4 * i + k] = w.c[k];
+}
+
+hipError_t launch_philox(hipStream_t st, uint64_t k0, uint64_t k1, const uint64_t* ctr,
+                         int64_t n, uint64_t* out) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_philox, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, k0, k1, ctr, n,
+                     out);
+  return hipGetLastError();
+}
+
+__global__ void k_load_state(const float* __restrict__ src, int f, int64_t T,
+                             float* __restrict__ x, float* __restrict__ xs, int ldx) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= T * ldx) return;
+  const int64_t r = i / ldx;
+  const int c = (int)(i % ldx);
+  const float v = c < f ? src[r * f + c] : 0.0f;
+  x[i] = v;
+  if (xs) xs[i] = v;
+}
+
+hipError_t launch_load_state(hipStream_t st, const float* src, int f, int64_t T, float* x,
+                             float* xs, int ldx) {
+  if (T <= 0) return hipSuccess;
+  const int64_t n = T * ldx;
+  hipLaunchKernelGGL(k_load_state, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src, f,
+                     T, x, xs, ldx);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
+// Truth encoder c = LN_t(u W_tin + b_tin): one wave per particle; lane owns columns
+// lane + 64 j. Statistics are two-pass in registers.
+constexpr int kMaxDPerLane = 16;   // d_model <= 1024
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_truth_encode(
+    const float* __restrict__ u, int ldu, int f, int64_t T_, const float* __restrict__ W,
+    const float* __restrict__ b, const float* __restrict__ g, const float* __restrict__ s,
+    int d, T* __restrict__ c, int ldc) {
+  const int lane = threadIdx.x & 63;
+  const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r >= T_) return;
+  float uf[16];
+  for (int k = 0; k < f; ++k) uf[k] = u[r * ldu + k];
+  const int nj = d >> 6;
+  float y[kMaxDPerLane];
+  float sum = 0.f;
+#pragma unroll
+  for (int jj = 0; jj < kMaxDPerLane; ++jj) {
+    if (jj < nj) {
+      const int j = lane + 64 * jj;
+      float a = b[j];
+      for (int k = 0; k < f; ++k) a = fmaf(uf[k], W[k * d + j], a);
+      y[jj] = a;
+      sum += a;
+    }
+  }
+  const float mean = wave_sum(sum) / d;
+  float q = 0.f;
+#pragma unroll
+  for (int jj = 0; jj < kMaxDPerLane; ++jj)
+    if (jj < nj) { const float dv = y[jj] - mean; q = fmaf(dv, dv, q); }
+  const float rstd = rsqrtf(wave_sum(q) / d + kLnEps);
+#pragma unroll
+  for (int jj = 0; jj < kMaxDPerLane; ++jj)
+    if (jj < nj) {
+      const int j = lane + 64 * jj;
+      c[r * ldc + j] = from_f32<T>((y[jj] - mean) * rstd * g[j] + s[j]);
+    }
+}
+
+template <typename T>
+hipError_t launch_truth_encode(hipStream_t st, const float* u, int ldu, int f, int64_t T_,
+                               const float* W, const float* b, const float* g,
+                               const float* s, int d, T* c, int ldc) {
+  if (T_ <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_truth_encode<T>, dim3((unsigned)((T_ + 3) / 4)), dim3(256), 0, st, u,
+                     ldu, f, T_, W, b, g, s, d, c, ldc);
+  return hipGetLastError();
+}
+template hipError_t launch_truth_encode<float>(hipStream_t, const float*, int, int, int64_t,
+                                               const float*, const float*, const float*,
+                                               const float*, int, float*, int);
+template hipError_t launch_truth_encode<bf16>(hipStream_t, const float*, int, int, int64_t,
+                                              const float*, const float*, const float*,
+                                              const float*, int, bf16*, int);
+
+// ---------------------------------------------------------------------------------------
+// Time embedding: temb[e, j] = b_xin[j] + b_time[j] + sum_k phi_k(t_e) W_time[k, j] with
+// phi = [sin(w_k t) | cos(w_k t)], w_k = 10000^(-k/(E/2)). One block per event.
+__global__ __launch_bounds__(256) void k_time_embed(const float* __restrict__ t_ev,
+                                                    float t_uniform, const float* __restrict__ W,
+                                                    const float* __restrict__ b_time,
+                                                    const float* __restrict__ b_xin, int E_dim,
+                                                    int d, float* __restrict__ temb) {
+  __shared__ float phi[64];
+  const int e = blockIdx.x;
+  const float t = t_ev ? t_ev[e] : t_uniform;
+  const int half = E_dim >> 1;
+  if (threadIdx.x < half) {
+    // ln(10000) / half scales the exponent
+    const float w = expf(-(float)threadIdx.x * (9.210340371976184f / (float)half));
+    float sn, cs;
+    sincosf(w * t, &sn, &cs);
+    phi[threadIdx.x] = sn;
+    phi[threadIdx.x + half] = cs;
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < d; j += blockDim.x) {
+    float a = 0.f;
+    for (int k = 0; k < E_dim; ++k) a = fmaf(phi[k], W[k * d + j], a);
+    temb[(int64_t)e * d + j] = (a + b_time[j]) + b_xin[j];
+  }
+}
+
+hipError_t launch_time_embed(hipStream_t st, const float* t_ev, float t_uniform, int n,
+                             const float* W_time, const float* b_time, const float* b_xin,
+                             int E_dim, int d, float* temb) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_time_embed, dim3(n), dim3(256), 0, st, t_ev, t_uniform, W_time, b_time,
+                     b_xin, E_dim, d, temb);
+  return hipGetLastError();
+}
+
+// Input embedding H = xs W_xin + temb: one thread per (token, 4 columns).
+__global__ __launch_bounds__(256) void k_embed(const float* __restrict__ xs, int ldx, int f,
+                                               int64_t T, const int32_t* __restrict__ tok_event,
+                                               const float* __restrict__ temb,
+                                               const float* __restrict__ W, int d,
+                                               float* __restrict__ H, int ldh) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int q = d >> 2;
+  if (i >= T * q) return;
+  const int64_t r = i / q;
+  const int j = (int)(i % q) * 4;
+  const float* te = temb + (tok_event ? (int64_t)tok_event[r] * d : 0);
+  float4 a = *(const float4*)(te + j);
+  const float* xr = xs + r * ldx;
+  for (int k = 0; k < f; ++k) {
+    const float xv = xr[k];
+    const float4 w = *(const float4*)(W + k * d + j);
+    a.x = fmaf(xv, w.x, a.x); a.y = fmaf(xv, w.y, a.y);
+    a.z = fmaf(xv, w.z, a.z); a.w = fmaf(xv, w.w, a.w);
+  }
+  *(float4*)(H + r * ldh + j) = a;
+}
+
+hipError_t launch_embed(hipStream_t st, const float* xs, int ldx, int f, int64_t T,
+                        const int32_t* tok_event, const float* temb, const float* W_xin,
+                        int d, float* H, int ldh) {
+  if (T <= 0) return hipSuccess;
+  const int64_t n = T * (d / 4);
+  hipLaunchKernelGGL(k_embed, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, xs, ldx, f, T,
+                     tok_event, temb, W_xin, d, H, ldh);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
+// ODE state update of one feature; v is the velocity evaluated at xs.
+__device__ __forceinline__ void ode_update(int mode, float h, float v, float* x, float* acc,
+                                           float* xs, float* out) {
+  switch (mode) {
+    case UPD_EULER: {
+      const float xn = fmaf(h, v, *x);
+      *x = xn; *xs = xn;
+      if (out) *out = xn;
+    } break;
+    case UPD_RK4_0:
+      *acc = v;
+      *xs = fmaf(0.5f * h, v, *x);
+      break;
+    case UPD_RK4_1:
+      *acc = fmaf(2.0f, v, *acc);
+      *xs = fmaf(0.5f * h, v, *x);
+      break;
+    case UPD_RK4_2:
+      *acc = fmaf(2.0f, v, *acc);
+      *xs = fmaf(h, v, *x);
+      break;
+    case UPD_RK4_3: {
+      const float xn = fmaf(h * (1.0f / 6.0f), *acc + v, *x);
+      *x = xn; *xs = xn;
+      if (out) *out = xn;
+    } break;
+    default:
+      if (out) *out = v;
+      break;
+  }
+}
+
+// Output head v = LN_f(H) W_out + b_out (FP32) fused with the ODE update: one wave per
+// token, lanes own columns lane + 64 j, the f output dots reduce across the wave.
+__global__ __launch_bounds__(256) void k_head_update(
+    const float* __restrict__ H, int ldh, int d, int64_t T, const float* __restrict__ g,
+    const float* __restrict__ s, const float* __restrict__ W, const float* __restrict__ bo,
+    int f, int mode, float h, float* __restrict__ x, float* __restrict__ acc,
+    float* __restrict__ xs, int ldx, float* __restrict__ out, int ldo) {
+  const int lane = threadIdx.x & 63;
+  const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r >= T) return;
+  const int nj = d >> 6;
+  const float* hr = H + r * ldh;
+  float y[kMaxDPerLane];
+  float sum = 0.f;
+#pragma unroll
+  for (int jj = 0; jj < kMaxDPerLane; ++jj)
+    if (jj < nj) { y[jj] = hr[lane + 64 * jj]; sum += y[jj]; }
+  const float mean = wave_sum(sum) / d;
+  float q = 0.f;
+#pragma unroll
+  for (int jj = 0; jj < kMaxDPerLane; ++jj)
+    if (jj < nj) { const float dv = y[jj] - mean; q = fmaf(dv, dv, q); }
+  const float rstd = rsqrtf(wave_sum(q) / d + kLnEps);
+  float part[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) part[k] = 0.f;
+#pragma unroll
+  for (int jj = 0; jj < kMaxDPerLane; ++jj)
+    if (jj < nj) {
+      const int j = lane + 64 * jj;
+      const float hn = (y[jj] - mean) * rstd * g[j] + s[j];
+      for (int k = 0; k < f; ++k) part[k] = fmaf(hn, W[j * f + k], part[k]);
+    }
+  float mine = 0.f;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) {
+    if (k < f) {
+      const float tot = wave_sum(part[k]);
+      if (lane == k) mine = tot;
+    }
+  }
+  if (lane < f) {
+    const float v = mine + bo[lane];
+    const int64_t o = r * ldx + lane;
+    ode_update(mode, h, v, x + o, acc + o, xs + o, out ? out + r * ldo + lane : nullptr);
+  }
+}
+
+hipError_t launch_head_update(hipStream_t st, const float* H, int ldh, int d, int64_t T,
+                              const float* g, const float* s, const float* W_out,
+                              const float* b_out, int f, int mode, float h, float* x,
+                              float* acc, float* xs, int ldx, float* out, int ldo) {
+  if (T <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_head_update, dim3((unsigned)((T + 3) / 4)), dim3(256), 0, st, H, ldh, d,
+                     T, g, s, W_out, b_out, f, mode, h, x, acc, xs, ldx, out, ldo);
+  return hipGetLastError();
+}
+
+__global__ void k_linear_update(float alpha, float beta, float t, int64_t T, int f, int mode,
+                                float h, float* __restrict__ x, float* __restrict__ acc,
+                                float* __restrict__ xs, int ldx, float* __restrict__ out,
+                                int ldo) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= T * f) return;
+  const int64_t r = i / f;
+  const int k = (int)(i % f);
+  const int64_t o = r * ldx + k;
+  const float v = (alpha + beta * t) * xs[o];
+  ode_update(mode, h, v, x + o, acc + o, xs + o, out ? out + r * ldo + k : nullptr);
+}
+
+hipError_t launch_linear_update(hipStream_t st, float alpha, float beta, float t, int64_t T,
+                                int f, int mode, float h, float* x, float* acc, float* xs,
+                                int ldx, float* out, int ldo) {
+  if (T <= 0) return hipSuccess;
+  const int64_t n = T * f;
+  hipLaunchKernelGGL(k_linear_update, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, alpha,
+                     beta, t, T, f, mode, h, x, acc, xs, ldx, out, ldo);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
+// Parameter packing and conversions.
+template <typename T>
+__global__ void k_pack_weight(const float* __restrict__ W, int K, int N, T* __restrict__ Wt) {
+  __shared__ float tile[32][33];
+  const int k0 = blockIdx.y * 32, n0 = blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 256 threads: 32 x 8
+  for (int i = ty; i < 32; i += 8) {
+    const int k = k0 + i, n = n0 + tx;
+    tile[i][tx] = (k < K && n < N) ? W[(int64_t)k * N + n] : 0.f;
+  }
+  __syncthreads();
+  for (int i = ty; i < 32; i += 8) {
+    const int n = n0 + i, k = k0 + tx;
+    if (n < N && k < K) Wt[(int64_t)n * K + k] = from_f32<T>(tile[tx][i]);
+  }
+}
+
+template <typename T>
+hipError_t launch_pack_weight(hipStream_t st, const float* W, int K, int N, T* Wt) {
+  dim3 grid((N + 31) / 32, (K + 31) / 32);
+  hipLaunchKernelGGL(k_pack_weight<T>, grid, dim3(256), 0, st, W, K, N, Wt);
+  return hipGetLastError();
+}
+template hipError_t launch_pack_weight<float>(hipStream_t, const float*, int, int, float*);
+template hipError_t launch_pack_weight<bf16>(hipStream_t, const float*, int, int, bf16*);
+
+template <typename T>
+__global__ void k_convert(const float* __restrict__ src, int64_t n, T* __restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = from_f32<T>(src[i]);
+}
+template <typename T>
+__global__ void k_to_f32(const T* __restrict__ src, int64_t n, float* __restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = to_f32(src[i]);
+}
+
+template <typename T>
+hipError_t launch_convert(hipStream_t st, const float* src, int64_t n, T* dst) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_convert<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src, n,
+                     dst);
+  return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_to_f32(hipStream_t st, const T* src, int64_t n, float* dst) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_to_f32<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src, n,
+                     dst);
+  return hipGetLastError();
+}
+template hipError_t launch_convert<float>(hipStream_t, const float*, int64_t, float*);
+template hipError_t launch_convert<bf16>(hipStream_t, const float*, int64_t, bf16*);
+template hipError_t launch_to_f32<float>(hipStream_t, const float*, int64_t, float*);
+template hipError_t launch_to_f32<bf16>(hipStream_t, const bf16*, int64_t, float*);
+
+// ---------------------------------------------------------------------------------------
+// Ragged packing: padded [E, n_max, f] + lengths -> CSR offsets + rows. Lengths are
+// clamped to [0, n_max], so the output never exceeds E * n_max rows.
+// One block computes the exclusive prefix sum (chunks of 1024 with a running carry).
+__device__ __forceinline__ int64_t clamp_len(int32_t v, int n_max) {
+  return v < 0 ? 0 : (v > n_max ? n_max : v);
+}
+
+__global__ __launch_bounds__(1024) void k_scan_lengths(const int32_t* __restrict__ len,
+                                                       int64_t E, int n_max,
+                                                       int64_t* __restrict__ off) {
+  __shared__ int64_t buf[1024];
+  __shared__ int64_t carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int64_t base = 0; base < E; base += 1024) {
+    const int64_t i = base + threadIdx.x;
+    buf[threadIdx.x] = i < E ? clamp_len(len[i], n_max) : 0;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {          // Hillis-Steele inclusive scan
+      const int64_t v = threadIdx.x >= o ? buf[threadIdx.x - o] : 0;
+      __syncthreads();
+      buf[threadIdx.x] += v;
+      __syncthreads();
+    }
+    if (i < E) off[i + 1] = carry + buf[threadIdx.x];
+    __syncthreads();
+    if (threadIdx.x == 1023) carry += buf[1023];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) off[0] = 0;
+}
+
+__global__ void k_scatter_rows(const float* __restrict__ padded, const int32_t* __restrict__ len,
+                               const int64_t* __restrict__ off, int64_t E, int n_max, int f,
+                               float* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // (e, slot, feature)
+  const int64_t per_event = (int64_t)n_max * f;
+  if (i >= E * per_event) return;
+  const int64_t e = i / per_event;
+  const int64_t rem = i % per_event;
+  const int slot = (int)(rem / f), k = (int)(rem % f);
+  if (slot < clamp_len(len[e], n_max)) out[(off[e] + slot) * f + k] = padded[i];
+}
+
+hipError_t launch_pack_padded(hipStream_t st, const float* padded, const int32_t* lengths,
+                              int64_t E, int n_max, int f, int64_t* off_out, float* feat_out) {
+  hipLaunchKernelGGL(k_scan_lengths, dim3(1), dim3(1024), 0, st, lengths, E, n_max, off_out);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || E == 0) return e;
+  const int64_t n = E * n_max * f;
+  hipLaunchKernelGGL(k_scatter_rows, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, padded,
+                     lengths, off_out, E, n_max, f, feat_out);
+  return hipGetLastError();
+}
+
+}  // namespace fmd
