@@ -1,0 +1,167 @@
+"""Benchmark of conditional flow-matching sampling on one MI355X.
+
+A step is one fmd_simulate call over the whole batch: the truth encoding with its cross K/V
+cache, the Philox noise, and every velocity evaluation and fused state update. The
+default workload has 4096 events with N ~ U{20..200} particles. The network is d = 256,
+6 blocks, 8 heads, integrated with RK4 over 16 steps (64 evaluations). Inputs are already
+resident in HBM when the timed region starts, and outputs stay in HBM.
+  value            BF16-path events/s (BF16 MFMA operands, FP32 accumulation/state)
+  fp32             the same workload on the plain FP32 path
+  error            worst per-feature normwise error of both paths against the FP64 oracle,
+                   on the events of the CPU sample
+  roofline         the kernel class with the largest device time, timed with HIP events
+                   on its launch stream during the timed steps
+  cpu_baseline     the FP64 oracle on a bounded sample of the same events, host cores
+Prints one JSON line on stdout.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+PEAK_TFLOPS = {"bf16": 2500.0, "fp32": 157.3}    # MI355X dense matrix peaks
+PEAK_HBM_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def time_path(fmd, torch, cfg, flat, off, feat_d, w, steps, warmup, timing):
+    m = fmd.Model(cfg, flat)
+    out = torch.empty((int(off[-1]), 9), dtype=torch.float32, device="cuda")
+    for _ in range(warmup):
+        m.simulate(off, feat_d, w.noise_seed, w.schedule, out=out)
+    torch.cuda.synchronize()
+    if timing:
+        m.timing_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        m.simulate(off, feat_d, w.noise_seed, w.schedule, out=out)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kern = {}
+    if timing:
+        for cls, name in enumerate(fmd.KERNEL_CLASSES):
+            ms, n, work = m.timing_read(cls)
+            kern[name] = {"ms": ms, "launches": n, "work": work, "kernel": m.kernel_name(cls)}
+        m.timing_enable(False)
+    m.close()
+    return dt, out.cpu().numpy(), kern
+
+
+def roofline(kern, dtype):
+    gemm_attn = {k: v for k, v in kern.items() if k != "other" and v["launches"]}
+    name, k = max(gemm_attn.items(), key=lambda kv: kv[1]["ms"])
+    avg_s = k["ms"] / k["launches"] * 1e-3
+    flops = k["work"] / k["launches"]
+    achieved = flops / avg_s / 1e12
+    peak = PEAK_TFLOPS[dtype]
+    total_ms = sum(v["ms"] for v in kern.values())
+    return {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 4), "traffic": None, "kernel": k["kernel"],
+            "class": name, "avg_launch_ms": round(k["ms"] / k["launches"], 4),
+            "flop_per_launch": flops, "share_of_device_time": round(k["ms"] / total_ms, 3)}
+
+
+def cpu_baseline(w, flat, off, feat, sample_events, processes):
+    from oracle import sample
+    ids = list(range(sample_events))
+    t0 = time.perf_counter()
+    outs = sample.simulate_events(flat, w.model, off, feat, w.schedule, seed=w.noise_seed,
+                                  event_ids=ids, processes=processes,
+                                  progress=lambda k, n: log(f"oracle: {k}/{n} events"))
+    dt = time.perf_counter() - t0
+    return dt, np.concatenate(outs)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--fp32-steps", type=int, default=1)
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=0, help="oracle events (0: 2 per core)")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for {a.gpus}): events are independent and "
+              "shard across GPUs without communication, but this build runs on one device.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2606_26089_amd import fmd
+    from workload import configs, errors, events, params
+
+    w = configs.BASE_BF16
+    off, feat = events.for_workload(w)
+    T = int(off[-1])
+    E = len(off) - 1
+    feat_d = torch.from_numpy(feat).cuda()
+    flat = params.draw(w.model, w.weight_seed)
+    log(f"workload {w.name}: {E} events, {T} particles, {w.schedule.evals} evaluations")
+
+    dt16, out16, kern16 = time_path(fmd, torch, w.model, flat, off, feat_d, w, a.steps, a.warmup, True)
+    ev16 = E * a.steps / dt16
+    log(f"bf16: {dt16 / a.steps * 1e3:.1f} ms/step, {ev16:.1f} events/s")
+    for name, k in kern16.items():
+        log(f"  {name:11s} {k['kernel']:14s} {k['ms'] / a.steps:9.1f} ms/step  {k['launches'] // a.steps:5d} "
+            f"launches/step  {k['work'] / max(k['ms'], 1e-9) / 1e9:8.1f} TFLOP/s")
+    rl = roofline(kern16, "bf16")
+    log(f"dominant kernel {rl['kernel']}: {rl['achieved']} TFLOP/s ({rl['frac']:.3f} of peak)")
+
+    fp32 = None
+    out32 = None
+    if not a.no_fp32:
+        cfg32 = w.model.with_precision(configs.FP32)
+        dt32, out32, kern32 = time_path(fmd, torch, cfg32, flat, off, feat_d, w, a.fp32_steps, 1, True)
+        ev32 = E * a.fp32_steps / dt32
+        log(f"fp32: {dt32 / a.fp32_steps * 1e3:.1f} ms/step, {ev32:.1f} events/s")
+        rl32 = roofline(kern32, "fp32")
+        fp32 = {"events_per_s": round(ev32, 2), "ms_per_step": round(dt32 / a.fp32_steps * 1e3, 2),
+                "roofline": rl32}
+
+    cpu = None
+    err = None
+    if not a.no_cpu_baseline:
+        cores = min(os.cpu_count() or 1, 16)
+        n = a.cpu_sample or 2 * cores
+        dt_cpu, ref = cpu_baseline(w, flat, off, feat, n, cores)
+        rows = int(off[n])
+        cpu = {"value": round(n / dt_cpu, 4), "unit": "events/s", "cores": cores, "kind": "oracle",
+               "sample": f"first {n} events of the workload ({rows} particles), full RK4 16 "
+                         f"integration in NumPy float64, {cores} processes, {dt_cpu:.1f} s"}
+        err = {"bf16_vs_oracle": float(errors.normwise_rel_err(out16[:rows], ref).max()),
+               "events_checked": n}
+        if out32 is not None:
+            err["fp32_vs_oracle"] = float(errors.normwise_rel_err(out32[:rows], ref).max())
+        log(f"oracle: {cpu['value']} events/s on {cores} cores; errors {err}")
+
+    line = {
+        "metric": "sampled events/s (BF16 path; FP32 plain path and errors vs the FP64 oracle "
+                  "alongside; p50/p99 event latency from the serving loop)",
+        "value": round(ev16, 2), "unit": "events/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": round(dt16 / a.steps * 1e3, 2),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+        "data": "synthetic (seeded truth events and stand-in weights)",
+        "config": {"workload": "4096 events, N~U{20..200}, d=256, 6 blocks, 8 heads, "
+                               "RK4 16 steps (64 evaluations)", "events": E, "particles": T,
+                   "precision": "bf16 operands, fp32 accumulation and state"},
+        "fp32": fp32, "error": err, "latency": None,
+        "roofline": rl, "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

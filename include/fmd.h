@@ -194,7 +194,7 @@ const char* fmd_kernel_name(fmd_model* m, int32_t kernel_class);
  * W is [K,N] row-major. With ln != 0, pro(A) = LN(A; g, s) over K features, otherwise
  * pro(A) = A. epi: 0 = store, 1 = exact GELU, 2 = accumulate (C += ...). For FMD_BF16,
  * A (after LN), W and the GELU output are rounded to BF16 as in the model.
- * Requires K % 32 == 0 and N % 64 == 0. */
+ * Requires K % 32 == 0 and N % 64 == 0; with ln also K % 64 == 0 and K <= 1024. */
 int fmd_debug_gemm(int32_t precision, int64_t M, int32_t N, int32_t K, const float* A,
                    const float* W, const float* bias, int32_t ln, const float* g,
                    const float* s, int32_t epi, float* C, void* hip_stream);

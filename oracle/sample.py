@@ -34,8 +34,17 @@ def _worker(args):
     return simulate_event(P, u, x0, scheme, n_steps, t0, t1)
 
 
+def _pool_init():
+    # one BLAS thread per worker process: the pool already spans the cores
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(1)
+    except ImportError:
+        pass
+
+
 def simulate_events(flat, cfg, offsets, feat, schedule, seed=None, x0=None, event_ids=None,
-                    dtype=np.float64, processes=1):
+                    dtype=np.float64, processes=1, progress=None):
     """Run events of a CSR batch; returns the list of per-event [N_e, 9] outputs.
 
     ``event_ids`` selects events (default all); noise uses the event's index in the batch.
@@ -54,10 +63,19 @@ def simulate_events(flat, cfg, offsets, feat, schedule, seed=None, x0=None, even
             xe = noise_event(seed, e, b - a, cfg.f_reco)
         jobs.append((flat, cfg, u, xe, schedule.scheme, schedule.n_steps,
                      schedule.t0, schedule.t1, dtype))
+    out = []
     if processes > 1 and len(jobs) > 1:
-        with ProcessPoolExecutor(processes) as ex:
-            return list(ex.map(_worker, jobs, chunksize=1))
-    return [_worker(j) for j in jobs]
+        with ProcessPoolExecutor(processes, initializer=_pool_init) as ex:
+            for r in ex.map(_worker, jobs, chunksize=1):
+                out.append(r)
+                if progress:
+                    progress(len(out), len(jobs))
+        return out
+    for j in jobs:
+        out.append(_worker(j))
+        if progress:
+            progress(len(out), len(jobs))
+    return out
 
 
 def simulate(flat, cfg, offsets, feat, schedule, seed=None, x0=None, dtype=np.float64,

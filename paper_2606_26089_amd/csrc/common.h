@@ -50,4 +50,38 @@ __device__ __forceinline__ float gelu_erf(float z) {
   return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f));
 }
 
+// ODE state update of one feature, v being the velocity evaluated at xs. Modes:
+// 0 Euler x += h v; 1..4 the four RK4 stages (acc collects k1 + 2 k2 + 2 k3, xs receives
+// the next stage input); 5 velocity only (v written to out).
+__device__ __forceinline__ void ode_update(int mode, float h, float v, float* x, float* acc,
+                                           float* xs, float* out) {
+  switch (mode) {
+    case 0: {
+      const float xn = fmaf(h, v, *x);
+      *x = xn; *xs = xn;
+      if (out) *out = xn;
+    } break;
+    case 1:
+      *acc = v;
+      *xs = fmaf(0.5f * h, v, *x);
+      break;
+    case 2:
+      *acc = fmaf(2.0f, v, *acc);
+      *xs = fmaf(0.5f * h, v, *x);
+      break;
+    case 3:
+      *acc = fmaf(2.0f, v, *acc);
+      *xs = fmaf(h, v, *x);
+      break;
+    case 4: {
+      const float xn = fmaf(h * (1.0f / 6.0f), *acc + v, *x);
+      *x = xn; *xs = xn;
+      if (out) *out = xn;
+    } break;
+    default:
+      if (out) *out = v;
+      break;
+  }
+}
+
 }  // namespace fmd

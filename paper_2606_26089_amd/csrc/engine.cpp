@@ -150,7 +150,7 @@ int grow_host(P*& p, size_t bytes) {
 
 void free_ws(Workspace& w) {
   void* dev[] = {w.x, w.acc, w.xs, w.H, w.qkv, w.att, w.qc, w.hid, w.c, w.kv, w.u, w.io,
-                 w.temb, w.tev, w.tok_event, w.off, w.work};
+                 w.temb, w.tev, w.stats, w.tok_event, w.off, w.work};
   for (void* p : dev)
     if (p) (void)hipFree(p);
   if (w.h_off) (void)hipHostFree(w.h_off);
@@ -186,6 +186,7 @@ int ensure_ws_alloc(fmd_model* m, int64_t T, int64_t E, int64_t items, bool* gre
     FMD_TRY(grow(w.tok_event, (size_t)cap * 4));
     if (m->kind == 0) {
       FMD_TRY(grow(w.H, (size_t)cap * d * 4));
+      FMD_TRY(grow(w.stats, (size_t)cap * sizeof(float2)));
       FMD_TRY(grow(w.qkv, (size_t)cap * 3 * d * es));
       FMD_TRY(grow(w.att, (size_t)cap * d * es));
       FMD_TRY(grow(w.qc, (size_t)cap * d * es));
@@ -365,9 +366,16 @@ int truth_cache(fmd_model* m, Call& c) {
   }));
   FMD_TRY(timed(m, c.st, FMD_K_OTHER, 2.0 * c.T * d * 2 * d * L, [&] {
     return launch_gemm<T>(c.st, FMD_K_OTHER, false, EPI_STORE, c.Tp, 2 * d * L, d, w.c, d,
-                          (const T*)m->Wkv, m->bkv, nullptr, nullptr, w.kv, 2 * d * L);
+                          (const T*)m->Wkv, m->bkv, nullptr, nullptr, nullptr, w.kv, 2 * d * L);
   }));
   return FMD_OK;
+}
+
+// LayerNorm statistics of every (padded) row of the residual stream.
+int row_stats(fmd_model* m, Call& c) {
+  Workspace& w = m->ws;
+  const int d = m->cfg.d_model;
+  return timed(m, c.st, FMD_K_OTHER, 0, [&] { return launch_row_stats(c.st, w.H, d, d, c.Tp, w.stats); });
 }
 
 // One evaluation of the velocity network at xs; leaves the residual stream in w.H.
@@ -386,13 +394,14 @@ int net_forward(fmd_model* m, Call& c, const float* t_ev, float t) {
   }));
   FMD_TRY(timed(m, c.st, FMD_K_OTHER, 0, [&] {
     return launch_embed(c.st, w.xs, kStateLd, 9, c.T, t_ev ? w.tok_event : nullptr, w.temb,
-                        m->W_xin, d, w.H, d);
+                        m->W_xin, d, w.H, d, w.stats);
   }));
   for (int l = 0; l < L; ++l) {
     const DevBlock& B = m->blk[l];
+    if (l > 0) FMD_TRY(row_stats(m, c));
     FMD_TRY(timed(m, c.st, FMD_K_GEMM_QKV, 2.0 * Td * d * 3 * d, [&] {
       return launch_gemm<T>(c.st, FMD_K_GEMM_QKV, true, EPI_STORE, c.Tp, 3 * d, d, w.H, d,
-                            (const T*)B.Wqkv, B.bqkv, B.g1, B.s1, w.qkv, 3 * d);
+                            (const T*)B.Wqkv, B.bqkv, w.stats, B.g1, B.s1, w.qkv, 3 * d);
     }));
     FMD_TRY(timed(m, c.st, FMD_K_ATTN_SELF, 4.0 * c.sum_n2 * d, [&] {
       return launch_attention<T>(c.st, false, dh, Hh, c.items, w.work, (const T*)qkv, 3 * d,
@@ -401,11 +410,12 @@ int net_forward(fmd_model* m, Call& c, const float* t_ev, float t) {
     }));
     FMD_TRY(timed(m, c.st, FMD_K_GEMM_PROJ, 2.0 * Td * d * d, [&] {
       return launch_gemm<T>(c.st, FMD_K_GEMM_PROJ, false, EPI_RESID, c.Tp, d, d, w.att, d,
-                            (const T*)B.Wo, B.bo, nullptr, nullptr, w.H, d);
+                            (const T*)B.Wo, B.bo, nullptr, nullptr, nullptr, w.H, d);
     }));
+    FMD_TRY(row_stats(m, c));
     FMD_TRY(timed(m, c.st, FMD_K_GEMM_PROJ, 2.0 * Td * d * d, [&] {
       return launch_gemm<T>(c.st, FMD_K_GEMM_PROJ, true, EPI_STORE, c.Tp, d, d, w.H, d,
-                            (const T*)B.Wqc, B.bqc, B.g2, B.s2, w.qc, d);
+                            (const T*)B.Wqc, B.bqc, w.stats, B.g2, B.s2, w.qc, d);
     }));
     FMD_TRY(timed(m, c.st, FMD_K_ATTN_CROSS, 4.0 * c.sum_n2 * d, [&] {
       const size_t o = (size_t)l * 2 * d * es;
@@ -415,15 +425,16 @@ int net_forward(fmd_model* m, Call& c, const float* t_ev, float t) {
     }));
     FMD_TRY(timed(m, c.st, FMD_K_GEMM_PROJ, 2.0 * Td * d * d, [&] {
       return launch_gemm<T>(c.st, FMD_K_GEMM_PROJ, false, EPI_RESID, c.Tp, d, d, w.att, d,
-                            (const T*)B.Woc, B.boc, nullptr, nullptr, w.H, d);
+                            (const T*)B.Woc, B.boc, nullptr, nullptr, nullptr, w.H, d);
     }));
+    FMD_TRY(row_stats(m, c));
     FMD_TRY(timed(m, c.st, FMD_K_GEMM_UP, 2.0 * Td * d * 4 * d, [&] {
       return launch_gemm<T>(c.st, FMD_K_GEMM_UP, true, EPI_GELU, c.Tp, 4 * d, d, w.H, d,
-                            (const T*)B.Wup, B.bup, B.g3, B.s3, w.hid, 4 * d);
+                            (const T*)B.Wup, B.bup, w.stats, B.g3, B.s3, w.hid, 4 * d);
     }));
     FMD_TRY(timed(m, c.st, FMD_K_GEMM_DOWN, 2.0 * Td * 4 * d * d, [&] {
       return launch_gemm<T>(c.st, FMD_K_GEMM_DOWN, false, EPI_RESID, c.Tp, d, 4 * d, w.hid,
-                            4 * d, (const T*)B.Wdn, B.bdn, nullptr, nullptr, w.H, d);
+                            4 * d, (const T*)B.Wdn, B.bdn, nullptr, nullptr, nullptr, w.H, d);
     }));
   }
   return FMD_OK;
@@ -436,9 +447,12 @@ int head(fmd_model* m, Call& c, int mode, float h, float t, float* out, int ldo)
       return launch_linear_update(c.st, (float)m->alpha, (float)m->beta, t, c.T, 9, mode, h, w.x,
                                   w.acc, w.xs, kStateLd, out, ldo);
     });
-  return timed(m, c.st, FMD_K_OTHER, 0, [&] {
-    return launch_head_update(c.st, w.H, m->cfg.d_model, m->cfg.d_model, c.T, m->g_f, m->s_f,
-                              m->W_out, m->b_out, 9, mode, h, w.x, w.acc, w.xs, kStateLd, out, ldo);
+  FMD_TRY(row_stats(m, c));
+  const int d = m->cfg.d_model;
+  const OdeArgs ode{w.x, w.acc, w.xs, out, c.T, kStateLd, ldo, 9, mode, h};
+  return timed(m, c.st, FMD_K_OTHER, 2.0 * c.T * d * 9, [&] {
+    return launch_gemm<float>(c.st, FMD_K_OTHER, true, EPI_ODE, c.Tp, 64, d, w.H, d, m->Wout_pk,
+                              m->bout_pk, w.stats, m->g_f, m->s_f, nullptr, 0, &ode);
   });
 }
 
@@ -543,6 +557,8 @@ int fmd_model_create(const fmd_model_config* cfg, const float* params, size_t n_
   if (grow(m->packed, (L * blk_elems) * es) != FMD_OK) return bail(FMD_E_NOMEM);
   if (grow(m->Wkv, (size_t)(L * 2 * d * d) * es) != FMD_OK) return bail(FMD_E_NOMEM);
   if (grow(m->bkv, (size_t)(L * 2 * d) * 4) != FMD_OK) return bail(FMD_E_NOMEM);
+  if (grow(m->Wout_pk, (size_t)64 * d * 4) != FMD_OK) return bail(FMD_E_NOMEM);
+  if (grow(m->bout_pk, (size_t)64 * 4) != FMD_OK) return bail(FMD_E_NOMEM);
   m->blk.assign(L, DevBlock{});
   char* pk = (char*)m->packed;
   char* wkv = (char*)m->Wkv;
@@ -597,8 +613,16 @@ int fmd_model_create(const fmd_model_config* cfg, const float* params, size_t n_
         break;
       case P_G_F: m->g_f = p; break;
       case P_S_F: m->s_f = p; break;
-      case P_W_OUT: m->W_out = p; break;
-      case P_B_OUT: m->b_out = p; break;
+      case P_W_OUT:
+        m->W_out = p;
+        if (launch_pack_weight<float>(nullptr, p, (int)rows, (int)cols, m->Wout_pk) != hipSuccess)
+          status = fail(FMD_E_DEVICE, "weight packing failed");
+        break;
+      case P_B_OUT:
+        m->b_out = p;
+        if (hipMemcpy(m->bout_pk, p, rows * 4, hipMemcpyDeviceToDevice) != hipSuccess)
+          status = fail(FMD_E_DEVICE, "bias copy failed");
+        break;
       default: break;
     }
   });
@@ -640,6 +664,8 @@ int fmd_model_destroy(fmd_model* m) {
   if (m->packed) (void)hipFree(m->packed);
   if (m->Wkv) (void)hipFree(m->Wkv);
   if (m->bkv) (void)hipFree(m->bkv);
+  if (m->Wout_pk) (void)hipFree(m->Wout_pk);
+  if (m->bout_pk) (void)hipFree(m->bout_pk);
   delete m;
   return FMD_OK;
 }
@@ -786,8 +812,10 @@ int fmd_debug_gemm(int32_t precision, int64_t M, int32_t N, int32_t K, const flo
   const size_t a_es = ln ? 4 : es;
   const size_t c_es = epi == EPI_RESID ? 4 : es;
   void *Ap = nullptr, *Wt = nullptr, *Cp = nullptr;
+  float2* st2 = nullptr;
   int status = FMD_OK;
-  if (grow(Ap, (size_t)Mp * K * a_es) || grow(Wt, (size_t)N * K * es) || grow(Cp, (size_t)Mp * N * c_es)) {
+  if (grow(Ap, (size_t)Mp * K * a_es) || grow(Wt, (size_t)N * K * es) || grow(Cp, (size_t)Mp * N * c_es) ||
+      grow(st2, (size_t)Mp * sizeof(float2))) {
     status = FMD_E_NOMEM;
   } else {
     hipError_t e = hipSuccess;
@@ -799,10 +827,14 @@ int fmd_debug_gemm(int32_t precision, int64_t M, int32_t N, int32_t K, const flo
                                 : launch_pack_weight<float>(st, W, K, N, (float*)Wt);
     if (e == hipSuccess && epi == EPI_RESID)
       e = hipMemcpyAsync(Cp, C, (size_t)M * N * 4, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess && ln) {
+      if (K % 64 || K > 1024) e = hipErrorInvalidValue;
+      else e = launch_row_stats(st, (const float*)Ap, K, K, Mp, st2);
+    }
     if (e == hipSuccess)
       e = precision == FMD_BF16
-              ? launch_gemm<bf16>(st, FMD_K_OTHER, ln != 0, epi, Mp, N, K, Ap, K, (const bf16*)Wt, bias, g, s, Cp, N)
-              : launch_gemm<float>(st, FMD_K_OTHER, ln != 0, epi, Mp, N, K, Ap, K, (const float*)Wt, bias, g, s, Cp, N);
+              ? launch_gemm<bf16>(st, FMD_K_OTHER, ln != 0, epi, Mp, N, K, Ap, K, (const bf16*)Wt, bias, st2, g, s, Cp, N)
+              : launch_gemm<float>(st, FMD_K_OTHER, ln != 0, epi, Mp, N, K, Ap, K, (const float*)Wt, bias, st2, g, s, Cp, N);
     if (e == hipSuccess) {
       if (epi == EPI_RESID || precision == FMD_FP32)
         e = hipMemcpyAsync(C, Cp, (size_t)M * N * 4, hipMemcpyDeviceToDevice, st);
@@ -815,6 +847,7 @@ int fmd_debug_gemm(int32_t precision, int64_t M, int32_t N, int32_t K, const flo
   if (Ap) (void)hipFree(Ap);
   if (Wt) (void)hipFree(Wt);
   if (Cp) (void)hipFree(Cp);
+  if (st2) (void)hipFree(st2);
   return status;
 }
 

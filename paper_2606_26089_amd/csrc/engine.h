@@ -34,6 +34,7 @@ struct Workspace {
   float* io = nullptr;             // [Tp, 9] staging of host state / outputs
   float* temb = nullptr;           // [max(E,1), d] time embedding
   float* tev = nullptr;            // [E] per-event time
+  float2* stats = nullptr;         // [Tp] LayerNorm (mean, rstd) of the rows of H
   int32_t* tok_event = nullptr;    // [Tp]
   int64_t* off = nullptr;          // [E + 1]
   int2* work = nullptr;            // attention work list
@@ -58,6 +59,8 @@ struct fmd_model {
   float* params = nullptr;         // flat FP32 copy on device
   void* packed = nullptr;          // packed matrices in the compute type
   float* bkv = nullptr;            // [L * 2d] cross K/V biases
+  float* Wout_pk = nullptr;        // [64][d] output head, transposed, rows >= f_reco zero (FP32)
+  float* bout_pk = nullptr;        // [64] output bias, zero-padded
   void* Wkv = nullptr;             // [L * 2d][d] cross K/V weights (packed)
   std::vector<fmd::DevBlock> blk;
   const float *W_tin, *b_tin, *g_t, *s_t, *W_xin, *b_xin, *W_time, *b_time, *g_f, *s_f, *W_out,

@@ -1,7 +1,8 @@
 // Token-parallel GEMMs of the velocity network on gfx950 matrix cores.
 //
 // C[M, N] = epi(pro(A)[M, K] W[K, N] + b) where pro is an optional LayerNorm over the K
-// features of each row (statistics in FP32, two passes) and epi stores, applies the exact
+// features of each row (FP32 statistics computed once per row by k_row_stats, applied while
+// the A tile is staged into LDS) and epi stores, applies the exact
 // GELU, or accumulates into the FP32 residual stream. Rows are tokens of the packed CSR
 // batch: every row is independent and its K-reduction order does not depend on where
 // the row sits in a tile, so a token's result is the same whatever batch it is part of.
@@ -44,9 +45,11 @@ template <typename T, bool LN, int EPI, int BN>
 __device__ __forceinline__ void gemm_body(const void* __restrict__ A_, int lda,
                                           const T* __restrict__ Wt, int K,
                                           const float* __restrict__ bias,
+                                          const float2* __restrict__ stats,
                                           const float* __restrict__ ln_g,
                                           const float* __restrict__ ln_s,
-                                          void* __restrict__ C_, int ldc, int n_tiles) {
+                                          void* __restrict__ C_, int ldc, int n_tiles,
+                                          const OdeArgs& ode) {
   using AT = typename std::conditional<LN, float, T>::type;
   constexpr int LDK = BK + LdsPad<T>::v;
   constexpr int TN = BN / 64;                        // 32-wide tiles per wave along N
@@ -70,15 +73,10 @@ __device__ __forceinline__ void gemm_body(const void* __restrict__ A_, int lda,
   const int n0 = nt * BN;
 
   if constexpr (LN) {
-    for (int rr = wave; rr < BM; rr += 4) {
-      const float* rowp = (const float*)A + (m0 + rr) * lda;
-      float s = 0.f;
-      for (int k = lane; k < K; k += 64) s += rowp[k];
-      const float mean = wave_sum(s) / K;
-      float q = 0.f;
-      for (int k = lane; k < K; k += 64) { const float dv = rowp[k] - mean; q = fmaf(dv, dv, q); }
-      const float var = wave_sum(q) / K;
-      if (lane == 0) { sMean[rr] = mean; sRstd[rr] = rsqrtf(var + kLnEps); }
+    if (tid < BM) {
+      const float2 st = stats[m0 + tid];
+      sMean[tid] = st.x;
+      sRstd[tid] = st.y;
     }
     __syncthreads();
   }
@@ -191,23 +189,54 @@ __device__ __forceinline__ void gemm_body(const void* __restrict__ A_, int lda,
 #undef FMD_STORE_TILES
 
   // epilogue
-#pragma unroll
-  for (int nj = 0; nj < TN; ++nj) {
-    const int col = n0 + wn * (BN / 2) + nj * 32 + (lane & 31);
-    const float bv = bias ? bias[col] : 0.f;
+  if constexpr (EPI == EPI_RESID) {
+    // per 32-row tile, read the residual values first: the stores may alias later loads
+    float* C = (float*)C_;
 #pragma unroll
     for (int mi = 0; mi < 2; ++mi) {
+      float old[TN][16];
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int64_t row = m0 + wm * 64 + mi * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
-        const float v = acc[mi][nj][r] + bv;
-        if constexpr (EPI == EPI_RESID) {
-          float* C = (float*)C_;
-          C[row * ldc + col] += v;
-        } else if constexpr (EPI == EPI_GELU) {
-          ((T*)C_)[row * ldc + col] = from_f32<T>(gelu_erf(v));
-        } else {
-          ((T*)C_)[row * ldc + col] = from_f32<T>(v);
+      for (int nj = 0; nj < TN; ++nj) {
+        const int col = n0 + wn * (BN / 2) + nj * 32 + (lane & 31);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int64_t row = m0 + wm * 64 + mi * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+          old[nj][r] = C[row * ldc + col];
+        }
+      }
+#pragma unroll
+      for (int nj = 0; nj < TN; ++nj) {
+        const int col = n0 + wn * (BN / 2) + nj * 32 + (lane & 31);
+        const float bv = bias ? bias[col] : 0.f;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int64_t row = m0 + wm * 64 + mi * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+          C[row * ldc + col] = old[nj][r] + (acc[mi][nj][r] + bv);
+        }
+      }
+    }
+  } else {
+#pragma unroll
+    for (int nj = 0; nj < TN; ++nj) {
+      const int col = n0 + wn * (BN / 2) + nj * 32 + (lane & 31);
+      const float bv = bias ? bias[col] : 0.f;
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int64_t row = m0 + wm * 64 + mi * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+          const float v = acc[mi][nj][r] + bv;
+          if constexpr (EPI == EPI_ODE) {
+            if (col < ode.nf && row < ode.m_valid) {
+              const int64_t o = row * ode.ldx + col;
+              ode_update(ode.mode, ode.h, v, ode.x + o, ode.acc + o, ode.xs + o,
+                         ode.out ? ode.out + row * ode.ldo + col : nullptr);
+            }
+          } else if constexpr (EPI == EPI_GELU) {
+            ((T*)C_)[row * ldc + col] = from_f32<T>(gelu_erf(v));
+          } else {
+            ((T*)C_)[row * ldc + col] = from_f32<T>(v);
+          }
         }
       }
     }
@@ -220,41 +249,45 @@ __device__ __forceinline__ void gemm_body(const void* __restrict__ A_, int lda,
   __global__ __launch_bounds__(NT) void NAME(const void* __restrict__ A, int lda,             \
                                              const T* __restrict__ Wt, int K,                 \
                                              const float* __restrict__ bias,                  \
+                                             const float2* __restrict__ stats,                \
                                              const float* __restrict__ g,                     \
                                              const float* __restrict__ s,                     \
-                                             void* __restrict__ C, int ldc, int n_tiles) {    \
-    gemm_body<T, LN, EPI, BN>(A, lda, Wt, K, bias, g, s, C, ldc, n_tiles);                    \
+                                             void* __restrict__ C, int ldc, int n_tiles,      \
+                                             OdeArgs ode) {                                   \
+    gemm_body<T, LN, EPI, BN>(A, lda, Wt, K, bias, stats, g, s, C, ldc, n_tiles, ode);        \
   }
 FMD_GEMM_KERNEL(k_gemm_qkv)     // LN1 -> [Q|K|V]
 FMD_GEMM_KERNEL(k_gemm_proj)    // attention output projections (+ residual), LN2 -> cross Q
 FMD_GEMM_KERNEL(k_gemm_up)      // LN3 -> MLP up + GELU
 FMD_GEMM_KERNEL(k_gemm_down)    // MLP down (+ residual)
+FMD_GEMM_KERNEL(k_gemm_head)    // LN_f -> output head + fused Euler/RK4 state update
 FMD_GEMM_KERNEL(k_gemm_any)     // truth K/V cache and test hooks
 #undef FMD_GEMM_KERNEL
 
 template <typename T>
-using GemmKernel = void (*)(const void*, int, const T*, int, const float*, const float*,
-                            const float*, void*, int, int);
+using GemmKernel = void (*)(const void*, int, const T*, int, const float*, const float2*,
+                            const float*, const float*, void*, int, int, OdeArgs);
 
 template <typename T, int BN>
 static hipError_t go(GemmKernel<T> k, hipStream_t st, int64_t Mp, int N, int K, const void* A,
-                     int lda, const T* Wt, const float* bias, const float* g, const float* s,
-                     void* C, int ldc) {
+                     int lda, const T* Wt, const float* bias, const float2* stats,
+                     const float* g, const float* s, void* C, int ldc, const OdeArgs& ode) {
   const int n_tiles = N / BN;
   const int64_t grid = (Mp / BM) * n_tiles;
   if (grid <= 0) return hipSuccess;
   if (grid > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(NT), 0, st, A, lda, Wt, K, bias, g, s, C, ldc,
-                     n_tiles);
+  hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(NT), 0, st, A, lda, Wt, K, bias, stats, g, s,
+                     C, ldc, n_tiles, ode);
   return hipGetLastError();
 }
 
 template <typename T, int BN>
 static hipError_t dispatch(hipStream_t st, int cls, bool ln, int epi, int64_t Mp, int N, int K,
                            const void* A, int lda, const T* Wt, const float* bias,
-                           const float* g, const float* s, void* C, int ldc) {
+                           const float2* stats, const float* g, const float* s, void* C,
+                           int ldc, const OdeArgs& ode) {
 #define FMD_GO(KER, L, E) \
-  return go<T, BN>(KER<T, L, E, BN>, st, Mp, N, K, A, lda, Wt, bias, g, s, C, ldc)
+  return go<T, BN>(KER<T, L, E, BN>, st, Mp, N, K, A, lda, Wt, bias, stats, g, s, C, ldc, ode)
   switch (cls) {
     case FMD_K_GEMM_QKV:
       if (ln && epi == EPI_STORE) FMD_GO(k_gemm_qkv, true, EPI_STORE);
@@ -270,6 +303,10 @@ static hipError_t dispatch(hipStream_t st, int cls, bool ln, int epi, int64_t Mp
       if (!ln && epi == EPI_RESID) FMD_GO(k_gemm_down, false, EPI_RESID);
       break;
     default:
+      if (epi == EPI_ODE) {
+        if (ln) FMD_GO(k_gemm_head, true, EPI_ODE);
+        break;
+      }
       if (ln) {
         if (epi == EPI_STORE) FMD_GO(k_gemm_any, true, EPI_STORE);
         if (epi == EPI_GELU) FMD_GO(k_gemm_any, true, EPI_GELU);
@@ -286,17 +323,79 @@ static hipError_t dispatch(hipStream_t st, int cls, bool ln, int epi, int64_t Mp
 template <typename T>
 hipError_t launch_gemm(hipStream_t st, int cls, bool ln, int epi, int64_t Mp, int N, int K,
                        const void* A, int lda, const T* Wt, const float* bias,
-                       const float* g, const float* s, void* C, int ldc) {
+                       const float2* stats, const float* g, const float* s, void* C, int ldc,
+                       const OdeArgs* ode) {
   if (Mp % BM || K % BK || N % 64) return hipErrorInvalidValue;
-  if (N % 128 == 0) return dispatch<T, 128>(st, cls, ln, epi, Mp, N, K, A, lda, Wt, bias, g, s, C, ldc);
-  return dispatch<T, 64>(st, cls, ln, epi, Mp, N, K, A, lda, Wt, bias, g, s, C, ldc);
+  if (ln && !stats) return hipErrorInvalidValue;
+  if ((epi == EPI_ODE) != (ode != nullptr)) return hipErrorInvalidValue;
+  const OdeArgs none{};
+  const OdeArgs& oa = ode ? *ode : none;
+  if (N % 128 == 0)
+    return dispatch<T, 128>(st, cls, ln, epi, Mp, N, K, A, lda, Wt, bias, stats, g, s, C, ldc, oa);
+  return dispatch<T, 64>(st, cls, ln, epi, Mp, N, K, A, lda, Wt, bias, stats, g, s, C, ldc, oa);
+}
+
+// LayerNorm row statistics: one wave per row, the row held in registers for two passes.
+// VEC: each lane reads 4 consecutive floats per step (rows whose length is a multiple of 256).
+template <bool VEC>
+__global__ __launch_bounds__(256) void k_row_stats(const float* __restrict__ A, int ld, int K,
+                                                   int64_t M, float2* __restrict__ stats) {
+  constexpr int kMax = 16;   // K <= 1024
+  const int lane = threadIdx.x & 63;
+  const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r >= M) return;
+  const float* rowp = A + r * ld;
+  float v[kMax];
+  float s = 0.f;
+  if constexpr (VEC) {
+    const int n = K >> 8;
+#pragma unroll
+    for (int i = 0; i < kMax / 4; ++i)
+      if (i < n) {
+        const float4 q = *(const float4*)(rowp + lane * 4 + 256 * i);
+        v[4 * i] = q.x; v[4 * i + 1] = q.y; v[4 * i + 2] = q.z; v[4 * i + 3] = q.w;
+        s += (q.x + q.y) + (q.z + q.w);
+      }
+    const float mean = wave_sum(s) / K;
+    float q = 0.f;
+#pragma unroll
+    for (int i = 0; i < kMax; ++i)
+      if (i < 4 * n) { const float dv = v[i] - mean; q = fmaf(dv, dv, q); }
+    const float var = wave_sum(q) / K;
+    if (lane == 0) stats[r] = make_float2(mean, rsqrtf(var + kLnEps));
+  } else {
+    const int n = K >> 6;
+#pragma unroll
+    for (int i = 0; i < kMax; ++i)
+      if (i < n) { v[i] = rowp[lane + 64 * i]; s += v[i]; }
+    const float mean = wave_sum(s) / K;
+    float q = 0.f;
+#pragma unroll
+    for (int i = 0; i < kMax; ++i)
+      if (i < n) { const float dv = v[i] - mean; q = fmaf(dv, dv, q); }
+    const float var = wave_sum(q) / K;
+    if (lane == 0) stats[r] = make_float2(mean, rsqrtf(var + kLnEps));
+  }
+}
+
+hipError_t launch_row_stats(hipStream_t st, const float* A, int ld, int K, int64_t M,
+                            float2* stats) {
+  if (M <= 0) return hipSuccess;
+  if (K % 64 || K > 1024) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)((M + 3) / 4));
+  if (K % 256 == 0 && ld % 4 == 0)
+    hipLaunchKernelGGL(k_row_stats<true>, grid, dim3(256), 0, st, A, ld, K, M, stats);
+  else
+    hipLaunchKernelGGL(k_row_stats<false>, grid, dim3(256), 0, st, A, ld, K, M, stats);
+  return hipGetLastError();
 }
 
 template hipError_t launch_gemm<float>(hipStream_t, int, bool, int, int64_t, int, int,
                                        const void*, int, const float*, const float*,
-                                       const float*, const float*, void*, int);
+                                       const float2*, const float*, const float*, void*, int,
+                                       const OdeArgs*);
 template hipError_t launch_gemm<bf16>(hipStream_t, int, bool, int, int64_t, int, int,
-                                      const void*, int, const bf16*, const float*, const float*,
-                                      const float*, void*, int);
+                                      const void*, int, const bf16*, const float*, const float2*,
+                                      const float*, const float*, void*, int, const OdeArgs*);
 
 }  // namespace fmd

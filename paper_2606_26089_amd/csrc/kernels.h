@@ -9,7 +9,7 @@
 
 namespace fmd {
 
-enum Epi { EPI_STORE = 0, EPI_GELU = 1, EPI_RESID = 2 };
+enum Epi { EPI_STORE = 0, EPI_GELU = 1, EPI_RESID = 2, EPI_ODE = 3 };
 
 // ODE update modes of the fused head kernel.
 enum UpdMode {
@@ -22,16 +22,36 @@ enum UpdMode {
 };
 
 constexpr int kStateLd = 16;       // row stride (floats) of the device ODE state arrays
+
+// Fused ODE update in a GEMM epilogue (EPI_ODE): the GEMM result v[r, c] for c < nf and
+// r < m_valid updates state element (r, c) with `mode`; see UpdMode.
+struct OdeArgs {
+  float* x;
+  float* acc;
+  float* xs;
+  float* out;       // optional [m_valid, ldo] copy of the new state (or of v)
+  int64_t m_valid;
+  int ldx, ldo, nf, mode;
+  float h;
+};
 constexpr int kGemmBM = 128;       // GEMM row tile; token buffers are padded to this
 
 // C = epi(pro(A) W + b). A: float [Mp, lda] if ln, else T [Mp, lda]. Wt: T [N, K]
 // (the transpose of the [K, N] weight). C: T [Mp, ldc] for STORE/GELU, float for RESID.
+// With ln, stats holds (mean, 1/sqrt(var + eps)) of every row of A (launch_row_stats)
+// and pro(A) = (A - mean) * rstd * g + s.
 // Requires Mp % 128 == 0, K % 32 == 0, N % 64 == 0.
 // `cls` (an FMD_K_* class) selects the kernel name the launch appears under in profiles.
 template <typename T>
 hipError_t launch_gemm(hipStream_t st, int cls, bool ln, int epi, int64_t Mp, int N, int K,
                        const void* A, int lda, const T* Wt, const float* bias,
-                       const float* g, const float* s, void* C, int ldc);
+                       const float2* stats, const float* g, const float* s, void* C, int ldc,
+                       const OdeArgs* ode = nullptr);
+
+// LayerNorm statistics of the rows of a float [M, ld] matrix over its first K columns:
+// stats[r] = (mean, 1/sqrt(biased var + eps)), two passes in registers, one wave per row.
+hipError_t launch_row_stats(hipStream_t st, const float* A, int ld, int K, int64_t M,
+                            float2* stats);
 
 // Masked multi-head attention over CSR events. work: int2 (event, 64-query tile) items.
 template <typename T>
@@ -62,17 +82,11 @@ hipError_t launch_time_embed(hipStream_t st, const float* t_ev, float t_uniform,
                              const float* W_time, const float* b_time, const float* b_xin,
                              int E_dim, int d, float* temb);
 
-// H[r, :] = temb[tok_event[r] or 0, :] + xs[r, :f] W_xin.
+// H[r, :] = temb[tok_event[r] or 0, :] + xs[r, :f] W_xin, with the LayerNorm
+// statistics of every new row written to stats[r].
 hipError_t launch_embed(hipStream_t st, const float* xs, int ldx, int f, int64_t T,
                         const int32_t* tok_event, const float* temb, const float* W_xin,
-                        int d, float* H, int ldh);
-
-// v = LN_f(H) W_out + b_out, then the ODE update `mode` with step h. When `out` is
-// non-null the updated x (or v for UPD_VELOCITY) is also written to out [T, ldo].
-hipError_t launch_head_update(hipStream_t st, const float* H, int ldh, int d, int64_t T,
-                              const float* g, const float* s, const float* W_out,
-                              const float* b_out, int f, int mode, float h, float* x,
-                              float* acc, float* xs, int ldx, float* out, int ldo);
+                        int d, float* H, int ldh, float2* stats);
 
 // v = (alpha + beta t) xs, then the same ODE update.
 hipError_t launch_linear_update(hipStream_t st, float alpha, float beta, float t, int64_t T,

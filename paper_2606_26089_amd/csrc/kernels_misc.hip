@@ -228,130 +228,52 @@ hipError_t launch_time_embed(hipStream_t st, const float* t_ev, float t_uniform,
   return hipGetLastError();
 }
 
-// Input embedding H = xs W_xin + temb: one thread per (token, 4 columns).
+// Input embedding H = xs W_xin + temb, one wave per token (lane owns columns lane + 64 j),
+// with the row's LayerNorm statistics for the first block.
 __global__ __launch_bounds__(256) void k_embed(const float* __restrict__ xs, int ldx, int f,
                                                int64_t T, const int32_t* __restrict__ tok_event,
                                                const float* __restrict__ temb,
                                                const float* __restrict__ W, int d,
-                                               float* __restrict__ H, int ldh) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int q = d >> 2;
-  if (i >= T * q) return;
-  const int64_t r = i / q;
-  const int j = (int)(i % q) * 4;
-  const float* te = temb + (tok_event ? (int64_t)tok_event[r] * d : 0);
-  float4 a = *(const float4*)(te + j);
-  const float* xr = xs + r * ldx;
-  for (int k = 0; k < f; ++k) {
-    const float xv = xr[k];
-    const float4 w = *(const float4*)(W + k * d + j);
-    a.x = fmaf(xv, w.x, a.x); a.y = fmaf(xv, w.y, a.y);
-    a.z = fmaf(xv, w.z, a.z); a.w = fmaf(xv, w.w, a.w);
-  }
-  *(float4*)(H + r * ldh + j) = a;
-}
-
-hipError_t launch_embed(hipStream_t st, const float* xs, int ldx, int f, int64_t T,
-                        const int32_t* tok_event, const float* temb, const float* W_xin,
-                        int d, float* H, int ldh) {
-  if (T <= 0) return hipSuccess;
-  const int64_t n = T * (d / 4);
-  hipLaunchKernelGGL(k_embed, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, xs, ldx, f, T,
-                     tok_event, temb, W_xin, d, H, ldh);
-  return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------------------
-// ODE state update of one feature; v is the velocity evaluated at xs.
-__device__ __forceinline__ void ode_update(int mode, float h, float v, float* x, float* acc,
-                                           float* xs, float* out) {
-  switch (mode) {
-    case UPD_EULER: {
-      const float xn = fmaf(h, v, *x);
-      *x = xn; *xs = xn;
-      if (out) *out = xn;
-    } break;
-    case UPD_RK4_0:
-      *acc = v;
-      *xs = fmaf(0.5f * h, v, *x);
-      break;
-    case UPD_RK4_1:
-      *acc = fmaf(2.0f, v, *acc);
-      *xs = fmaf(0.5f * h, v, *x);
-      break;
-    case UPD_RK4_2:
-      *acc = fmaf(2.0f, v, *acc);
-      *xs = fmaf(h, v, *x);
-      break;
-    case UPD_RK4_3: {
-      const float xn = fmaf(h * (1.0f / 6.0f), *acc + v, *x);
-      *x = xn; *xs = xn;
-      if (out) *out = xn;
-    } break;
-    default:
-      if (out) *out = v;
-      break;
-  }
-}
-
-// Output head v = LN_f(H) W_out + b_out (FP32) fused with the ODE update: one wave per
-// token, lanes own columns lane + 64 j, the f output dots reduce across the wave.
-__global__ __launch_bounds__(256) void k_head_update(
-    const float* __restrict__ H, int ldh, int d, int64_t T, const float* __restrict__ g,
-    const float* __restrict__ s, const float* __restrict__ W, const float* __restrict__ bo,
-    int f, int mode, float h, float* __restrict__ x, float* __restrict__ acc,
-    float* __restrict__ xs, int ldx, float* __restrict__ out, int ldo) {
+                                               float* __restrict__ H, int ldh,
+                                               float2* __restrict__ stats) {
   const int lane = threadIdx.x & 63;
   const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (r >= T) return;
+  const float* te = temb + (tok_event ? (int64_t)tok_event[r] * d : 0);
+  float xv[16];
+  for (int k = 0; k < f; ++k) xv[k] = xs[r * ldx + k];
   const int nj = d >> 6;
-  const float* hr = H + r * ldh;
   float y[kMaxDPerLane];
   float sum = 0.f;
 #pragma unroll
   for (int jj = 0; jj < kMaxDPerLane; ++jj)
-    if (jj < nj) { y[jj] = hr[lane + 64 * jj]; sum += y[jj]; }
+    if (jj < nj) {
+      const int j = lane + 64 * jj;
+      float a = te[j];
+      for (int k = 0; k < f; ++k) a = fmaf(xv[k], W[k * d + j], a);
+      y[jj] = a;
+      sum += a;
+      H[r * ldh + j] = a;
+    }
   const float mean = wave_sum(sum) / d;
   float q = 0.f;
 #pragma unroll
   for (int jj = 0; jj < kMaxDPerLane; ++jj)
     if (jj < nj) { const float dv = y[jj] - mean; q = fmaf(dv, dv, q); }
-  const float rstd = rsqrtf(wave_sum(q) / d + kLnEps);
-  float part[12];
-#pragma unroll
-  for (int k = 0; k < 12; ++k) part[k] = 0.f;
-#pragma unroll
-  for (int jj = 0; jj < kMaxDPerLane; ++jj)
-    if (jj < nj) {
-      const int j = lane + 64 * jj;
-      const float hn = (y[jj] - mean) * rstd * g[j] + s[j];
-      for (int k = 0; k < f; ++k) part[k] = fmaf(hn, W[j * f + k], part[k]);
-    }
-  float mine = 0.f;
-#pragma unroll
-  for (int k = 0; k < 12; ++k) {
-    if (k < f) {
-      const float tot = wave_sum(part[k]);
-      if (lane == k) mine = tot;
-    }
-  }
-  if (lane < f) {
-    const float v = mine + bo[lane];
-    const int64_t o = r * ldx + lane;
-    ode_update(mode, h, v, x + o, acc + o, xs + o, out ? out + r * ldo + lane : nullptr);
-  }
+  const float var = wave_sum(q) / d;
+  if (lane == 0) stats[r] = make_float2(mean, rsqrtf(var + kLnEps));
 }
 
-hipError_t launch_head_update(hipStream_t st, const float* H, int ldh, int d, int64_t T,
-                              const float* g, const float* s, const float* W_out,
-                              const float* b_out, int f, int mode, float h, float* x,
-                              float* acc, float* xs, int ldx, float* out, int ldo) {
+hipError_t launch_embed(hipStream_t st, const float* xs, int ldx, int f, int64_t T,
+                        const int32_t* tok_event, const float* temb, const float* W_xin,
+                        int d, float* H, int ldh, float2* stats) {
   if (T <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_head_update, dim3((unsigned)((T + 3) / 4)), dim3(256), 0, st, H, ldh, d,
-                     T, g, s, W_out, b_out, f, mode, h, x, acc, xs, ldx, out, ldo);
+  hipLaunchKernelGGL(k_embed, dim3((unsigned)((T + 3) / 4)), dim3(256), 0, st, xs, ldx, f, T,
+                     tok_event, temb, W_xin, d, H, ldh, stats);
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------------------
 __global__ void k_linear_update(float alpha, float beta, float t, int64_t T, int f, int mode,
                                 float h, float* __restrict__ x, float* __restrict__ acc,
                                 float* __restrict__ xs, int ldx, float* __restrict__ out,

@@ -5,6 +5,7 @@ integrations and 1e-5 for one velocity evaluation; BF16 path 2e-2, with the pT a
 response mean and width within 1% of the oracle's.
 """
 
+import dataclasses
 import os
 
 import numpy as np
@@ -65,6 +66,7 @@ def test_linear_field_closed_form(env, scheme, K):
                                  configs.BASE_MODEL.with_precision(configs.BF16)])
 def test_velocity_matches_oracle(env, cfg):
     torch, fmd = env
+    cfg = dataclasses.replace(cfg, n_max=1000)
     flat = params.draw(cfg, seed=4, perturbed=True)
     sizes = [1, 2, 0, 17, 64, 65, 40] if cfg.d_model == 64 else [1, 33, 0, 130, 200]
     off = np.r_[0, np.cumsum(sizes)].astype(np.int64)
