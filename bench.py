@@ -53,18 +53,22 @@ def time_path(fmd, torch, cfg, flat, off, feat_d, w, steps, warmup, timing):
             ms, n, work = m.timing_read(cls)
             kern[name] = {"ms": ms, "launches": n, "work": work, "kernel": m.kernel_name(cls)}
         m.timing_enable(False)
+    tiles = {e["site"]: f"{e['BM']}x{e['BN']}x{e['BK']}/{e['threads']}t"
+             for e in m.tuning_table()["entries"]}
+    kern["_tiles"] = tiles
     m.close()
     return dt, out.cpu().numpy(), kern
 
 
 def roofline(kern, dtype):
-    gemm_attn = {k: v for k, v in kern.items() if k != "other" and v["launches"]}
+    gemm_attn = {k: v for k, v in kern.items() if not k.startswith("_") and k != "other"
+                 and v["launches"]}
     name, k = max(gemm_attn.items(), key=lambda kv: kv[1]["ms"])
     avg_s = k["ms"] / k["launches"] * 1e-3
     flops = k["work"] / k["launches"]
     achieved = flops / avg_s / 1e12
     peak = PEAK_TFLOPS[dtype]
-    total_ms = sum(v["ms"] for v in kern.values())
+    total_ms = sum(v["ms"] for k_, v in kern.items() if not k_.startswith("_"))
     return {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
             "frac": round(achieved / peak, 4), "traffic": None, "kernel": k["kernel"],
             "class": name, "avg_launch_ms": round(k["ms"] / k["launches"], 4),
@@ -114,7 +118,10 @@ def main():
     dt16, out16, kern16 = time_path(fmd, torch, w.model, flat, off, feat_d, w, a.steps, a.warmup, True)
     ev16 = E * a.steps / dt16
     log(f"bf16: {dt16 / a.steps * 1e3:.1f} ms/step, {ev16:.1f} events/s")
+    log(f"  tiles chosen by the autotuner: {kern16['_tiles']}")
     for name, k in kern16.items():
+        if name.startswith("_"):
+            continue
         log(f"  {name:11s} {k['kernel']:14s} {k['ms'] / a.steps:9.1f} ms/step  {k['launches'] // a.steps:5d} "
             f"launches/step  {k['work'] / max(k['ms'], 1e-9) / 1e9:8.1f} TFLOP/s")
     rl = roofline(kern16, "bf16")
@@ -129,7 +136,7 @@ def main():
         log(f"fp32: {dt32 / a.fp32_steps * 1e3:.1f} ms/step, {ev32:.1f} events/s")
         rl32 = roofline(kern32, "fp32")
         fp32 = {"events_per_s": round(ev32, 2), "ms_per_step": round(dt32 / a.fp32_steps * 1e3, 2),
-                "roofline": rl32}
+                "roofline": rl32, "tiles": kern32["_tiles"]}
 
     cpu = None
     err = None
@@ -156,7 +163,8 @@ def main():
         "data": "synthetic (seeded truth events and stand-in weights)",
         "config": {"workload": "4096 events, N~U{20..200}, d=256, 6 blocks, 8 heads, "
                                "RK4 16 steps (64 evaluations)", "events": E, "particles": T,
-                   "precision": "bf16 operands, fp32 accumulation and state"},
+                   "precision": "bf16 operands, fp32 accumulation and state",
+                   "tiles": kern16["_tiles"]},
         "fp32": fp32, "error": err, "latency": None,
         "roofline": rl, "cpu_baseline": cpu,
     }

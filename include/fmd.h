@@ -188,16 +188,34 @@ int fmd_timing_read(fmd_model* m, int32_t kernel_class, double* total_ms, int64_
 /* Name of the HIP kernel behind a class, as rocprofv3 reports it (static string). */
 const char* fmd_kernel_name(fmd_model* m, int32_t kernel_class);
 
+/* ---- tile autotuner ------------------------------------------------------------------- */
+
+/* The GEMM sites of the network (QKV, attention projections with the residual, cross-query,
+ * MLP up, MLP down) each choose among candidate tilings of the matrix-core kernel.
+ * While enabled (the default), the first call whose padded token count falls in a new
+ * power-of-two bucket times every candidate on that call's real shapes and buffers and
+ * keeps the fastest. Tilings differ only in speed: every tiling produces bitwise-identical
+ * results. */
+int fmd_autotune_enable(fmd_model* m, int32_t enable);
+
+/* The chosen tilings as a JSON object (site, log2 token bucket, tile id and shape, measured
+ * microseconds). Writes at most cap bytes including the terminator; *needed receives
+ * the full size. */
+int fmd_tuning_table(fmd_model* m, char* buf, size_t cap, size_t* needed);
+
 /* ---- kernel test hooks (used by the parity tests) --------------------------------------- */
 
 /* C[M,N] = epi(pro(A) W + b) with the model's GEMM kernel, all operands DEVICE FP32.
  * W is [K,N] row-major. With ln != 0, pro(A) = LN(A; g, s) over K features, otherwise
  * pro(A) = A. epi: 0 = store, 1 = exact GELU, 2 = accumulate (C += ...). For FMD_BF16,
  * A (after LN), W and the GELU output are rounded to BF16 as in the model.
- * Requires K % 32 == 0 and N % 64 == 0; with ln also K % 64 == 0 and K <= 1024. */
+ * Requires K % 32 == 0 and N % 64 == 0; with ln also K % 64 == 0 and K <= 1024.
+ * tile selects a candidate tiling of the autotuner (-1: default); (ln, store), (ln, GELU)
+ * and (no ln, accumulate) accept every tiling that divides the shape, other combinations
+ * tilings 0 and 4. FMD_E_UNSUPPORTED if the tiling does not divide the shape. */
 int fmd_debug_gemm(int32_t precision, int64_t M, int32_t N, int32_t K, const float* A,
                    const float* W, const float* bias, int32_t ln, const float* g,
-                   const float* s, int32_t epi, float* C, void* hip_stream);
+                   const float* s, int32_t epi, float* C, int32_t tile, void* hip_stream);
 
 /* Masked multi-head attention per event with the model's kernel, all operands DEVICE FP32.
  * Q is [Tq, H*dh] and K, V are [Tk, H*dh] in CSR events (q_offsets, kv_offsets: host

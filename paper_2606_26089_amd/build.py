@@ -17,8 +17,10 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libfmdet.so")
 
-SOURCES = ["kernels_misc.hip", "gemm.hip", "attention.hip", "engine.cpp"]
-HEADERS = ["common.h", "kernels.h", "engine.h", os.path.join("..", "..", "include", "fmd.h")]
+SOURCES = ["gemm_bf16.hip", "gemm_f32.hip", "kernels_misc.hip", "gemm.hip", "attention.hip",
+           "engine.cpp"]
+HEADERS = ["common.h", "kernels.h", "engine.h", "gemm_body.h", "gemm_inst.h",
+           os.path.join("..", "..", "include", "fmd.h")]
 
 ARCH = "gfx950"
 COMMON_FLAGS = [

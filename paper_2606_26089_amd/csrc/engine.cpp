@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "engine.h"
+#include "gemm_body.h"
 #include "kernels.h"
 
 using namespace fmd;
@@ -378,6 +379,93 @@ int row_stats(fmd_model* m, Call& c) {
   return timed(m, c.st, FMD_K_OTHER, 0, [&] { return launch_row_stats(c.st, w.H, d, d, c.Tp, w.stats); });
 }
 
+int bucket_of(int64_t Tp) {
+  int b = 0;
+  while (b + 1 < kTuneBuckets && ((int64_t)1 << (b + 1)) <= Tp) ++b;
+  return b;
+}
+
+int tile_for(const fmd_model* m, int slot, int64_t Tp, int N) {
+  const int t = m->tune[slot][bucket_of(Tp)];
+  return t >= 0 ? t : default_tile(N);
+}
+
+// Launches the GEMM of one tuning slot with a given tiling on the live workspace.
+template <typename T>
+hipError_t slot_gemm(fmd_model* m, Call& c, int slot, int tile, const DevBlock& B) {
+  Workspace& w = m->ws;
+  const int d = m->cfg.d_model;
+  switch (slot) {
+    case TS_QKV:
+      return launch_gemm<T>(c.st, FMD_K_GEMM_QKV, true, EPI_STORE, c.Tp, 3 * d, d, w.H, d,
+                            (const T*)B.Wqkv, B.bqkv, w.stats, B.g1, B.s1, w.qkv, 3 * d, nullptr, tile);
+    case TS_PROJ_RES:
+      return launch_gemm<T>(c.st, FMD_K_GEMM_PROJ, false, EPI_RESID, c.Tp, d, d, w.att, d,
+                            (const T*)B.Wo, B.bo, nullptr, nullptr, nullptr, w.H, d, nullptr, tile);
+    case TS_PROJ_LN:
+      return launch_gemm<T>(c.st, FMD_K_GEMM_PROJ, true, EPI_STORE, c.Tp, d, d, w.H, d,
+                            (const T*)B.Wqc, B.bqc, w.stats, B.g2, B.s2, w.qc, d, nullptr, tile);
+    case TS_UP:
+      return launch_gemm<T>(c.st, FMD_K_GEMM_UP, true, EPI_GELU, c.Tp, 4 * d, d, w.H, d,
+                            (const T*)B.Wup, B.bup, w.stats, B.g3, B.s3, w.hid, 4 * d, nullptr, tile);
+    default:
+      return launch_gemm<T>(c.st, FMD_K_GEMM_DOWN, false, EPI_RESID, c.Tp, d, 4 * d, w.hid, 4 * d,
+                            (const T*)B.Wdn, B.bdn, nullptr, nullptr, nullptr, w.H, d, nullptr, tile);
+  }
+}
+
+// Autotuner: for every GEMM site not yet tuned for this token-count bucket, time each
+// candidate tiling that divides the shape (1 warm-up + 3 timed launches, best of the
+// three) and keep the fastest. All tilings give bitwise-identical results (same
+// k-slice accumulation order per element), so the choice affects speed only. Runs before
+// the first evaluation of a call, while the activation buffers hold nothing that is used
+// later (the residual stream is rebuilt by the next input embedding).
+template <typename T>
+int autotune(fmd_model* m, Call& c) {
+  if (!m->autotune || m->kind != 0) return FMD_OK;
+  const int b = bucket_of(c.Tp);
+  const int d = m->cfg.d_model;
+  const int N[TS_COUNT] = {3 * d, d, d, 4 * d, d};
+  const int K[TS_COUNT] = {d, d, d, d, 4 * d};
+  bool any = false;
+  for (int sl = 0; sl < TS_COUNT; ++sl) any |= m->tune[sl][b] < 0;
+  if (!any) return FMD_OK;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  int status = FMD_OK;
+  for (int sl = 0; sl < TS_COUNT && status == FMD_OK; ++sl) {
+    if (m->tune[sl][b] >= 0) continue;
+    int best = -1;
+    float best_us = 0.f;
+    for (int t = 0; t < kGemmTiles; ++t) {
+      if (!tile_fits(t, c.Tp, N[sl], K[sl])) continue;
+      if (slot_gemm<T>(m, c, sl, t, m->blk[0]) != hipSuccess) {
+        (void)hipGetLastError();
+        continue;
+      }
+      float run_best = 1e30f;
+      for (int rep = 0; rep < 3; ++rep) {
+        float ms = 0.f;
+        if (hipEventRecord(e0, c.st) != hipSuccess || slot_gemm<T>(m, c, sl, t, m->blk[0]) != hipSuccess ||
+            hipEventRecord(e1, c.st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+          status = fail(FMD_E_DEVICE, "autotune launch failed");
+          break;
+        }
+        run_best = std::min(run_best, ms * 1e3f);
+      }
+      if (status != FMD_OK) break;
+      if (best < 0 || run_best < best_us) best = t, best_us = run_best;
+    }
+    m->tune[sl][b] = (int8_t)(best >= 0 ? best : default_tile(N[sl]));
+    m->tune_us[sl][b] = best_us;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return status;
+}
+
 // One evaluation of the velocity network at xs; leaves the residual stream in w.H.
 template <typename T>
 int net_forward(fmd_model* m, Call& c, const float* t_ev, float t) {
@@ -401,7 +489,8 @@ int net_forward(fmd_model* m, Call& c, const float* t_ev, float t) {
     if (l > 0) FMD_TRY(row_stats(m, c));
     FMD_TRY(timed(m, c.st, FMD_K_GEMM_QKV, 2.0 * Td * d * 3 * d, [&] {
       return launch_gemm<T>(c.st, FMD_K_GEMM_QKV, true, EPI_STORE, c.Tp, 3 * d, d, w.H, d,
-                            (const T*)B.Wqkv, B.bqkv, w.stats, B.g1, B.s1, w.qkv, 3 * d);
+                            (const T*)B.Wqkv, B.bqkv, w.stats, B.g1, B.s1, w.qkv, 3 * d, nullptr,
+                            tile_for(m, TS_QKV, c.Tp, 3 * d));
     }));
     FMD_TRY(timed(m, c.st, FMD_K_ATTN_SELF, 4.0 * c.sum_n2 * d, [&] {
       return launch_attention<T>(c.st, false, dh, Hh, c.items, w.work, (const T*)qkv, 3 * d,
@@ -410,12 +499,14 @@ int net_forward(fmd_model* m, Call& c, const float* t_ev, float t) {
     }));
     FMD_TRY(timed(m, c.st, FMD_K_GEMM_PROJ, 2.0 * Td * d * d, [&] {
       return launch_gemm<T>(c.st, FMD_K_GEMM_PROJ, false, EPI_RESID, c.Tp, d, d, w.att, d,
-                            (const T*)B.Wo, B.bo, nullptr, nullptr, nullptr, w.H, d);
+                            (const T*)B.Wo, B.bo, nullptr, nullptr, nullptr, w.H, d, nullptr,
+                            tile_for(m, TS_PROJ_RES, c.Tp, d));
     }));
     FMD_TRY(row_stats(m, c));
     FMD_TRY(timed(m, c.st, FMD_K_GEMM_PROJ, 2.0 * Td * d * d, [&] {
       return launch_gemm<T>(c.st, FMD_K_GEMM_PROJ, true, EPI_STORE, c.Tp, d, d, w.H, d,
-                            (const T*)B.Wqc, B.bqc, w.stats, B.g2, B.s2, w.qc, d);
+                            (const T*)B.Wqc, B.bqc, w.stats, B.g2, B.s2, w.qc, d, nullptr,
+                            tile_for(m, TS_PROJ_LN, c.Tp, d));
     }));
     FMD_TRY(timed(m, c.st, FMD_K_ATTN_CROSS, 4.0 * c.sum_n2 * d, [&] {
       const size_t o = (size_t)l * 2 * d * es;
@@ -425,16 +516,19 @@ int net_forward(fmd_model* m, Call& c, const float* t_ev, float t) {
     }));
     FMD_TRY(timed(m, c.st, FMD_K_GEMM_PROJ, 2.0 * Td * d * d, [&] {
       return launch_gemm<T>(c.st, FMD_K_GEMM_PROJ, false, EPI_RESID, c.Tp, d, d, w.att, d,
-                            (const T*)B.Woc, B.boc, nullptr, nullptr, nullptr, w.H, d);
+                            (const T*)B.Woc, B.boc, nullptr, nullptr, nullptr, w.H, d, nullptr,
+                            tile_for(m, TS_PROJ_RES, c.Tp, d));
     }));
     FMD_TRY(row_stats(m, c));
     FMD_TRY(timed(m, c.st, FMD_K_GEMM_UP, 2.0 * Td * d * 4 * d, [&] {
       return launch_gemm<T>(c.st, FMD_K_GEMM_UP, true, EPI_GELU, c.Tp, 4 * d, d, w.H, d,
-                            (const T*)B.Wup, B.bup, w.stats, B.g3, B.s3, w.hid, 4 * d);
+                            (const T*)B.Wup, B.bup, w.stats, B.g3, B.s3, w.hid, 4 * d, nullptr,
+                            tile_for(m, TS_UP, c.Tp, 4 * d));
     }));
     FMD_TRY(timed(m, c.st, FMD_K_GEMM_DOWN, 2.0 * Td * 4 * d * d, [&] {
       return launch_gemm<T>(c.st, FMD_K_GEMM_DOWN, false, EPI_RESID, c.Tp, d, 4 * d, w.hid,
-                            4 * d, (const T*)B.Wdn, B.bdn, nullptr, nullptr, nullptr, w.H, d);
+                            4 * d, (const T*)B.Wdn, B.bdn, nullptr, nullptr, nullptr, w.H, d, nullptr,
+                            tile_for(m, TS_DOWN, c.Tp, d));
     }));
   }
   return FMD_OK;
@@ -505,9 +599,11 @@ int simulate_impl(fmd_model* m, const fmd_events_in* truth, const float* x0, uin
   if (m->kind == 0) {
     if (m->cfg.precision == FMD_BF16) {
       FMD_TRY(truth_cache<bf16>(m, c));
+      FMD_TRY(autotune<bf16>(m, c));
       FMD_TRY(integrate<bf16>(m, c, sched, out, 9));
     } else {
       FMD_TRY(truth_cache<float>(m, c));
+      FMD_TRY(autotune<float>(m, c));
       FMD_TRY(integrate<float>(m, c, sched, out, 9));
     }
   } else {
@@ -543,6 +639,8 @@ int fmd_model_create(const fmd_model_config* cfg, const float* params, size_t n_
     return fail(FMD_E_INVALID, "parameter vector has %zu values, the config needs %zu", n_params, need);
   fmd_model* m = new fmd_model();
   m->cfg = *cfg;
+  std::memset(m->tune, -1, sizeof(m->tune));
+  std::memset(m->tune_us, 0, sizeof(m->tune_us));
   auto bail = [&](int s) {
     fmd_model_destroy(m);
     return s;
@@ -709,9 +807,11 @@ int fmd_velocity(fmd_model* m, const fmd_events_in* truth, const float* x,
   float* out = truth->on_device ? v : w.io;
   if (m->cfg.precision == FMD_BF16) {
     FMD_TRY(truth_cache<bf16>(m, c));
+    FMD_TRY(autotune<bf16>(m, c));
     FMD_TRY(net_forward<bf16>(m, c, tev, 0.f));
   } else {
     FMD_TRY(truth_cache<float>(m, c));
+    FMD_TRY(autotune<float>(m, c));
     FMD_TRY(net_forward<float>(m, c, tev, 0.f));
   }
   FMD_TRY(head(m, c, UPD_VELOCITY, 0.f, 0.f, out, 9));
@@ -796,11 +896,47 @@ const char* fmd_kernel_name(fmd_model* m, int32_t cls) {
   return cls >= 0 && cls < FMD_K_COUNT ? names[cls] : "";
 }
 
+int fmd_autotune_enable(fmd_model* m, int32_t enable) {
+  if (!m) return fail(FMD_E_INVALID, "null model");
+  m->autotune = enable != 0;
+  return FMD_OK;
+}
+
+int fmd_tuning_table(fmd_model* m, char* buf, size_t cap, size_t* needed) {
+  if (!m) return fail(FMD_E_INVALID, "null model");
+  static const char* slot_names[TS_COUNT] = {"qkv", "proj_residual", "proj_ln", "mlp_up", "mlp_down"};
+  std::string js = "{\"precision\": \"";
+  js += m->cfg.precision == FMD_BF16 ? "bf16" : "fp32";
+  js += "\", \"d_model\": " + std::to_string(m->cfg.d_model) + ", \"entries\": [";
+  bool first = true;
+  for (int sl = 0; sl < TS_COUNT; ++sl)
+    for (int b = 0; b < kTuneBuckets; ++b) {
+      if (m->tune[sl][b] < 0) continue;
+      const TileDims t = tile_dims(m->tune[sl][b]);
+      char e[256];
+      snprintf(e, sizeof(e),
+               "%s{\"site\": \"%s\", \"tokens_log2\": %d, \"tile\": %d, \"BM\": %d, \"BN\": %d, "
+               "\"BK\": %d, \"threads\": %d, \"us\": %.1f}",
+               first ? "" : ", ", slot_names[sl], b, (int)m->tune[sl][b], t.BM, t.BN, t.BK, t.threads,
+               m->tune_us[sl][b]);
+      js += e;
+      first = false;
+    }
+  js += "]}";
+  if (needed) *needed = js.size() + 1;
+  if (buf && cap > 0) {
+    const size_t n = std::min(cap - 1, js.size());
+    std::memcpy(buf, js.data(), n);
+    buf[n] = 0;
+  }
+  return FMD_OK;
+}
+
 // ---- test hooks ---------------------------------------------------------------------
 
 int fmd_debug_gemm(int32_t precision, int64_t M, int32_t N, int32_t K, const float* A,
                    const float* W, const float* bias, int32_t ln, const float* g,
-                   const float* s, int32_t epi, float* C, void* hip_stream) {
+                   const float* s, int32_t epi, float* C, int32_t tile, void* hip_stream) {
   if (precision != FMD_FP32 && precision != FMD_BF16) return fail(FMD_E_INVALID, "bad precision");
   if (M < 0 || N <= 0 || K <= 0 || K % 32 || N % 64) return fail(FMD_E_INVALID, "bad GEMM shape");
   if (epi < 0 || epi > 2) return fail(FMD_E_INVALID, "bad epilogue");
@@ -808,6 +944,12 @@ int fmd_debug_gemm(int32_t precision, int64_t M, int32_t N, int32_t K, const flo
   if (!A || !W || !C || (ln && (!g || !s))) return fail(FMD_E_INVALID, "null operand");
   hipStream_t st = (hipStream_t)hip_stream;
   const int64_t Mp = round_up(M, kGemmBM);
+  if (tile >= kGemmTiles || (tile >= 0 && !tile_fits(tile, Mp, N, K)))
+    return fail(FMD_E_UNSUPPORTED, "tiling %d does not divide the shape", tile);
+  const int cls = ln && epi == EPI_STORE ? FMD_K_GEMM_QKV : ln && epi == EPI_GELU ? FMD_K_GEMM_UP
+                  : !ln && epi == EPI_RESID ? FMD_K_GEMM_DOWN : FMD_K_OTHER;
+  if (cls == FMD_K_OTHER && tile != -1 && tile != 0 && tile != 4)
+    return fail(FMD_E_UNSUPPORTED, "this epilogue combination has tilings 0 and 4 only");
   const size_t es = precision == FMD_BF16 ? 2 : 4;
   const size_t a_es = ln ? 4 : es;
   const size_t c_es = epi == EPI_RESID ? 4 : es;
@@ -833,8 +975,8 @@ int fmd_debug_gemm(int32_t precision, int64_t M, int32_t N, int32_t K, const flo
     }
     if (e == hipSuccess)
       e = precision == FMD_BF16
-              ? launch_gemm<bf16>(st, FMD_K_OTHER, ln != 0, epi, Mp, N, K, Ap, K, (const bf16*)Wt, bias, st2, g, s, Cp, N)
-              : launch_gemm<float>(st, FMD_K_OTHER, ln != 0, epi, Mp, N, K, Ap, K, (const float*)Wt, bias, st2, g, s, Cp, N);
+              ? launch_gemm<bf16>(st, cls, ln != 0, epi, Mp, N, K, Ap, K, (const bf16*)Wt, bias, st2, g, s, Cp, N, nullptr, tile)
+              : launch_gemm<float>(st, cls, ln != 0, epi, Mp, N, K, Ap, K, (const float*)Wt, bias, st2, g, s, Cp, N, nullptr, tile);
     if (e == hipSuccess) {
       if (epi == EPI_RESID || precision == FMD_FP32)
         e = hipMemcpyAsync(C, Cp, (size_t)M * N * 4, hipMemcpyDeviceToDevice, st);

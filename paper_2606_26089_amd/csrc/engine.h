@@ -43,6 +43,10 @@ struct Workspace {
   int64_t h_cap_ev = 0, h_cap_items = 0;
 };
 
+// GEMM sites the autotuner chooses a tiling for.
+enum TuneSlot { TS_QKV = 0, TS_PROJ_RES = 1, TS_PROJ_LN = 2, TS_UP = 3, TS_DOWN = 4, TS_COUNT = 5 };
+constexpr int kTuneBuckets = 40;   // floor(log2(padded token count))
+
 struct TimingRec {
   int cls;
   double work;
@@ -66,6 +70,9 @@ struct fmd_model {
   const float *W_tin, *b_tin, *g_t, *s_t, *W_xin, *b_xin, *W_time, *b_time, *g_f, *s_f, *W_out,
       *b_out;
   fmd::Workspace ws;
+  int autotune = 1;                // 1: time the candidate tilings on first use of a size bucket
+  int8_t tune[fmd::TS_COUNT][fmd::kTuneBuckets];   // chosen tiling, -1 = not tuned yet
+  float tune_us[fmd::TS_COUNT][fmd::kTuneBuckets]; // its measured time
   bool timing = false;
   std::vector<fmd::TimingRec> trec;
   std::vector<hipEvent_t> ev_pool;

@@ -34,19 +34,25 @@ struct OdeArgs {
   int ldx, ldo, nf, mode;
   float h;
 };
-constexpr int kGemmBM = 128;       // GEMM row tile; token buffers are padded to this
+constexpr int kGemmBM = 256;       // largest GEMM row tile; token buffers are padded to this
 
 // C = epi(pro(A) W + b). A: float [Mp, lda] if ln, else T [Mp, lda]. Wt: T [N, K]
 // (the transpose of the [K, N] weight). C: T [Mp, ldc] for STORE/GELU, float for RESID.
 // With ln, stats holds (mean, 1/sqrt(var + eps)) of every row of A (launch_row_stats)
 // and pro(A) = (A - mean) * rstd * g + s.
-// Requires Mp % 128 == 0, K % 32 == 0, N % 64 == 0.
-// `cls` (an FMD_K_* class) selects the kernel name the launch appears under in profiles.
+// Requires Mp % 256 == 0, K % 32 == 0, N % 64 == 0 and a tiling that divides the shape.
+// `cls` (an FMD_K_* class) selects the kernel name the launch appears under in profiles;
+// `tile` picks one of the candidate tilings (gemm_body.h), -1 the default for N.
 template <typename T>
 hipError_t launch_gemm(hipStream_t st, int cls, bool ln, int epi, int64_t Mp, int N, int K,
                        const void* A, int lda, const T* Wt, const float* bias,
                        const float2* stats, const float* g, const float* s, void* C, int ldc,
-                       const OdeArgs* ode = nullptr);
+                       const OdeArgs* ode = nullptr, int tile = -1);
+
+// Candidate GEMM tilings the autotuner chooses from, and whether one divides a shape.
+constexpr int kGemmTiles = 7;
+bool tile_fits(int tile, int64_t Mp, int N, int K);
+int default_tile(int N);
 
 // LayerNorm statistics of the rows of a float [M, ld] matrix over its first K columns:
 // stats[r] = (mean, 1/sqrt(biased var + eps)), two passes in registers, one wave per row.

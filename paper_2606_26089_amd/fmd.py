@@ -87,9 +87,11 @@ def lib():
         "fmd_timing_read": (c_int32, [c_void_p, c_int32, ctypes.POINTER(c_double),
                                       ctypes.POINTER(c_int64), ctypes.POINTER(c_double)]),
         "fmd_kernel_name": (ctypes.c_char_p, [c_void_p, c_int32]),
+        "fmd_autotune_enable": (c_int32, [c_void_p, c_int32]),
+        "fmd_tuning_table": (c_int32, [c_void_p, ctypes.c_char_p, c_size_t, ctypes.POINTER(c_size_t)]),
         "fmd_debug_gemm": (c_int32, [c_int32, c_int64, c_int32, c_int32, c_void_p, c_void_p,
                                      c_void_p, c_int32, c_void_p, c_void_p, c_int32, c_void_p,
-                                     c_void_p]),
+                                     c_int32, c_void_p]),
         "fmd_debug_attention": (c_int32, [c_int32, c_int64, P_int64, P_int64, c_int32, c_int32,
                                           c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     }
@@ -250,6 +252,17 @@ class Model:
                                      ctypes.byref(work)))
         return ms.value, n.value, work.value
 
+    def autotune_enable(self, on=True):
+        _check(lib().fmd_autotune_enable(self._h, int(bool(on))))
+
+    def tuning_table(self):
+        import json
+        need = c_size_t()
+        _check(lib().fmd_tuning_table(self._h, None, 0, ctypes.byref(need)))
+        buf = ctypes.create_string_buffer(need.value)
+        _check(lib().fmd_tuning_table(self._h, buf, need.value, None))
+        return json.loads(buf.value.decode())
+
     def kernel_name(self, cls):
         return lib().fmd_kernel_name(self._h, int(cls)).decode()
 
@@ -289,8 +302,9 @@ def debug_philox(key0, key1, counters, out=None, stream=None):
     return out
 
 
-def debug_gemm(precision, A, W, bias=None, ln=None, epi=0, C=None, stream=None):
-    """Device float32 tensors: A [M, K], W [K, N]; ln = (g, s) or None; epi 0/1/2."""
+def debug_gemm(precision, A, W, bias=None, ln=None, epi=0, C=None, tile=-1, stream=None):
+    """Device float32 tensors: A [M, K], W [K, N]; ln = (g, s) or None; epi 0/1/2;
+    tile = candidate tiling (-1 default)."""
     import torch
     M, K = A.shape
     N = W.shape[1]
@@ -299,7 +313,7 @@ def debug_gemm(precision, A, W, bias=None, ln=None, epi=0, C=None, stream=None):
     g, s = ln if ln is not None else (None, None)
     P = lambda t: c_void_p(t.data_ptr()) if t is not None else None  # noqa: E731
     _check(lib().fmd_debug_gemm(int(precision), M, N, K, P(A), P(W), P(bias), int(ln is not None),
-                                P(g), P(s), int(epi), P(C), _stream(stream)))
+                                P(g), P(s), int(epi), P(C), int(tile), _stream(stream)))
     return C
 
 

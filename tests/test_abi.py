@@ -114,7 +114,7 @@ def test_null_model_and_errors_are_reported(fmd):
     assert b"null model" in L.fmd_last_error()
     assert L.fmd_noise(0, None, 1, 9, None, None) == fmd.E_INVALID
     assert L.fmd_pack_padded(None, None, 1, 4, 9, None, None, None) == fmd.E_INVALID
-    assert L.fmd_debug_gemm(0, 4, 60, 32, None, None, None, 0, None, None, 0, None, None) == fmd.E_INVALID
+    assert L.fmd_debug_gemm(0, 4, 60, 32, None, None, None, 0, None, None, 0, None, -1, None) == fmd.E_INVALID
     assert L.fmd_model_destroy(None) == fmd.OK
     assert L.fmd_kernel_name(None, fmd.K_GEMM_UP) == b"k_gemm_up"
 

@@ -105,6 +105,40 @@ def test_gemm(env, prec, M, N, K, ln, epi):
     assert normwise(out.cpu().numpy(), ref) < tol
 
 
+TILE_CASES = [  # (M, N, K, ln, epi) exercising every tiling of the autotuner
+    (700, 768, 256, True, 0), (300, 1024, 256, True, 1), (513, 256, 1024, False, 2),
+    (200, 256, 256, False, 2), (100, 64, 64, True, 0),
+]
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("M,N,K,ln,epi", TILE_CASES)
+def test_gemm_every_tiling_matches(env, prec, M, N, K, ln, epi):
+    """Each candidate tiling that divides the shape gives the same bits as the default."""
+    torch, fmd = env
+    rng = np.random.default_rng(M + N)
+    dev = lambda a: torch.from_numpy(a).cuda()  # noqa: E731
+    A = dev(rng.standard_normal((M, K)).astype(np.float32))
+    W = dev((rng.standard_normal((K, N)) / np.sqrt(K)).astype(np.float32))
+    b = dev(rng.standard_normal(N).astype(np.float32))
+    g = dev((1 + 0.1 * rng.standard_normal(K)).astype(np.float32))
+    s = dev((0.1 * rng.standard_normal(K)).astype(np.float32))
+    C0 = rng.standard_normal((M, N)).astype(np.float32)
+    ref = fmd.debug_gemm(prec, A, W, b, (g, s) if ln else None, epi,
+                         dev(C0.copy()) if epi == 2 else None).cpu().numpy()
+    tried = 0
+    for tile in range(7):
+        try:
+            out = fmd.debug_gemm(prec, A, W, b, (g, s) if ln else None, epi,
+                                 dev(C0.copy()) if epi == 2 else None, tile=tile).cpu().numpy()
+        except fmd.FmdError as e:
+            assert e.status == fmd.E_UNSUPPORTED
+            continue
+        tried += 1
+        assert np.array_equal(out, ref), tile
+    assert tried >= 2
+
+
 ATTN_CASES = [  # (event sizes, heads, dh)
     ([1], 1, 16), ([2, 31, 32, 33], 4, 16), ([64, 65, 1, 127, 128, 129], 8, 32),
     ([200, 3, 150], 8, 32), ([1000], 2, 32), ([17, 70], 2, 64), ([0, 5, 0, 9], 4, 32),
