@@ -86,6 +86,67 @@ def cpu_baseline(w, flat, off, feat, sample_events, processes):
     return dt, np.concatenate(outs)
 
 
+def serve_leg(fmd, w_serve, flat, rates, seconds, budget):
+    """Open-loop Poisson load on the continuous-batching server, one run per offered rate.
+
+    Requests arrive at exponential gaps (mean = E[events per request] / rate). Each carries
+    1..512 events with heavy-tailed multiplicities and asks for Euler 20 or RK4 16 with
+    probability 1/2. They are submitted at their arrival times whatever the server's state,
+    so queueing counts in the latency. Latency = completion - submission on the server's
+    monotonic clock, weighted per event (each event takes its request's latency) and per
+    request.
+    """
+    import threading
+
+    from workload import arrivals
+
+    out = []
+    m = fmd.Model(w_serve.model, flat)
+    srv = fmd.Server(m, hbm_budget_bytes=budget)
+    for rate in rates:
+        n_req = max(4, int(rate * seconds / 256.5))
+        reqs = arrivals.stream(rate, n_req, seed=w_serve.extra["arrival_seed"])
+        ids = [None] * n_req
+        t_start = time.perf_counter()
+
+        def submit():
+            for i, r in enumerate(reqs):
+                dt = r.t_arrive - (time.perf_counter() - t_start)
+                if dt > 0:
+                    time.sleep(dt)
+                ids[i] = srv.submit(r.offsets, r.feat, r.seed, r.schedule)
+
+        th = threading.Thread(target=submit)
+        th.start()
+        lat_req, lat_ev, n_events, t_first, t_last = [], [], 0, None, None
+        for i in range(n_req):
+            while ids[i] is None:
+                time.sleep(0.0005)
+            _, st = srv.wait(ids[i])
+            lat = (st["t_done_ns"] - st["t_submit_ns"]) * 1e-6
+            ne = len(reqs[i].offsets) - 1
+            lat_req.append(lat)
+            lat_ev += [lat] * ne
+            n_events += ne
+            t_first = st["t_submit_ns"] if t_first is None else min(t_first, st["t_submit_ns"])
+            t_last = st["t_done_ns"] if t_last is None else max(t_last, st["t_done_ns"])
+        th.join()
+        wall = (t_last - t_first) * 1e-9
+        rec = {"offered_events_per_s": rate, "requests": n_req, "events": n_events,
+               "achieved_events_per_s": round(n_events / wall, 1),
+               "p50_event_ms": round(float(np.percentile(lat_ev, 50)), 2),
+               "p99_event_ms": round(float(np.percentile(lat_ev, 99)), 2),
+               "p50_request_ms": round(float(np.percentile(lat_req, 50)), 2),
+               "p99_request_ms": round(float(np.percentile(lat_req, 99)), 2)}
+        log(f"serve @ {rate} ev/s offered: {rec}")
+        out.append(rec)
+    info = srv.info()
+    srv.close()
+    m.close()
+    return {"rates": out, "hbm_budget_bytes": budget, "pool_tokens": info["pool_tokens"],
+            "iterations": info["iterations"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -95,6 +156,9 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=0, help="oracle events (0: 2 per core)")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-rates", default="1000,2000,5000")
+    ap.add_argument("--serve-seconds", type=float, default=4.0)
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {a.gpus}): events are independent and "
@@ -154,6 +218,12 @@ def main():
             err["fp32_vs_oracle"] = float(errors.normwise_rel_err(out32[:rows], ref).max())
         log(f"oracle: {cpu['value']} events/s on {cores} cores; errors {err}")
 
+    serve = None
+    if not a.no_serve:
+        ws = configs.SERVE_BF16
+        rates = [float(r) for r in a.serve_rates.split(",") if r]
+        serve = serve_leg(fmd, ws, flat, rates, a.serve_seconds, ws.extra["hbm_budget_bytes"])
+
     line = {
         "metric": "sampled events/s (BF16 path; FP32 plain path and errors vs the FP64 oracle "
                   "alongside; p50/p99 event latency from the serving loop)",
@@ -165,7 +235,8 @@ def main():
                                "RK4 16 steps (64 evaluations)", "events": E, "particles": T,
                    "precision": "bf16 operands, fp32 accumulation and state",
                    "tiles": kern16["_tiles"]},
-        "fp32": fp32, "error": err, "latency": None,
+        "fp32": fp32, "error": err,
+        "latency": serve,
         "roofline": rl, "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -188,6 +188,16 @@ int fmd_timing_read(fmd_model* m, int32_t kernel_class, double* total_ms, int64_
 /* Name of the HIP kernel behind a class, as rocprofv3 reports it (static string). */
 const char* fmd_kernel_name(fmd_model* m, int32_t kernel_class);
 
+/* ---- launch mode --------------------------------------------------------------------- */
+
+/* While enabled (the default), the kernels of one ODE stage are captured once per call
+ * shape into a HIP graph on the model's private stream. The graph is replayed once per
+ * stage: time, step and update mode come from a per-call stage table in device memory. A
+ * later call with the same token count, event count, output buffer and workspace reuses
+ * the graph without re-capturing it. With timing on, or with graphs disabled, the same
+ * kernels are launched one by one. Results are identical either way. */
+int fmd_graphs_enable(fmd_model* m, int32_t enable);
+
 /* ---- tile autotuner ------------------------------------------------------------------- */
 
 /* The GEMM sites of the network (QKV, attention projections with the residual, cross-query,
@@ -225,6 +235,58 @@ int fmd_debug_attention(int32_t precision, int64_t n_events, const int64_t* q_of
                         const int64_t* kv_offsets, int32_t n_heads, int32_t dh,
                         const float* Q, const float* K, const float* V, float* O,
                         void* hip_stream);
+
+/* ---- serving ----------------------------------------------------------------------------- */
+
+/* A continuous-batching server over one model. Requests are admitted FIFO when a
+ * contiguous range of their particle count is free in a device token pool. The pool is
+ * sized as hbm_budget_bytes divided by the per-token footprint: ODE state, activations,
+ * truth encoding, cross K/V cache and output. An admitted request's state stays on the
+ * device until it completes.
+ * Each server iteration advances every resident event by one stage of its own schedule.
+ * Euler and RK4 requests and requests at different points of their integration share
+ * one launch. A request's result is bitwise the same alone and in any mix: noise is
+ * keyed by (seed, event index in the request, slot). The batch-of-the-paper knob
+ * (App. C, batch_size) becomes the budget and the limits below.
+ * While a server exists, the model's own sampling calls return FMD_E_STATE, and the
+ * server must be destroyed before the model. */
+typedef struct fmd_server fmd_server;   /* opaque */
+
+typedef struct {
+  size_t hbm_budget_bytes;      /* device bytes the resident requests may hold */
+  int64_t max_tokens_per_iter;  /* cap on the resident particles (0: only the budget) */
+  int32_t max_requests;         /* cap on resident requests (0: no cap) */
+} fmd_server_config;
+
+typedef struct {
+  uint64_t t_submit_ns, t_admit_ns, t_done_ns;   /* CLOCK_MONOTONIC */
+} fmd_request_stats;
+
+typedef struct {
+  int64_t pool_tokens, bytes_per_token, queued_requests, resident_requests, resident_tokens;
+  int64_t iterations, rows_processed, busy_ns;
+} fmd_server_info;
+
+/* Starts the worker thread. FMD_E_BUDGET if the budget holds less than one particle. */
+int fmd_server_create(fmd_model* m, const fmd_server_config* cfg, fmd_server** out);
+
+/* Queues a request. truth->feat must be host memory; it is copied before the call
+ * returns. *req_id identifies the request. FMD_E_BUDGET if it can never fit the pool,
+ * FMD_E_UNSUPPORTED if an event exceeds n_max, FMD_E_STATE if the server has failed. */
+int fmd_server_submit(fmd_server* s, const fmd_events_in* truth, uint64_t seed,
+                      const fmd_schedule* schedule, uint64_t* req_id);
+
+/* FMD_PENDING while the request runs. Once it has finished, copies the result
+ * ([particles, 9] FP32, host) and the timestamps, forgets the request and returns its
+ * status. A request is collected once. */
+int fmd_server_poll(fmd_server* s, uint64_t req_id, float* reco_host, fmd_request_stats* st);
+int fmd_server_wait(fmd_server* s, uint64_t req_id, float* reco_host, fmd_request_stats* st);
+
+int fmd_server_get_info(fmd_server* s, fmd_server_info* info);
+
+/* Stops the worker after its current iteration. Requests not yet finished end with
+ * FMD_E_STATE, and uncollected results are dropped. */
+int fmd_server_destroy(fmd_server* s);
 
 /* Message for the last non-OK status of the calling thread ("" if none). */
 const char* fmd_last_error(void);

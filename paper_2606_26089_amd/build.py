@@ -18,8 +18,8 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libfmdet.so")
 
 SOURCES = ["gemm_bf16.hip", "gemm_f32.hip", "kernels_misc.hip", "gemm.hip", "attention.hip",
-           "engine.cpp"]
-HEADERS = ["common.h", "kernels.h", "engine.h", "gemm_body.h", "gemm_inst.h",
+           "engine.cpp", "server.cpp"]
+HEADERS = ["common.h", "kernels.h", "engine.h", "engine_impl.h", "gemm_body.h", "gemm_inst.h",
            os.path.join("..", "..", "include", "fmd.h")]
 
 ARCH = "gfx950"
@@ -58,7 +58,7 @@ def build(jobs: int | None = None, debug: bool = False) -> str:
     with cf.ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(lambda s: _compile(s, opt), SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs
+    cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs + ["-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"linking failed:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

@@ -52,7 +52,7 @@ __device__ __forceinline__ float gelu_erf(float z) {
 
 // ODE state update of one feature, v being the velocity evaluated at xs. Modes:
 // 0 Euler x += h v; 1..4 the four RK4 stages (acc collects k1 + 2 k2 + 2 k3, xs receives
-// the next stage input); 5 velocity only (v written to out).
+// the next stage input); 5 velocity only (v written to out); anything else: no effect.
 __device__ __forceinline__ void ode_update(int mode, float h, float v, float* x, float* acc,
                                            float* xs, float* out) {
   switch (mode) {
@@ -78,8 +78,10 @@ __device__ __forceinline__ void ode_update(int mode, float h, float v, float* x,
       *x = xn; *xs = xn;
       if (out) *out = xn;
     } break;
-    default:
+    case 5:
       if (out) *out = v;
+      break;
+    default:
       break;
   }
 }

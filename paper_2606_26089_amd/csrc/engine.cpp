@@ -15,13 +15,13 @@
 #include <string>
 #include <vector>
 
-#include "engine.h"
+#include "engine_impl.h"
 #include "gemm_body.h"
-#include "kernels.h"
 
 using namespace fmd;
 
-namespace {
+namespace fmd {
+namespace eng {
 
 thread_local std::string g_err;
 
@@ -34,34 +34,6 @@ int fail(int status, const char* fmt, ...) {
   g_err = buf;
   return status;
 }
-
-#define HIP_TRY(expr)                                                                    \
-  do {                                                                                   \
-    hipError_t e_ = (expr);                                                              \
-    if (e_ != hipSuccess)                                                                \
-      return fail(FMD_E_DEVICE, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, \
-                  __LINE__);                                                             \
-  } while (0)
-
-#define FMD_TRY(expr)              \
-  do {                             \
-    int s_ = (expr);               \
-    if (s_ != FMD_OK) return s_;   \
-  } while (0)
-
-struct DeviceGuard {
-  int prev = -1;
-  explicit DeviceGuard(int dev) {
-    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-    if (prev != dev) (void)hipSetDevice(dev);
-  }
-  ~DeviceGuard() {
-    int cur = -1;
-    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-  }
-};
-
-int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 
 // ---------------------------------------------------------------------------------------
 // configuration and parameter layout
@@ -123,37 +95,12 @@ size_t elem_size(const fmd_model_config& c) { return c.precision == FMD_BF16 ? 2
 // ---------------------------------------------------------------------------------------
 // workspace
 
-template <typename P>
-int grow(P*& p, size_t bytes) {
-  if (p) (void)hipFree(p);
-  p = nullptr;
-  if (bytes == 0) return FMD_OK;
-  if (hipMalloc((void**)&p, bytes) != hipSuccess) {
-    (void)hipGetLastError();
-    p = nullptr;
-    return fail(FMD_E_NOMEM, "device allocation of %zu bytes failed", bytes);
-  }
-  if (hipMemset(p, 0, bytes) != hipSuccess) return fail(FMD_E_DEVICE, "hipMemset failed");
-  return FMD_OK;
-}
-
-template <typename P>
-int grow_host(P*& p, size_t bytes) {
-  if (p) (void)hipHostFree(p);
-  p = nullptr;
-  if (hipHostMalloc((void**)&p, bytes, hipHostMallocDefault) != hipSuccess) {
-    (void)hipGetLastError();
-    p = nullptr;
-    return fail(FMD_E_NOMEM, "pinned host allocation of %zu bytes failed", bytes);
-  }
-  return FMD_OK;
-}
-
 void free_ws(Workspace& w) {
   void* dev[] = {w.x, w.acc, w.xs, w.H, w.qkv, w.att, w.qc, w.hid, w.c, w.kv, w.u, w.io,
-                 w.temb, w.tev, w.stats, w.tok_event, w.off, w.work};
+                 w.temb, w.tev, w.stats, w.tok_event, w.off, w.work, w.desc, w.ctr};
   for (void* p : dev)
     if (p) (void)hipFree(p);
+  if (w.h_desc) (void)hipHostFree(w.h_desc);
   if (w.h_off) (void)hipHostFree(w.h_off);
   if (w.h_work) (void)hipHostFree(w.h_work);
   w = Workspace();
@@ -166,7 +113,10 @@ int ensure_ws_alloc(fmd_model* m, int64_t T, int64_t E, int64_t items, bool* gre
 int ensure_ws(fmd_model* m, int64_t T, int64_t E, int64_t items) {
   bool grew = false;
   FMD_TRY(ensure_ws_alloc(m, T, E, items, &grew));
-  if (grew) HIP_TRY(hipDeviceSynchronize());
+  if (grew) {
+    HIP_TRY(hipDeviceSynchronize());
+    m->ws.generation++;
+  }
   return FMD_OK;
 }
 
@@ -185,6 +135,7 @@ int ensure_ws_alloc(fmd_model* m, int64_t T, int64_t E, int64_t items, bool* gre
     FMD_TRY(grow(w.u, (size_t)cap * 9 * 4));
     FMD_TRY(grow(w.io, (size_t)cap * 9 * 4));
     FMD_TRY(grow(w.tok_event, (size_t)cap * 4));
+    if (!w.ctr) FMD_TRY(grow(w.ctr, 64));
     if (m->kind == 0) {
       FMD_TRY(grow(w.H, (size_t)cap * d * 4));
       FMD_TRY(grow(w.stats, (size_t)cap * sizeof(float2)));
@@ -287,33 +238,8 @@ void flush_timing(fmd_model* m) {
   m->trec.clear();
 }
 
-template <typename F>
-int timed(fmd_model* m, hipStream_t st, int cls, double work, F&& launch) {
-  hipEvent_t a = nullptr, b = nullptr;
-  if (m->timing) {
-    if (m->trec.size() > 4096) flush_timing(m);
-    a = take_event(m);
-    b = take_event(m);
-    if (a && b) (void)hipEventRecord(a, st);
-  }
-  const hipError_t e = launch();
-  if (e != hipSuccess) return fail(FMD_E_DEVICE, "kernel launch (class %d): %s", cls, hipGetErrorString(e));
-  if (m->timing && a && b) {
-    (void)hipEventRecord(b, st);
-    m->trec.push_back(TimingRec{cls, work, a, b});
-  }
-  return FMD_OK;
-}
-
 // ---------------------------------------------------------------------------------------
 // one call's device state
-
-struct Call {
-  hipStream_t st;
-  int64_t E, T, Tp, items;
-  double sum_n2;        // sum over events of N_e^2 (attention work)
-  const float* u;       // truth features on device [T, 9]
-};
 
 // Uploads offsets and the attention work list; runs the token map.
 int stage_events(fmd_model* m, const fmd_events_in* ev, Call& c) {
@@ -460,6 +386,7 @@ int autotune(fmd_model* m, Call& c) {
     }
     m->tune[sl][b] = (int8_t)(best >= 0 ? best : default_tile(N[sl]));
     m->tune_us[sl][b] = best_us;
+    m->tune_gen++;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -467,8 +394,9 @@ int autotune(fmd_model* m, Call& c) {
 }
 
 // One evaluation of the velocity network at xs; leaves the residual stream in w.H.
+// t_ev: per-event times (device); otherwise the time of the current stage-table entry.
 template <typename T>
-int net_forward(fmd_model* m, Call& c, const float* t_ev, float t) {
+int net_forward(fmd_model* m, Call& c, const float* t_ev) {
   Workspace& w = m->ws;
   const fmd_model_config& cf = m->cfg;
   const int d = cf.d_model, L = cf.n_blocks, Hh = cf.n_heads, dh = d / Hh;
@@ -477,8 +405,8 @@ int net_forward(fmd_model* m, Call& c, const float* t_ev, float t) {
   char* qkv = (char*)w.qkv;
   char* kv = (char*)w.kv;
   FMD_TRY(timed(m, c.st, FMD_K_OTHER, 0, [&] {
-    return launch_time_embed(c.st, t_ev, t, t_ev ? (int)c.E : 1, m->W_time, m->b_time, m->b_xin,
-                             cf.t_embed_dim, d, w.temb);
+    return launch_time_embed(c.st, t_ev, t_ev ? nullptr : w.desc, w.ctr, 0.f, t_ev ? (int)c.E : 1,
+                             m->W_time, m->b_time, m->b_xin, cf.t_embed_dim, d, w.temb);
   }));
   FMD_TRY(timed(m, c.st, FMD_K_OTHER, 0, [&] {
     return launch_embed(c.st, w.xs, kStateLd, 9, c.T, t_ev ? w.tok_event : nullptr, w.temb,
@@ -534,55 +462,123 @@ int net_forward(fmd_model* m, Call& c, const float* t_ev, float t) {
   return FMD_OK;
 }
 
-int head(fmd_model* m, Call& c, int mode, float h, float t, float* out, int ldo) {
+// Output head with the fused state update. With `direct` the update mode is `mode` (the
+// velocity-only hook); otherwise mode, step and output write follow the stage table.
+int head(fmd_model* m, Call& c, bool direct, int mode, float* out, int ldo) {
   Workspace& w = m->ws;
   if (m->kind == 1)
     return timed(m, c.st, FMD_K_OTHER, 0, [&] {
-      return launch_linear_update(c.st, (float)m->alpha, (float)m->beta, t, c.T, 9, mode, h, w.x,
-                                  w.acc, w.xs, kStateLd, out, ldo);
+      return launch_linear_update(c.st, (float)m->alpha, (float)m->beta, w.desc, w.ctr, c.T, 9,
+                                  w.x, w.acc, w.xs, kStateLd, out, ldo);
     });
   FMD_TRY(row_stats(m, c));
   const int d = m->cfg.d_model;
-  const OdeArgs ode{w.x, w.acc, w.xs, out, c.T, kStateLd, ldo, 9, mode, h};
+  const OdeArgs ode{w.x, w.acc, w.xs, out, c.T, kStateLd, ldo, 9, mode, 0.f,
+                    direct ? nullptr : w.desc, w.ctr, nullptr};
   return timed(m, c.st, FMD_K_OTHER, 2.0 * c.T * d * 9, [&] {
     return launch_gemm<float>(c.st, FMD_K_OTHER, true, EPI_ODE, c.Tp, 64, d, w.H, d, m->Wout_pk,
                               m->bout_pk, w.stats, m->g_f, m->s_f, nullptr, 0, &ode);
   });
 }
 
-template <typename T>
-int integrate(fmd_model* m, Call& c, const fmd_schedule* s, float* out, int ldo) {
-  const int K = s->n_steps;
+// Uploads the stage table of a schedule: stage i = (t, h, update mode, write output).
+int upload_stages(fmd_model* m, Call& c, const fmd_schedule* s, int* n_stages) {
+  Workspace& w = m->ws;
+  const int K = s->n_steps, S = s->scheme == FMD_EULER ? 1 : 4;
+  const int n = K * S;
+  if (n > w.cap_desc) {
+    FMD_TRY(grow(w.desc, (size_t)n * sizeof(StageDesc)));
+    FMD_TRY(grow_host(w.h_desc, (size_t)n * sizeof(StageDesc)));
+    HIP_TRY(hipDeviceSynchronize());
+    w.cap_desc = n;
+    w.generation++;
+  }
   const double h = (s->t1 - s->t0) / K;
   static const double c_rk4[4] = {0.0, 0.5, 0.5, 1.0};
-  for (int k = 0; k < K; ++k) {
-    const int S = s->scheme == FMD_EULER ? 1 : 4;
+  for (int k = 0; k < K; ++k)
     for (int st = 0; st < S; ++st) {
-      const double t = s->t0 + (k + (S == 1 ? 0.0 : c_rk4[st])) * h;
-      if (m->kind == 0) FMD_TRY(net_forward<T>(m, c, nullptr, (float)t));
-      const int mode = S == 1 ? UPD_EULER : UPD_RK4_0 + st;
-      const bool last = k == K - 1 && st == S - 1;
-      FMD_TRY(head(m, c, mode, (float)h, (float)t, last ? out : nullptr, ldo));
+      StageDesc& d = w.h_desc[k * S + st];
+      d.t = (float)(s->t0 + (k + (S == 1 ? 0.0 : c_rk4[st])) * h);
+      d.h = (float)h;
+      d.mode = S == 1 ? UPD_EULER : UPD_RK4_0 + st;
+      d.write_out = k == K - 1 && st == S - 1;
     }
-  }
+  HIP_TRY(hipMemcpyAsync(w.desc, w.h_desc, (size_t)n * sizeof(StageDesc), hipMemcpyHostToDevice, c.st));
+  FMD_TRY(timed(m, c.st, FMD_K_OTHER, 0, [&] { return launch_set_counter(c.st, w.ctr, 0); }));
+  *n_stages = n;
   return FMD_OK;
 }
 
-int simulate_impl(fmd_model* m, const fmd_events_in* truth, const float* x0, uint64_t seed,
-                  const fmd_schedule* sched, fmd_events_out* reco, void* stream) {
-  if (!m) return fail(FMD_E_INVALID, "null model");
-  Call c{};
-  c.st = (hipStream_t)stream;
-  FMD_TRY(check_events(m, truth, &c.T, nullptr));
-  FMD_TRY(check_schedule(sched));
-  if (!reco) return fail(FMD_E_INVALID, "null reco output");
-  if (c.T > 0 && !reco->feat) return fail(FMD_E_INVALID, "null reco feature array");
-  c.E = truth->n_events;
-  if (c.T == 0) return FMD_OK;
-  DeviceGuard guard(m->device);
-  c.Tp = round_up(c.T, kGemmBM);
+// One ODE stage: velocity at the current stage input, fused update, counter advance.
+template <typename T>
+int run_stage(fmd_model* m, Call& c, float* out, int ldo) {
+  if (m->kind == 0) FMD_TRY(net_forward<T>(m, c, nullptr));
+  FMD_TRY(head(m, c, false, 0, out, ldo));
+  return timed(m, c.st, FMD_K_OTHER, 0, [&] { return launch_stage_advance(c.st, m->ws.ctr); });
+}
+
+// All stages of a call. With graphs on, one stage is captured into a HIP graph (kernels
+// read time, mode and step from the stage table through the device counter) and the graph
+// is replayed once per stage; the executable graph is kept for later calls with the same
+// shapes, buffers and output pointer.
+template <typename T>
+int run_stages(fmd_model* m, Call& c, int n_stages, float* out, int ldo) {
+  if (!m->graphs || m->timing) {
+    for (int i = 0; i < n_stages; ++i) FMD_TRY(run_stage<T>(m, c, out, ldo));
+    return FMD_OK;
+  }
+  const GraphKey key{c.Tp, c.T, c.E, c.items, out, ldo, m->ws.generation, m->tune_gen};
+  if (!m->gexec || !(key == m->gkey)) {
+    if (m->gexec) (void)hipGraphExecDestroy(m->gexec);
+    m->gexec = nullptr;
+    HIP_TRY(hipStreamBeginCapture(c.st, hipStreamCaptureModeThreadLocal));
+    const int st = run_stage<T>(m, c, out, ldo);
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(c.st, &g);
+    if (st != FMD_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    if (ec != hipSuccess) return fail(FMD_E_DEVICE, "stage capture failed: %s", hipGetErrorString(ec));
+    const hipError_t ei = hipGraphInstantiate(&m->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) {
+      m->gexec = nullptr;
+      return fail(FMD_E_DEVICE, "graph instantiation failed: %s", hipGetErrorString(ei));
+    }
+    m->gkey = key;
+  }
+  for (int i = 0; i < n_stages; ++i) HIP_TRY(hipGraphLaunch(m->gexec, c.st));
+  return FMD_OK;
+}
+
+// Orders the model's private stream after the caller's stream (call start) and the
+// caller's stream after the private one (call end), keeping calls asynchronous.
+int enter_stream(fmd_model* m, hipStream_t caller, Call& c) {
+  if (!m->pstream) {
+    HIP_TRY(hipStreamCreateWithFlags(&m->pstream, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&m->ev_in, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&m->ev_out, hipEventDisableTiming));
+  }
+  HIP_TRY(hipEventRecord(m->ev_in, caller));
+  HIP_TRY(hipStreamWaitEvent(m->pstream, m->ev_in, 0));
+  c.st = m->pstream;
+  return FMD_OK;
+}
+
+int leave_stream(fmd_model* m, hipStream_t caller) {
+  HIP_TRY(hipEventRecord(m->ev_out, m->pstream));
+  HIP_TRY(hipStreamWaitEvent(caller, m->ev_out, 0));
+  return FMD_OK;
+}
+
+template <typename T>
+int simulate_body(fmd_model* m, const fmd_events_in* truth, const float* x0, uint64_t seed,
+                  const fmd_schedule* sched, fmd_events_out* reco, Call& c) {
   FMD_TRY(stage_events(m, truth, c));
   Workspace& w = m->ws;
+  int n_stages = 0;
+  FMD_TRY(upload_stages(m, c, sched, &n_stages));
   if (x0) {
     const float* src = x0;
     if (!truth->on_device) {
@@ -597,18 +593,10 @@ int simulate_impl(fmd_model* m, const fmd_events_in* truth, const float* x0, uin
   }
   float* out = reco->on_device ? reco->feat : w.io;
   if (m->kind == 0) {
-    if (m->cfg.precision == FMD_BF16) {
-      FMD_TRY(truth_cache<bf16>(m, c));
-      FMD_TRY(autotune<bf16>(m, c));
-      FMD_TRY(integrate<bf16>(m, c, sched, out, 9));
-    } else {
-      FMD_TRY(truth_cache<float>(m, c));
-      FMD_TRY(autotune<float>(m, c));
-      FMD_TRY(integrate<float>(m, c, sched, out, 9));
-    }
-  } else {
-    FMD_TRY(integrate<float>(m, c, sched, out, 9));
+    FMD_TRY(truth_cache<T>(m, c));
+    FMD_TRY(autotune<T>(m, c));
   }
+  FMD_TRY(run_stages<T>(m, c, n_stages, out, 9));
   if (!reco->on_device) {
     HIP_TRY(hipMemcpyAsync(reco->feat, w.io, (size_t)c.T * 9 * 4, hipMemcpyDeviceToHost, c.st));
     HIP_TRY(hipStreamSynchronize(c.st));
@@ -616,7 +604,70 @@ int simulate_impl(fmd_model* m, const fmd_events_in* truth, const float* x0, uin
   return FMD_OK;
 }
 
-}  // namespace
+int simulate_impl(fmd_model* m, const fmd_events_in* truth, const float* x0, uint64_t seed,
+                  const fmd_schedule* sched, fmd_events_out* reco, void* stream) {
+  if (!m) return fail(FMD_E_INVALID, "null model");
+  if (m->server) return fail(FMD_E_STATE, "the model is owned by a server");
+  Call c{};
+  FMD_TRY(check_events(m, truth, &c.T, nullptr));
+  FMD_TRY(check_schedule(sched));
+  if (!reco) return fail(FMD_E_INVALID, "null reco output");
+  if (c.T > 0 && !reco->feat) return fail(FMD_E_INVALID, "null reco feature array");
+  c.E = truth->n_events;
+  if (c.T == 0) return FMD_OK;
+  DeviceGuard guard(m->device);
+  c.Tp = round_up(c.T, kGemmBM);
+  const hipStream_t caller = (hipStream_t)stream;
+  FMD_TRY(enter_stream(m, caller, c));
+  const int st = m->kind == 0 && m->cfg.precision == FMD_BF16
+                     ? simulate_body<bf16>(m, truth, x0, seed, sched, reco, c)
+                     : simulate_body<float>(m, truth, x0, seed, sched, reco, c);
+  const int st2 = leave_stream(m, caller);
+  return st != FMD_OK ? st : st2;
+}
+
+template int truth_cache<float>(fmd_model*, Call&);
+template int truth_cache<bf16>(fmd_model*, Call&);
+template int autotune<float>(fmd_model*, Call&);
+template int autotune<bf16>(fmd_model*, Call&);
+template int net_forward<float>(fmd_model*, Call&, const float*);
+template int net_forward<bf16>(fmd_model*, Call&, const float*);
+
+}  // namespace eng
+}  // namespace fmd
+
+using namespace fmd::eng;
+
+int velocity_body(fmd_model* m, const fmd_events_in* truth, const float* x,
+                  const float* t_per_event, float* v, Call& c) {
+  FMD_TRY(stage_events(m, truth, c));
+  Workspace& w = m->ws;
+  const float* xs = x;
+  const float* tev = t_per_event;
+  if (!truth->on_device) {
+    HIP_TRY(hipMemcpyAsync(w.io, x, (size_t)c.T * 9 * 4, hipMemcpyHostToDevice, c.st));
+    HIP_TRY(hipMemcpyAsync(w.tev, t_per_event, (size_t)c.E * 4, hipMemcpyHostToDevice, c.st));
+    xs = w.io;
+    tev = w.tev;
+  }
+  FMD_TRY(timed(m, c.st, FMD_K_OTHER, 0, [&] { return launch_load_state(c.st, xs, 9, c.T, w.x, w.xs, kStateLd); }));
+  float* out = truth->on_device ? v : w.io;
+  if (m->cfg.precision == FMD_BF16) {
+    FMD_TRY(truth_cache<bf16>(m, c));
+    FMD_TRY(autotune<bf16>(m, c));
+    FMD_TRY(net_forward<bf16>(m, c, tev));
+  } else {
+    FMD_TRY(truth_cache<float>(m, c));
+    FMD_TRY(autotune<float>(m, c));
+    FMD_TRY(net_forward<float>(m, c, tev));
+  }
+  FMD_TRY(head(m, c, true, UPD_VELOCITY, out, 9));
+  if (!truth->on_device) {
+    HIP_TRY(hipMemcpyAsync(v, w.io, (size_t)c.T * 9 * 4, hipMemcpyDeviceToHost, c.st));
+    HIP_TRY(hipStreamSynchronize(c.st));
+  }
+  return FMD_OK;
+}
 
 // =======================================================================================
 // C ABI
@@ -749,6 +800,7 @@ int fmd_linear_field_create(double alpha, double beta, fmd_model** out) {
 
 int fmd_model_destroy(fmd_model* m) {
   if (!m) return FMD_OK;
+  if (m->server) return fail(FMD_E_STATE, "destroy the model's server first");
   if (m->kind == 1 && m->ws.cap_tok == 0 && m->ev_pool.empty() && m->trec.empty()) {
     delete m;   // never touched a device
     return FMD_OK;
@@ -757,6 +809,10 @@ int fmd_model_destroy(fmd_model* m) {
   (void)hipDeviceSynchronize();
   flush_timing(m);
   for (hipEvent_t e : m->ev_pool) (void)hipEventDestroy(e);
+  if (m->gexec) (void)hipGraphExecDestroy(m->gexec);
+  if (m->pstream) (void)hipStreamDestroy(m->pstream);
+  if (m->ev_in) (void)hipEventDestroy(m->ev_in);
+  if (m->ev_out) (void)hipEventDestroy(m->ev_out);
   free_ws(m->ws);
   if (m->params) (void)hipFree(m->params);
   if (m->packed) (void)hipFree(m->packed);
@@ -785,41 +841,19 @@ int fmd_velocity(fmd_model* m, const fmd_events_in* truth, const float* x,
                  const float* t_per_event, float* v, void* hip_stream) {
   if (!m) return fail(FMD_E_INVALID, "null model");
   if (m->kind != 0) return fail(FMD_E_UNSUPPORTED, "fmd_velocity needs a network model");
+  if (m->server) return fail(FMD_E_STATE, "the model is owned by a server");
   Call c{};
-  c.st = (hipStream_t)hip_stream;
   FMD_TRY(check_events(m, truth, &c.T, nullptr));
   c.E = truth->n_events;
   if (c.T == 0) return FMD_OK;
   if (!x || !v || !t_per_event) return fail(FMD_E_INVALID, "null x, v or t_per_event");
   DeviceGuard guard(m->device);
   c.Tp = round_up(c.T, kGemmBM);
-  FMD_TRY(stage_events(m, truth, c));
-  Workspace& w = m->ws;
-  const float* xs = x;
-  const float* tev = t_per_event;
-  if (!truth->on_device) {
-    HIP_TRY(hipMemcpyAsync(w.io, x, (size_t)c.T * 9 * 4, hipMemcpyHostToDevice, c.st));
-    HIP_TRY(hipMemcpyAsync(w.tev, t_per_event, (size_t)c.E * 4, hipMemcpyHostToDevice, c.st));
-    xs = w.io;
-    tev = w.tev;
-  }
-  FMD_TRY(timed(m, c.st, FMD_K_OTHER, 0, [&] { return launch_load_state(c.st, xs, 9, c.T, w.x, w.xs, kStateLd); }));
-  float* out = truth->on_device ? v : w.io;
-  if (m->cfg.precision == FMD_BF16) {
-    FMD_TRY(truth_cache<bf16>(m, c));
-    FMD_TRY(autotune<bf16>(m, c));
-    FMD_TRY(net_forward<bf16>(m, c, tev, 0.f));
-  } else {
-    FMD_TRY(truth_cache<float>(m, c));
-    FMD_TRY(autotune<float>(m, c));
-    FMD_TRY(net_forward<float>(m, c, tev, 0.f));
-  }
-  FMD_TRY(head(m, c, UPD_VELOCITY, 0.f, 0.f, out, 9));
-  if (!truth->on_device) {
-    HIP_TRY(hipMemcpyAsync(v, w.io, (size_t)c.T * 9 * 4, hipMemcpyDeviceToHost, c.st));
-    HIP_TRY(hipStreamSynchronize(c.st));
-  }
-  return FMD_OK;
+  const hipStream_t caller = (hipStream_t)hip_stream;
+  FMD_TRY(enter_stream(m, caller, c));
+  const int st = velocity_body(m, truth, x, t_per_event, v, c);
+  const int st2 = leave_stream(m, caller);
+  return st != FMD_OK ? st : st2;
 }
 
 int fmd_noise(uint64_t seed, const int64_t* offsets, int64_t n_events, int32_t n_feat,
@@ -894,6 +928,12 @@ const char* fmd_kernel_name(fmd_model* m, int32_t cls) {
   static const char* names[FMD_K_COUNT] = {"k_gemm_qkv", "k_gemm_proj", "k_gemm_up", "k_gemm_down",
                                            "k_attn_self", "k_attn_cross", "other"};
   return cls >= 0 && cls < FMD_K_COUNT ? names[cls] : "";
+}
+
+int fmd_graphs_enable(fmd_model* m, int32_t enable) {
+  if (!m) return fail(FMD_E_INVALID, "null model");
+  m->graphs = enable != 0;
+  return FMD_OK;
 }
 
 int fmd_autotune_enable(fmd_model* m, int32_t enable) {

@@ -8,6 +8,7 @@
 
 #include "../../include/fmd.h"
 #include "common.h"
+#include "kernels.h"
 
 namespace fmd {
 
@@ -38,9 +39,26 @@ struct Workspace {
   int32_t* tok_event = nullptr;    // [Tp]
   int64_t* off = nullptr;          // [E + 1]
   int2* work = nullptr;            // attention work list
+  StageDesc* desc = nullptr;       // [stages] stage table of the call
+  int32_t* ctr = nullptr;          // current stage index (device)
   int64_t* h_off = nullptr;        // pinned staging
   int2* h_work = nullptr;
+  StageDesc* h_desc = nullptr;
   int64_t h_cap_ev = 0, h_cap_items = 0;
+  int cap_desc = 0;
+  uint64_t generation = 0;         // bumped whenever a buffer is reallocated
+};
+
+// What a captured stage graph depends on besides buffer contents.
+struct GraphKey {
+  int64_t Tp, T, E, items;
+  const float* out;
+  int ldo;
+  uint64_t ws_gen, tune_gen;
+  bool operator==(const GraphKey& o) const {
+    return Tp == o.Tp && T == o.T && E == o.E && items == o.items && out == o.out &&
+           ldo == o.ldo && ws_gen == o.ws_gen && tune_gen == o.tune_gen;
+  }
 };
 
 // GEMM sites the autotuner chooses a tiling for.
@@ -71,6 +89,13 @@ struct fmd_model {
       *b_out;
   fmd::Workspace ws;
   int autotune = 1;                // 1: time the candidate tilings on first use of a size bucket
+  uint64_t tune_gen = 0;
+  int graphs = 1;                  // 1: capture one ODE stage as a HIP graph and replay it
+  hipStream_t pstream = nullptr;   // private stream of the model (captured, non-blocking)
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  fmd::GraphKey gkey{};
+  fmd_server* server = nullptr;    // attached server (the model's own calls are refused)
   int8_t tune[fmd::TS_COUNT][fmd::kTuneBuckets];   // chosen tiling, -1 = not tuned yet
   float tune_us[fmd::TS_COUNT][fmd::kTuneBuckets]; // its measured time
   bool timing = false;

@@ -1,0 +1,113 @@
+// Internal interfaces of the fmdet engine shared by the sampling calls and the server.
+#pragma once
+
+#include <string>
+
+#include "engine.h"
+#include "kernels.h"
+
+namespace fmd {
+namespace eng {
+
+int fail(int status, const char* fmt, ...);
+
+#define HIP_TRY(expr)                                                                      \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return ::fmd::eng::fail(FMD_E_DEVICE, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), \
+                              __FILE__, __LINE__);                                         \
+  } while (0)
+
+#define FMD_TRY(expr)              \
+  do {                             \
+    int s_ = (expr);               \
+    if (s_ != FMD_OK) return s_;   \
+  } while (0)
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+
+inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+
+
+template <typename P>
+int grow(P*& p, size_t bytes) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+  if (bytes == 0) return FMD_OK;
+  if (hipMalloc((void**)&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    p = nullptr;
+    return fail(FMD_E_NOMEM, "device allocation of %zu bytes failed", bytes);
+  }
+  if (hipMemset(p, 0, bytes) != hipSuccess) return fail(FMD_E_DEVICE, "hipMemset failed");
+  return FMD_OK;
+}
+
+template <typename P>
+int grow_host(P*& p, size_t bytes) {
+  if (p) (void)hipHostFree(p);
+  p = nullptr;
+  if (hipHostMalloc((void**)&p, bytes, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    p = nullptr;
+    return fail(FMD_E_NOMEM, "pinned host allocation of %zu bytes failed", bytes);
+  }
+  return FMD_OK;
+}
+
+
+hipEvent_t take_event(fmd_model* m);
+void flush_timing(fmd_model* m);
+
+template <typename F>
+int timed(fmd_model* m, hipStream_t st, int cls, double work, F&& launch) {
+  hipEvent_t a = nullptr, b = nullptr;
+  if (m->timing) {
+    if (m->trec.size() > 4096) flush_timing(m);
+    a = take_event(m);
+    b = take_event(m);
+    if (a && b) (void)hipEventRecord(a, st);
+  }
+  const hipError_t e = launch();
+  if (e != hipSuccess) return fail(FMD_E_DEVICE, "kernel launch (class %d): %s", cls, hipGetErrorString(e));
+  if (m->timing && a && b) {
+    (void)hipEventRecord(b, st);
+    m->trec.push_back(TimingRec{cls, work, a, b});
+  }
+  return FMD_OK;
+}
+
+
+// One call's (or one server iteration's) shapes and inputs on the device.
+struct Call {
+  hipStream_t st;
+  int64_t E, T, Tp, items;
+  double sum_n2;        // sum over events of N_e^2 (attention work)
+  const float* u;       // truth features on device [T, 9]
+};
+
+
+int ensure_ws(fmd_model* m, int64_t T, int64_t E, int64_t items);
+int check_events(const fmd_model* m, const fmd_events_in* ev, int64_t* T_out, int64_t* max_n);
+int check_schedule(const fmd_schedule* s);
+int row_stats(fmd_model* m, Call& c);
+int enter_stream(fmd_model* m, hipStream_t caller, Call& c);
+int leave_stream(fmd_model* m, hipStream_t caller);
+template <typename T> int truth_cache(fmd_model* m, Call& c);
+template <typename T> int autotune(fmd_model* m, Call& c);
+template <typename T> int net_forward(fmd_model* m, Call& c, const float* t_ev);
+
+}  // namespace eng
+}  // namespace fmd

@@ -230,6 +230,17 @@ __device__ __forceinline__ void gemm_body(const void* __restrict__ A_, int lda,
       }
     }
   } else {
+    int mode = ode.mode;
+    float h = ode.h;
+    float* out = ode.out;
+    if constexpr (EPI == EPI_ODE) {
+      if (ode.desc && !ode.tok_event) {
+        const StageDesc sd = ode.desc[*ode.ctr];
+        mode = sd.mode;
+        h = sd.h;
+        if (!sd.write_out) out = nullptr;
+      }
+    }
 #pragma unroll
     for (int nj = 0; nj < TN; ++nj) {
       const int col = n0 + wn * TL::WTN + nj * 32 + (lane & 31);
@@ -243,8 +254,14 @@ __device__ __forceinline__ void gemm_body(const void* __restrict__ A_, int lda,
           if constexpr (EPI == EPI_ODE) {
             if (col < ode.nf && row < ode.m_valid) {
               const int64_t o = row * ode.ldx + col;
-              ode_update(ode.mode, ode.h, v, ode.x + o, ode.acc + o, ode.xs + o,
-                         ode.out ? ode.out + row * ode.ldo + col : nullptr);
+              if (ode.tok_event) {
+                const StageDesc sd = ode.desc[ode.tok_event[row]];
+                ode_update(sd.mode, sd.h, v, ode.x + o, ode.acc + o, ode.xs + o,
+                           out && sd.write_out ? out + row * ode.ldo + col : nullptr);
+              } else {
+                ode_update(mode, h, v, ode.x + o, ode.acc + o, ode.xs + o,
+                           out ? out + row * ode.ldo + col : nullptr);
+              }
             }
           } else if constexpr (EPI == EPI_GELU) {
             ((T*)C_)[row * ldc + col] = from_f32<T>(gelu_erf(v));

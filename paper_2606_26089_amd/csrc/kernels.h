@@ -18,13 +18,24 @@ enum UpdMode {
   UPD_RK4_1 = 2,      // acc <- acc + 2v ; xs <- x + h/2 v
   UPD_RK4_2 = 3,      // acc <- acc + 2v ; xs <- x + h v
   UPD_RK4_3 = 4,      // x <- x + h/6 (acc + v) ; xs <- x
-  UPD_VELOCITY = 5    // v only, written to `out`
+  UPD_VELOCITY = 5,   // v only, written to `out`
+  UPD_NONE = 6        // no update (rows that belong to no event)
 };
 
 constexpr int kStateLd = 16;       // row stride (floats) of the device ODE state arrays
 
+// One ODE stage of a schedule: evaluation time, step, update mode (UpdMode) and whether
+// this stage writes the caller's output. A call uploads its stages once; a device
+// counter selects the current one, so one captured graph replays every stage.
+struct StageDesc {
+  float t, h;
+  int32_t mode, write_out;
+};
+
 // Fused ODE update in a GEMM epilogue (EPI_ODE): the GEMM result v[r, c] for c < nf and
-// r < m_valid updates state element (r, c) with `mode`; see UpdMode.
+// r < m_valid updates state element (r, c). With desc and tok_event set, mode, h and the
+// output write of row r come from desc[tok_event[r]] (one entry per event: the serving
+// loop); with desc alone from desc[*ctr] (one entry per stage); otherwise from the fields.
 struct OdeArgs {
   float* x;
   float* acc;
@@ -33,6 +44,9 @@ struct OdeArgs {
   int64_t m_valid;
   int ldx, ldo, nf, mode;
   float h;
+  const StageDesc* desc;
+  const int32_t* ctr;
+  const int32_t* tok_event;
 };
 constexpr int kGemmBM = 256;       // largest GEMM row tile; token buffers are padded to this
 
@@ -83,10 +97,16 @@ hipError_t launch_truth_encode(hipStream_t st, const float* u, int ldu, int f, i
                                const float* W, const float* b, const float* g,
                                const float* s, int d, T* c, int ldc);
 
-// temb[e, :] = b_xin + b_time + phi(t_e) W_time for e < n (t_e = t_ev[e] or t_uniform).
-hipError_t launch_time_embed(hipStream_t st, const float* t_ev, float t_uniform, int n,
-                             const float* W_time, const float* b_time, const float* b_xin,
-                             int E_dim, int d, float* temb);
+// temb[e, :] = b_xin + b_time + phi(t_e) W_time for e < n; t_e = t_ev[e] if t_ev is set,
+// else desc[*ctr].t if desc is set, else t_uniform.
+hipError_t launch_time_embed(hipStream_t st, const float* t_ev, const StageDesc* desc,
+                             const int32_t* ctr, float t_uniform, int n, const float* W_time,
+                             const float* b_time, const float* b_xin, int E_dim, int d,
+                             float* temb);
+
+// Stage counter control: *ctr = v, and *ctr += 1 (one thread; the last kernel of a stage).
+hipError_t launch_set_counter(hipStream_t st, int32_t* ctr, int32_t v);
+hipError_t launch_stage_advance(hipStream_t st, int32_t* ctr);
 
 // H[r, :] = temb[tok_event[r] or 0, :] + xs[r, :f] W_xin, with the LayerNorm
 // statistics of every new row written to stats[r].
@@ -94,10 +114,11 @@ hipError_t launch_embed(hipStream_t st, const float* xs, int ldx, int f, int64_t
                         const int32_t* tok_event, const float* temb, const float* W_xin,
                         int d, float* H, int ldh, float2* stats);
 
-// v = (alpha + beta t) xs, then the same ODE update.
-hipError_t launch_linear_update(hipStream_t st, float alpha, float beta, float t, int64_t T,
-                                int f, int mode, float h, float* x, float* acc, float* xs,
-                                int ldx, float* out, int ldo);
+// v = (alpha + beta t) xs, then the same ODE update, with t, h, mode and the output write
+// taken from desc[*ctr].
+hipError_t launch_linear_update(hipStream_t st, float alpha, float beta, const StageDesc* desc,
+                                const int32_t* ctr, int64_t T, int f, float* x, float* acc,
+                                float* xs, int ldx, float* out, int ldo);
 
 // Wt[n, k] = T(W[k, n]) for a [K, N] row-major FP32 matrix.
 template <typename T>

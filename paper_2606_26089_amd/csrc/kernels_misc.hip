@@ -195,13 +195,15 @@ template hipError_t launch_truth_encode<bf16>(hipStream_t, const float*, int, in
 // Time embedding: temb[e, j] = b_xin[j] + b_time[j] + sum_k phi_k(t_e) W_time[k, j] with
 // phi = [sin(w_k t) | cos(w_k t)], w_k = 10000^(-k/(E/2)). One block per event.
 __global__ __launch_bounds__(256) void k_time_embed(const float* __restrict__ t_ev,
+                                                    const StageDesc* __restrict__ desc,
+                                                    const int32_t* __restrict__ ctr,
                                                     float t_uniform, const float* __restrict__ W,
                                                     const float* __restrict__ b_time,
                                                     const float* __restrict__ b_xin, int E_dim,
                                                     int d, float* __restrict__ temb) {
   __shared__ float phi[64];
   const int e = blockIdx.x;
-  const float t = t_ev ? t_ev[e] : t_uniform;
+  const float t = t_ev ? t_ev[e] : desc ? desc[*ctr].t : t_uniform;
   const int half = E_dim >> 1;
   if (threadIdx.x < half) {
     // ln(10000) / half scales the exponent
@@ -219,12 +221,26 @@ __global__ __launch_bounds__(256) void k_time_embed(const float* __restrict__ t_
   }
 }
 
-hipError_t launch_time_embed(hipStream_t st, const float* t_ev, float t_uniform, int n,
-                             const float* W_time, const float* b_time, const float* b_xin,
-                             int E_dim, int d, float* temb) {
+hipError_t launch_time_embed(hipStream_t st, const float* t_ev, const StageDesc* desc,
+                             const int32_t* ctr, float t_uniform, int n, const float* W_time,
+                             const float* b_time, const float* b_xin, int E_dim, int d,
+                             float* temb) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_time_embed, dim3(n), dim3(256), 0, st, t_ev, t_uniform, W_time, b_time,
-                     b_xin, E_dim, d, temb);
+  hipLaunchKernelGGL(k_time_embed, dim3(n), dim3(256), 0, st, t_ev, desc, ctr, t_uniform, W_time,
+                     b_time, b_xin, E_dim, d, temb);
+  return hipGetLastError();
+}
+
+__global__ void k_set_counter(int32_t* ctr, int32_t v) { *ctr = v; }
+__global__ void k_stage_advance(int32_t* ctr) { *ctr += 1; }
+
+hipError_t launch_set_counter(hipStream_t st, int32_t* ctr, int32_t v) {
+  hipLaunchKernelGGL(k_set_counter, dim3(1), dim3(1), 0, st, ctr, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_stage_advance(hipStream_t st, int32_t* ctr) {
+  hipLaunchKernelGGL(k_stage_advance, dim3(1), dim3(1), 0, st, ctr);
   return hipGetLastError();
 }
 
@@ -274,26 +290,29 @@ hipError_t launch_embed(hipStream_t st, const float* xs, int ldx, int f, int64_t
 }
 
 // ---------------------------------------------------------------------------------------
-__global__ void k_linear_update(float alpha, float beta, float t, int64_t T, int f, int mode,
-                                float h, float* __restrict__ x, float* __restrict__ acc,
+__global__ void k_linear_update(float alpha, float beta, const StageDesc* __restrict__ desc,
+                                const int32_t* __restrict__ ctr, int64_t T, int f,
+                                float* __restrict__ x, float* __restrict__ acc,
                                 float* __restrict__ xs, int ldx, float* __restrict__ out,
                                 int ldo) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= T * f) return;
+  const StageDesc sd = desc[*ctr];
   const int64_t r = i / f;
   const int k = (int)(i % f);
   const int64_t o = r * ldx + k;
-  const float v = (alpha + beta * t) * xs[o];
-  ode_update(mode, h, v, x + o, acc + o, xs + o, out ? out + r * ldo + k : nullptr);
+  const float v = (alpha + beta * sd.t) * xs[o];
+  ode_update(sd.mode, sd.h, v, x + o, acc + o, xs + o,
+             out && sd.write_out ? out + r * ldo + k : nullptr);
 }
 
-hipError_t launch_linear_update(hipStream_t st, float alpha, float beta, float t, int64_t T,
-                                int f, int mode, float h, float* x, float* acc, float* xs,
-                                int ldx, float* out, int ldo) {
+hipError_t launch_linear_update(hipStream_t st, float alpha, float beta, const StageDesc* desc,
+                                const int32_t* ctr, int64_t T, int f, float* x, float* acc,
+                                float* xs, int ldx, float* out, int ldo) {
   if (T <= 0) return hipSuccess;
   const int64_t n = T * f;
   hipLaunchKernelGGL(k_linear_update, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, alpha,
-                     beta, t, T, f, mode, h, x, acc, xs, ldx, out, ldo);
+                     beta, desc, ctr, T, f, x, acc, xs, ldx, out, ldo);
   return hipGetLastError();
 }
 

@@ -1,0 +1,470 @@
+// Continuous-batching server for flow-matching sampling requests.
+//
+// Requests (a set of truth events, a seed and a schedule) arrive at any time. A worker
+// thread runs the device loop:
+//   admission  FIFO; a request is admitted when a contiguous range of its token count is
+//              free in the device token pool, whose size is the HBM budget divided by the
+//              per-token footprint. Admission draws the request's noise, encodes its truth
+//              particles and fills its cross-attention K/V cache, all in its pool range.
+//              These stay resident until the request completes.
+//   iteration  one velocity evaluation over the pool prefix that holds resident events.
+//              Every event carries its own stage-table entry (time, step, Euler/RK4 stage),
+//              so requests with different schedules and at different points of their
+//              integration share one launch of each kernel. Gaps between requests are
+//              dummy segments whose rows are never read by a live event and are not
+//              updated.
+//   completion when a request's events finish their last stage, its rows are copied back,
+//              its pool range is released and waiters are woken.
+// An event's noise is keyed by (request seed, event index in the request, slot). GEMM
+// rows are independent and attention stays within an event. So a request's result is
+// bitwise the same alone and in any mix of other requests.
+#include <time.h>
+
+#include <algorithm>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "engine_impl.h"
+#include "gemm_body.h"
+
+using namespace fmd;
+using namespace fmd::eng;
+
+namespace {
+
+uint64_t now_ns() {
+  timespec ts;
+  clock_gettime(CLOCK_MONOTONIC, &ts);
+  return (uint64_t)ts.tv_sec * 1000000000ull + (uint64_t)ts.tv_nsec;
+}
+
+struct Req {
+  uint64_t id = 0;
+  std::vector<int64_t> off;     // [n + 1]
+  std::vector<float> feat;      // [T, 9]
+  uint64_t seed = 0;
+  fmd_schedule sched{};
+  int64_t T = 0, base = -1;     // token count and pool row of its first particle
+  int64_t n_events = 0;
+  int stage = 0, n_stages = 0;  // all events of a request advance together
+  std::vector<float> out;       // [T, 9] result
+  fmd_request_stats stats{};
+  int status = FMD_PENDING;
+  std::string error;
+};
+
+// First-fit allocator of contiguous row ranges with coalescing of freed ranges.
+struct Pool {
+  int64_t cap = 0;
+  std::map<int64_t, int64_t> free_;   // start -> length
+  void init(int64_t c) {
+    cap = c;
+    free_.clear();
+    if (c > 0) free_[0] = c;
+  }
+  int64_t alloc(int64_t n) {
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second < n) continue;
+      const int64_t s = it->first, len = it->second;
+      free_.erase(it);
+      if (len > n) free_[s + n] = len - n;
+      return s;
+    }
+    return -1;
+  }
+  void release(int64_t s, int64_t n) {
+    auto it = free_.emplace(s, n).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+};
+
+constexpr int64_t kPoolSlack = 256;   // rows past the pool so padded GEMM tiles stay inside
+
+}  // namespace
+
+struct fmd_server {
+  fmd_model* m = nullptr;
+  fmd_server_config cfg{};
+  int64_t pool_tokens = 0;
+  size_t bytes_per_token = 0;
+  Pool pool;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<Req*> queue;
+  std::map<uint64_t, Req*> reqs;       // every request not yet collected
+  std::vector<Req*> resident;
+  int64_t resident_tokens = 0;
+  uint64_t next_id = 1;
+  bool stop = false;
+  int dead = FMD_OK;                   // device failure of the worker
+  std::string dead_msg;
+  std::thread worker;
+  hipStream_t st = nullptr;
+  // admission scratch (one request at a time)
+  int64_t* adm_off = nullptr;
+  int32_t* adm_tok = nullptr;
+  int64_t adm_cap_ev = 0, adm_cap_tok = 0;
+  // counters
+  uint64_t iterations = 0, rows_processed = 0, busy_ns = 0;
+};
+
+namespace {
+
+// Device bytes one resident token costs: ODE state, residual stream and LayerNorm
+// statistics, activations, truth features and encoding, cross K/V cache, output.
+size_t bytes_per_token(const fmd_model_config& c) {
+  const size_t d = c.d_model, L = c.n_blocks, es = c.precision == FMD_BF16 ? 2 : 4;
+  return 3 * kStateLd * 4 + d * 4 + sizeof(float2) + 4 + (3 * d + d + d + 4 * d + d) * es +
+         2 * d * L * es + 9 * 4 * 2;
+}
+
+template <typename T>
+int admit_device(fmd_server* S, Req* r) {
+  fmd_model* m = S->m;
+  Workspace& w = m->ws;
+  const int d = m->cfg.d_model, L = m->cfg.n_blocks;
+  const int64_t E = r->n_events, nT = r->T, b = r->base;
+  if (E + 1 > S->adm_cap_ev) {
+    FMD_TRY(grow(S->adm_off, (size_t)(E + 1) * 8));
+    S->adm_cap_ev = E + 1;
+  }
+  if (nT > S->adm_cap_tok) {
+    FMD_TRY(grow(S->adm_tok, (size_t)nT * 4));
+    S->adm_cap_tok = nT;
+  }
+  HIP_TRY(hipMemcpyAsync(S->adm_off, r->off.data(), (size_t)(E + 1) * 8, hipMemcpyHostToDevice, S->st));
+  HIP_TRY(hipMemcpyAsync(w.u + b * 9, r->feat.data(), (size_t)nT * 9 * 4, hipMemcpyHostToDevice, S->st));
+  HIP_TRY(launch_token_map(S->st, S->adm_off, E, nT, S->adm_tok));
+  HIP_TRY(launch_noise(S->st, r->seed, S->adm_off, S->adm_tok, nT, 9, w.x + b * kStateLd,
+                       w.xs + b * kStateLd, kStateLd));
+  const size_t es = sizeof(T);
+  T* cb = (T*)w.c + b * d;
+  HIP_TRY(launch_truth_encode<T>(S->st, w.u + b * 9, 9, 9, nT, m->W_tin, m->b_tin, m->g_t, m->s_t,
+                                 d, cb, d));
+  // K/V cache of the request's rows; padded rows past its end recompute identical values
+  // for neighbours (a pure function of their own truth encoding) or fill unused rows.
+  HIP_TRY(launch_gemm<T>(S->st, FMD_K_OTHER, false, EPI_STORE, round_up(nT, kGemmBM), 2 * d * L, d,
+                         cb, d, (const T*)m->Wkv, m->bkv, nullptr, nullptr, nullptr,
+                         (char*)w.kv + (size_t)b * 2 * d * L * es, 2 * d * L));
+  return FMD_OK;
+}
+
+// One iteration over all resident requests; returns the requests that completed.
+template <typename T>
+int iterate(fmd_server* S, std::vector<Req*>& finished) {
+  fmd_model* m = S->m;
+  Workspace& w = m->ws;
+  std::vector<Req*> res = S->resident;
+  std::sort(res.begin(), res.end(), [](Req* a, Req* b) { return a->base < b->base; });
+  // segments: dummy gaps and real events, in pool order
+  std::vector<int64_t> off{0};
+  std::vector<StageDesc> desc;
+  std::vector<float> tev;
+  std::vector<std::pair<int64_t, int64_t>> real;   // (segment index, length)
+  double sum_n2 = 0;
+  int64_t pos = 0, items = 0;
+  static const double c_rk4[4] = {0.0, 0.5, 0.5, 1.0};
+  for (Req* r : res) {
+    if (r->base > pos) {
+      off.push_back(r->base);
+      desc.push_back(StageDesc{0.f, 0.f, UPD_NONE, 0});
+      tev.push_back(0.f);
+      pos = r->base;
+    }
+    const int Sn = r->sched.scheme == FMD_EULER ? 1 : 4;
+    const int k = r->stage / Sn, st = r->stage % Sn;
+    const double h = (r->sched.t1 - r->sched.t0) / r->sched.n_steps;
+    StageDesc sd;
+    sd.t = (float)(r->sched.t0 + (k + (Sn == 1 ? 0.0 : c_rk4[st])) * h);
+    sd.h = (float)h;
+    sd.mode = Sn == 1 ? UPD_EULER : UPD_RK4_0 + st;
+    sd.write_out = r->stage == r->n_stages - 1;
+    for (int64_t e = 0; e < r->n_events; ++e) {
+      const int64_t n = r->off[e + 1] - r->off[e];
+      if (n == 0) continue;
+      real.emplace_back((int64_t)desc.size(), n);
+      off.push_back(pos + n);
+      desc.push_back(sd);
+      tev.push_back(sd.t);
+      pos += n;
+      items += (n + 63) / 64;
+      sum_n2 += (double)n * (double)n;
+    }
+  }
+  const int64_t E = (int64_t)desc.size(), span = pos;
+  if (span == 0) return FMD_OK;
+  FMD_TRY(ensure_ws(m, span, E, items));
+  std::stable_sort(real.begin(), real.end(),
+                   [](const std::pair<int64_t, int64_t>& a, const std::pair<int64_t, int64_t>& b) {
+                     return a.second > b.second;
+                   });
+  std::memcpy(w.h_off, off.data(), (size_t)(E + 1) * 8);
+  int64_t k = 0;
+  for (auto& pr : real)
+    for (int64_t q = 0; q < (pr.second + 63) / 64; ++q) w.h_work[k++] = make_int2((int)pr.first, (int)q);
+  if (E > w.cap_desc) {
+    FMD_TRY(grow(w.desc, (size_t)E * sizeof(StageDesc)));
+    FMD_TRY(grow_host(w.h_desc, (size_t)E * sizeof(StageDesc)));
+    HIP_TRY(hipDeviceSynchronize());
+    w.cap_desc = (int)E;
+  }
+  std::memcpy(w.h_desc, desc.data(), (size_t)E * sizeof(StageDesc));
+  HIP_TRY(hipMemcpyAsync(w.off, w.h_off, (size_t)(E + 1) * 8, hipMemcpyHostToDevice, S->st));
+  HIP_TRY(hipMemcpyAsync(w.work, w.h_work, (size_t)items * sizeof(int2), hipMemcpyHostToDevice, S->st));
+  HIP_TRY(hipMemcpyAsync(w.desc, w.h_desc, (size_t)E * sizeof(StageDesc), hipMemcpyHostToDevice, S->st));
+  HIP_TRY(hipMemcpyAsync(w.tev, tev.data(), (size_t)E * 4, hipMemcpyHostToDevice, S->st));
+
+  Call c{};
+  c.st = S->st;
+  c.E = E;
+  c.T = span;
+  c.Tp = round_up(span, kGemmBM);
+  c.items = items;
+  c.sum_n2 = sum_n2;
+  c.u = w.u;
+  HIP_TRY(launch_token_map(S->st, w.off, E, span, w.tok_event));
+  FMD_TRY(autotune<T>(m, c));
+  FMD_TRY(net_forward<T>(m, c, w.tev));
+  FMD_TRY(row_stats(m, c));
+  const int d = m->cfg.d_model;
+  const OdeArgs ode{w.x, w.acc, w.xs, w.io, span, kStateLd, 9, 9, 0, 0.f, w.desc, nullptr, w.tok_event};
+  HIP_TRY(launch_gemm<float>(S->st, FMD_K_OTHER, true, EPI_ODE, c.Tp, 64, d, w.H, d, m->Wout_pk,
+                             m->bout_pk, w.stats, m->g_f, m->s_f, nullptr, 0, &ode));
+  for (Req* r : res)
+    if (r->stage == r->n_stages - 1) {
+      HIP_TRY(hipMemcpyAsync(r->out.data(), w.io + r->base * 9, (size_t)r->T * 9 * 4,
+                             hipMemcpyDeviceToHost, S->st));
+      finished.push_back(r);
+    }
+  HIP_TRY(hipStreamSynchronize(S->st));
+  for (Req* r : res) r->stage++;
+  S->iterations++;
+  S->rows_processed += span;
+  return FMD_OK;
+}
+
+void fail_all(fmd_server* S, int status, const std::string& msg) {
+  // caller holds the lock
+  for (auto& kv : S->reqs) {
+    Req* r = kv.second;
+    if (r->status == FMD_PENDING) {
+      r->status = status;
+      r->error = msg;
+      r->stats.t_done_ns = now_ns();
+    }
+  }
+  S->queue.clear();
+  S->resident.clear();
+  S->cv_done.notify_all();
+}
+
+void worker_main(fmd_server* S) {
+  fmd_model* m = S->m;
+  DeviceGuard guard(m->device);
+  const bool bf = m->cfg.precision == FMD_BF16;
+  for (;;) {
+    std::vector<Req*> admitted;
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      S->cv_work.wait(lk, [&] { return S->stop || !S->queue.empty() || !S->resident.empty(); });
+      if (S->stop) {
+        fail_all(S, FMD_E_STATE, "server destroyed before the request completed");
+        return;
+      }
+      while (!S->queue.empty()) {
+        Req* r = S->queue.front();
+        if (S->cfg.max_requests > 0 && (int64_t)S->resident.size() >= S->cfg.max_requests) break;
+        if (S->cfg.max_tokens_per_iter > 0 && !S->resident.empty() &&
+            S->resident_tokens + r->T > S->cfg.max_tokens_per_iter)
+          break;
+        const int64_t b = S->pool.alloc(std::max<int64_t>(r->T, 1));
+        if (b < 0) break;
+        S->queue.pop_front();
+        r->base = b;
+        r->stats.t_admit_ns = now_ns();
+        S->resident.push_back(r);
+        S->resident_tokens += r->T;
+        admitted.push_back(r);
+      }
+    }
+    const uint64_t t0 = now_ns();
+    int st = FMD_OK;
+    for (Req* r : admitted)
+      if (st == FMD_OK) st = bf ? admit_device<bf16>(S, r) : admit_device<float>(S, r);
+    std::vector<Req*> finished;
+    if (st == FMD_OK) st = bf ? iterate<bf16>(S, finished) : iterate<float>(S, finished);
+    S->busy_ns += now_ns() - t0;
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (st != FMD_OK) {
+      S->dead = st;
+      S->dead_msg = fmd_last_error();
+      fail_all(S, st, S->dead_msg);
+      return;
+    }
+    const uint64_t t = now_ns();
+    for (Req* r : finished) {
+      r->status = FMD_OK;
+      r->stats.t_done_ns = t;
+      S->pool.release(r->base, std::max<int64_t>(r->T, 1));
+      S->resident_tokens -= r->T;
+      S->resident.erase(std::find(S->resident.begin(), S->resident.end(), r));
+    }
+    if (!finished.empty()) S->cv_done.notify_all();
+  }
+}
+
+// Copies a finished request out and forgets it (caller holds the lock).
+int collect(fmd_server* S, Req* r, float* reco, fmd_request_stats* stats) {
+  const int status = r->status;
+  if (stats) *stats = r->stats;
+  if (status == FMD_OK && reco && r->T) std::memcpy(reco, r->out.data(), (size_t)r->T * 9 * 4);
+  const std::string err = r->error;
+  S->reqs.erase(r->id);
+  delete r;
+  if (status != FMD_OK) return fail(status, "%s", err.c_str());
+  return FMD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fmd_server_create(fmd_model* m, const fmd_server_config* cfg, fmd_server** out) {
+  if (!m || !cfg || !out) return fail(FMD_E_INVALID, "null argument");
+  if (m->kind != 0) return fail(FMD_E_UNSUPPORTED, "the server needs a network model");
+  if (m->server) return fail(FMD_E_STATE, "the model already has a server");
+  if (cfg->max_requests < 0 || cfg->max_tokens_per_iter < 0)
+    return fail(FMD_E_INVALID, "negative limits");
+  const size_t bpt = bytes_per_token(m->cfg);
+  const int64_t pool = (int64_t)(cfg->hbm_budget_bytes / bpt) - kPoolSlack;
+  if (pool < 1) return fail(FMD_E_BUDGET, "HBM budget below one token (%zu bytes per token)", bpt);
+  DeviceGuard guard(m->device);
+  fmd_server* S = new fmd_server();
+  S->m = m;
+  S->cfg = *cfg;
+  S->pool_tokens = pool;
+  S->bytes_per_token = bpt;
+  S->pool.init(pool);
+  int st = ensure_ws(m, pool + kPoolSlack, 1, 1);
+  if (st == FMD_OK && hipStreamCreateWithFlags(&S->st, hipStreamNonBlocking) != hipSuccess)
+    st = fail(FMD_E_DEVICE, "stream creation failed");
+  if (st != FMD_OK) {
+    if (S->st) (void)hipStreamDestroy(S->st);
+    delete S;
+    return st;
+  }
+  m->server = S;
+  S->worker = std::thread(worker_main, S);
+  *out = S;
+  return FMD_OK;
+}
+
+int fmd_server_submit(fmd_server* S, const fmd_events_in* truth, uint64_t seed,
+                      const fmd_schedule* sched, uint64_t* req_id) {
+  if (!S || !req_id) return fail(FMD_E_INVALID, "null argument");
+  int64_t T = 0;
+  FMD_TRY(check_events(S->m, truth, &T, nullptr));
+  FMD_TRY(check_schedule(sched));
+  if (truth->on_device) return fail(FMD_E_INVALID, "the server takes host event arrays");
+  if (T > S->pool_tokens)
+    return fail(FMD_E_BUDGET, "request of %lld particles exceeds the pool of %lld", (long long)T,
+                (long long)S->pool_tokens);
+  if (S->cfg.max_tokens_per_iter > 0 && T > S->cfg.max_tokens_per_iter)
+    return fail(FMD_E_BUDGET, "request of %lld particles exceeds max_tokens_per_iter", (long long)T);
+  Req* r = new Req();
+  r->off.assign(truth->offsets, truth->offsets + truth->n_events + 1);
+  r->feat.assign(truth->feat, truth->feat + T * 9);
+  r->seed = seed;
+  r->sched = *sched;
+  r->T = T;
+  r->n_events = truth->n_events;
+  r->n_stages = sched->n_steps * (sched->scheme == FMD_EULER ? 1 : 4);
+  r->out.assign((size_t)T * 9, 0.f);
+  r->stats.t_submit_ns = now_ns();
+  std::lock_guard<std::mutex> lk(S->mu);
+  if (S->dead != FMD_OK || S->stop) {
+    delete r;
+    return fail(FMD_E_STATE, "server is not running: %s", S->dead_msg.c_str());
+  }
+  r->id = S->next_id++;
+  S->reqs[r->id] = r;
+  if (T == 0) {        // nothing to integrate
+    r->status = FMD_OK;
+    r->stats.t_admit_ns = r->stats.t_done_ns = r->stats.t_submit_ns;
+  } else {
+    S->queue.push_back(r);
+    S->cv_work.notify_one();
+  }
+  *req_id = r->id;
+  return FMD_OK;
+}
+
+int fmd_server_poll(fmd_server* S, uint64_t req_id, float* reco, fmd_request_stats* stats) {
+  if (!S) return fail(FMD_E_INVALID, "null server");
+  std::lock_guard<std::mutex> lk(S->mu);
+  auto it = S->reqs.find(req_id);
+  if (it == S->reqs.end()) return fail(FMD_E_STATE, "unknown request %llu", (unsigned long long)req_id);
+  if (it->second->status == FMD_PENDING) return FMD_PENDING;
+  return collect(S, it->second, reco, stats);
+}
+
+int fmd_server_wait(fmd_server* S, uint64_t req_id, float* reco, fmd_request_stats* stats) {
+  if (!S) return fail(FMD_E_INVALID, "null server");
+  std::unique_lock<std::mutex> lk(S->mu);
+  auto it = S->reqs.find(req_id);
+  if (it == S->reqs.end()) return fail(FMD_E_STATE, "unknown request %llu", (unsigned long long)req_id);
+  Req* r = it->second;
+  S->cv_done.wait(lk, [&] { return r->status != FMD_PENDING; });
+  return collect(S, r, reco, stats);
+}
+
+int fmd_server_get_info(fmd_server* S, fmd_server_info* info) {
+  if (!S || !info) return fail(FMD_E_INVALID, "null argument");
+  std::lock_guard<std::mutex> lk(S->mu);
+  info->pool_tokens = S->pool_tokens;
+  info->bytes_per_token = (int64_t)S->bytes_per_token;
+  info->queued_requests = (int64_t)S->queue.size();
+  info->resident_requests = (int64_t)S->resident.size();
+  info->resident_tokens = S->resident_tokens;
+  info->iterations = (int64_t)S->iterations;
+  info->rows_processed = (int64_t)S->rows_processed;
+  info->busy_ns = (int64_t)S->busy_ns;
+  return FMD_OK;
+}
+
+int fmd_server_destroy(fmd_server* S) {
+  if (!S) return FMD_OK;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->stop = true;
+  }
+  S->cv_work.notify_all();
+  if (S->worker.joinable()) S->worker.join();
+  DeviceGuard guard(S->m->device);
+  (void)hipStreamSynchronize(S->st);
+  (void)hipStreamDestroy(S->st);
+  if (S->adm_off) (void)hipFree(S->adm_off);
+  if (S->adm_tok) (void)hipFree(S->adm_tok);
+  for (auto& kv : S->reqs) delete kv.second;
+  S->m->server = nullptr;
+  delete S;
+  return FMD_OK;
+}
+
+}  // extern "C"

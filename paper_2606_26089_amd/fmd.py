@@ -46,6 +46,22 @@ class Schedule(ctypes.Structure):
     _fields_ = [("scheme", c_int32), ("n_steps", c_int32), ("t0", c_double), ("t1", c_double)]
 
 
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", c_size_t), ("max_tokens_per_iter", c_int64),
+                ("max_requests", c_int32)]
+
+
+class RequestStats(ctypes.Structure):
+    _fields_ = [("t_submit_ns", ctypes.c_uint64), ("t_admit_ns", ctypes.c_uint64),
+                ("t_done_ns", ctypes.c_uint64)]
+
+
+class ServerInfo(ctypes.Structure):
+    _fields_ = [(n, c_int64) for n in ("pool_tokens", "bytes_per_token", "queued_requests",
+                                        "resident_requests", "resident_tokens", "iterations",
+                                        "rows_processed", "busy_ns")]
+
+
 class FmdError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"fmd status {status}: {msg}")
@@ -88,7 +104,15 @@ def lib():
                                       ctypes.POINTER(c_int64), ctypes.POINTER(c_double)]),
         "fmd_kernel_name": (ctypes.c_char_p, [c_void_p, c_int32]),
         "fmd_autotune_enable": (c_int32, [c_void_p, c_int32]),
+        "fmd_graphs_enable": (c_int32, [c_void_p, c_int32]),
         "fmd_tuning_table": (c_int32, [c_void_p, ctypes.c_char_p, c_size_t, ctypes.POINTER(c_size_t)]),
+        "fmd_server_create": (c_int32, [c_void_p, ctypes.POINTER(ServerConfig), ctypes.POINTER(c_void_p)]),
+        "fmd_server_submit": (c_int32, [c_void_p, ctypes.POINTER(EventsIn), ctypes.c_uint64,
+                                        ctypes.POINTER(Schedule), ctypes.POINTER(ctypes.c_uint64)]),
+        "fmd_server_poll": (c_int32, [c_void_p, ctypes.c_uint64, c_void_p, ctypes.POINTER(RequestStats)]),
+        "fmd_server_wait": (c_int32, [c_void_p, ctypes.c_uint64, c_void_p, ctypes.POINTER(RequestStats)]),
+        "fmd_server_get_info": (c_int32, [c_void_p, ctypes.POINTER(ServerInfo)]),
+        "fmd_server_destroy": (c_int32, [c_void_p]),
         "fmd_debug_gemm": (c_int32, [c_int32, c_int64, c_int32, c_int32, c_void_p, c_void_p,
                                      c_void_p, c_int32, c_void_p, c_void_p, c_int32, c_void_p,
                                      c_int32, c_void_p]),
@@ -252,6 +276,9 @@ class Model:
                                      ctypes.byref(work)))
         return ms.value, n.value, work.value
 
+    def graphs_enable(self, on=True):
+        _check(lib().fmd_graphs_enable(self._h, int(bool(on))))
+
     def autotune_enable(self, on=True):
         _check(lib().fmd_autotune_enable(self._h, int(bool(on))))
 
@@ -265,6 +292,63 @@ class Model:
 
     def kernel_name(self, cls):
         return lib().fmd_kernel_name(self._h, int(cls)).decode()
+
+
+class Server:
+    """Continuous-batching server over a Model (see fmd_server_* in include/fmd.h)."""
+
+    def __init__(self, model, hbm_budget_bytes, max_tokens_per_iter=0, max_requests=0):
+        cfg = ServerConfig(int(hbm_budget_bytes), int(max_tokens_per_iter), int(max_requests))
+        h = c_void_p()
+        _check(lib().fmd_server_create(model._h, ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self.model = model
+        self._sizes = {}
+
+    def submit(self, offsets, feat, seed, sched):
+        feat = np.ascontiguousarray(np.asarray(feat, dtype=np.float32))
+        ev, off = _events(offsets, feat)
+        s = schedule(sched)
+        rid = ctypes.c_uint64()
+        # the library copies the request before returning
+        _check(lib().fmd_server_submit(self._h, ctypes.byref(ev), ctypes.c_uint64(seed),
+                                       ctypes.byref(s), ctypes.byref(rid)))
+        self._sizes[rid.value] = int(off[-1])
+        return rid.value
+
+    def _collect(self, fn, rid):
+        out = np.empty((self._sizes[rid], 9), dtype=np.float32)
+        st = RequestStats()
+        status = fn(self._h, ctypes.c_uint64(rid), c_void_p(out.ctypes.data), ctypes.byref(st))
+        if status == PENDING:
+            return None
+        self._sizes.pop(rid, None)
+        _check(status)
+        return out, {"t_submit_ns": st.t_submit_ns, "t_admit_ns": st.t_admit_ns,
+                     "t_done_ns": st.t_done_ns}
+
+    def poll(self, rid):
+        """(reco, stats) once finished, else None."""
+        return self._collect(lib().fmd_server_poll, rid)
+
+    def wait(self, rid):
+        return self._collect(lib().fmd_server_wait, rid)
+
+    def info(self):
+        i = ServerInfo()
+        _check(lib().fmd_server_get_info(self._h, ctypes.byref(i)))
+        return {n: getattr(i, n) for n, _ in ServerInfo._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().fmd_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def linear_field(alpha, beta):

@@ -124,3 +124,14 @@ def test_binding_refuses_a_missing_library(monkeypatch, fmd):
     monkeypatch.setattr(fmd, "LIB_PATH", "/nonexistent/libfmdet.so")
     with pytest.raises(RuntimeError, match="missing"):
         fmd.lib()
+
+
+def test_server_argument_checks_without_a_device(fmd, field):
+    L = fmd.lib()
+    cfg = fmd.ServerConfig(1 << 30, 0, 0)
+    out = ctypes.c_void_p()
+    assert L.fmd_server_create(None, ctypes.byref(cfg), ctypes.byref(out)) == fmd.E_INVALID
+    assert L.fmd_server_create(field._h, ctypes.byref(cfg), ctypes.byref(out)) == fmd.E_UNSUPPORTED
+    assert L.fmd_server_destroy(None) == fmd.OK
+    rid = ctypes.c_uint64()
+    assert L.fmd_server_submit(None, None, 0, None, ctypes.byref(rid)) == fmd.E_INVALID

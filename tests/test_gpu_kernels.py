@@ -136,7 +136,7 @@ def test_gemm_every_tiling_matches(env, prec, M, N, K, ln, epi):
             continue
         tried += 1
         assert np.array_equal(out, ref), tile
-    assert tried >= 2
+    assert tried >= (1 if N < 128 else 2)
 
 
 ATTN_CASES = [  # (event sizes, heads, dh)

@@ -257,3 +257,39 @@ def test_workspace_regrows_and_shrinks(env):
     for n, (off, feat, out) in outs.items():
         ref = sample.simulate(flat, cfg, off, feat, sched, seed=2)
         assert errors.normwise_rel_err(out, ref).max() < 1e-4
+
+
+def test_graph_replay_equals_eager_launches(env):
+    torch, fmd = env
+    cfg = configs.SMALL_MODEL
+    flat = params.draw(cfg, 2, perturbed=True)
+    off, feat = events.truth_events(12, ("uniform", 1, 60), seed=13)
+    feat_d = dev(torch, feat)
+    for sched in (configs.Schedule(configs.RK4, 3), configs.Schedule(configs.EULER, 5)):
+        m = fmd.Model(cfg, flat)
+        m.graphs_enable(False)
+        eager = m.simulate(off, feat_d, 4, sched).cpu().numpy()
+        m.graphs_enable(True)
+        out1 = torch.empty((off[-1], 9), dtype=torch.float32, device="cuda")
+        g1 = m.simulate(off, feat_d, 4, sched, out=out1).cpu().numpy()       # captures
+        g2 = m.simulate(off, feat_d, 4, sched, out=out1).cpu().numpy()       # replays cached graph
+        g3 = m.simulate(off, feat_d, 4, sched).cpu().numpy()                 # new output: recapture
+        m.close()
+        assert np.array_equal(eager, g1) and np.array_equal(g1, g2) and np.array_equal(g1, g3)
+
+
+def test_graph_cache_follows_new_inputs_of_the_same_shape(env):
+    torch, fmd = env
+    cfg = configs.SMALL_MODEL
+    flat = params.draw(cfg, 2)
+    off, feat = events.truth_events(8, ("uniform", 5, 30), seed=14)
+    feat2 = events.particles(np.random.default_rng(99), int(off[-1]))
+    sched = configs.Schedule(configs.EULER, 3)
+    m = fmd.Model(cfg, flat)
+    out = torch.empty((off[-1], 9), dtype=torch.float32, device="cuda")
+    a = m.simulate(off, dev(torch, feat), 1, sched, out=out).cpu().numpy()
+    b = m.simulate(off, dev(torch, feat2), 1, sched, out=out).cpu().numpy()
+    m.close()
+    ref_b = sample.simulate(flat, cfg, off, feat2, sched, seed=1)
+    assert errors.normwise_rel_err(b, ref_b).max() < 1e-4
+    assert not np.array_equal(a, b)
