@@ -29,6 +29,22 @@ __device__ __forceinline__ float wave_max(float v) {
   return v;
 }
 
+// Transpose-reduction of 32 per-lane values over the 32 lanes of a half wave: afterwards
+// v[0] of lane l holds the sum over the 32 lanes of value (l & 31). 31 exchanges instead of
+// 5 per value: at each step a lane keeps half of its values and adds its partner's copy.
+__device__ __forceinline__ void transpose_reduce32(float (&v)[32], int lane) {
+#pragma unroll
+  for (int m = 16, n = 32; m >= 1; m >>= 1, n >>= 1) {
+    const bool up = (lane & m) != 0;
+#pragma unroll
+    for (int i = 0; i < n / 2; ++i) {
+      const float send = up ? v[i] : v[i + n / 2];
+      const float keep = up ? v[i + n / 2] : v[i];
+      v[i] = keep + __shfl_xor(send, m, kWave);
+    }
+  }
+}
+
 // Workgroups of a 1-D launch are dealt round-robin to the XCDs (block b runs on XCD b % 8).
 // Renumber them so that each XCD owns one contiguous range of logical tiles: neighbouring
 // tiles that share an operand then share that XCD's L2. A bijection on [0, n).

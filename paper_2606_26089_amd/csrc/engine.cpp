@@ -300,6 +300,7 @@ int truth_cache(fmd_model* m, Call& c) {
 
 // LayerNorm statistics of every (padded) row of the residual stream.
 int row_stats(fmd_model* m, Call& c) {
+  if (m->fuse_stats) return FMD_OK;   // the producing residual GEMM wrote them
   Workspace& w = m->ws;
   const int d = m->cfg.d_model;
   return timed(m, c.st, FMD_K_OTHER, 0, [&] { return launch_row_stats(c.st, w.H, d, d, c.Tp, w.stats); });
@@ -311,10 +312,17 @@ int bucket_of(int64_t Tp) {
   return b;
 }
 
+bool full_row_slot(const fmd_model* m, int slot) {
+  return m->fuse_stats && (slot == TS_PROJ_RES || slot == TS_DOWN);
+}
+
 int tile_for(const fmd_model* m, int slot, int64_t Tp, int N) {
   const int t = m->tune[slot][bucket_of(Tp)];
-  return t >= 0 ? t : default_tile(N);
+  if (t >= 0) return t;
+  return full_row_slot(m, slot) ? default_tile_rows(N) : default_tile(N);
 }
+
+int resid_epi(const fmd_model* m) { return m->fuse_stats ? EPI_RESID_LN : EPI_RESID; }
 
 // Launches the GEMM of one tuning slot with a given tiling on the live workspace.
 template <typename T>
@@ -326,8 +334,9 @@ hipError_t slot_gemm(fmd_model* m, Call& c, int slot, int tile, const DevBlock& 
       return launch_gemm<T>(c.st, FMD_K_GEMM_QKV, true, EPI_STORE, c.Tp, 3 * d, d, w.H, d,
                             (const T*)B.Wqkv, B.bqkv, w.stats, B.g1, B.s1, w.qkv, 3 * d, nullptr, tile);
     case TS_PROJ_RES:
-      return launch_gemm<T>(c.st, FMD_K_GEMM_PROJ, false, EPI_RESID, c.Tp, d, d, w.att, d,
-                            (const T*)B.Wo, B.bo, nullptr, nullptr, nullptr, w.H, d, nullptr, tile);
+      return launch_gemm<T>(c.st, FMD_K_GEMM_PROJ, false, resid_epi(m), c.Tp, d, d, w.att, d,
+                            (const T*)B.Wo, B.bo, nullptr, nullptr, nullptr, w.H, d,
+                            m->fuse_stats ? &c.sargs : nullptr, tile);
     case TS_PROJ_LN:
       return launch_gemm<T>(c.st, FMD_K_GEMM_PROJ, true, EPI_STORE, c.Tp, d, d, w.H, d,
                             (const T*)B.Wqc, B.bqc, w.stats, B.g2, B.s2, w.qc, d, nullptr, tile);
@@ -335,8 +344,9 @@ hipError_t slot_gemm(fmd_model* m, Call& c, int slot, int tile, const DevBlock& 
       return launch_gemm<T>(c.st, FMD_K_GEMM_UP, true, EPI_GELU, c.Tp, 4 * d, d, w.H, d,
                             (const T*)B.Wup, B.bup, w.stats, B.g3, B.s3, w.hid, 4 * d, nullptr, tile);
     default:
-      return launch_gemm<T>(c.st, FMD_K_GEMM_DOWN, false, EPI_RESID, c.Tp, d, 4 * d, w.hid, 4 * d,
-                            (const T*)B.Wdn, B.bdn, nullptr, nullptr, nullptr, w.H, d, nullptr, tile);
+      return launch_gemm<T>(c.st, FMD_K_GEMM_DOWN, false, resid_epi(m), c.Tp, d, 4 * d, w.hid, 4 * d,
+                            (const T*)B.Wdn, B.bdn, nullptr, nullptr, nullptr, w.H, d,
+                            m->fuse_stats ? &c.sargs : nullptr, tile);
   }
 }
 
@@ -356,6 +366,8 @@ int autotune(fmd_model* m, Call& c) {
   bool any = false;
   for (int sl = 0; sl < TS_COUNT; ++sl) any |= m->tune[sl][b] < 0;
   if (!any) return FMD_OK;
+  c.sargs = OdeArgs{};
+  c.sargs.stats_out = m->ws.stats;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
@@ -365,7 +377,7 @@ int autotune(fmd_model* m, Call& c) {
     int best = -1;
     float best_us = 0.f;
     for (int t = 0; t < kGemmTiles; ++t) {
-      if (!tile_fits(t, c.Tp, N[sl], K[sl])) continue;
+      if (!tile_fits(t, c.Tp, N[sl], K[sl], full_row_slot(m, sl))) continue;
       if (slot_gemm<T>(m, c, sl, t, m->blk[0]) != hipSuccess) {
         (void)hipGetLastError();
         continue;
@@ -384,7 +396,8 @@ int autotune(fmd_model* m, Call& c) {
       if (status != FMD_OK) break;
       if (best < 0 || run_best < best_us) best = t, best_us = run_best;
     }
-    m->tune[sl][b] = (int8_t)(best >= 0 ? best : default_tile(N[sl]));
+    m->tune[sl][b] = (int8_t)(best >= 0 ? best : full_row_slot(m, sl) ? default_tile_rows(N[sl])
+                                                               : default_tile(N[sl]));
     m->tune_us[sl][b] = best_us;
     m->tune_gen++;
   }
@@ -404,6 +417,8 @@ int net_forward(fmd_model* m, Call& c, const float* t_ev) {
   const size_t es = sizeof(T);
   char* qkv = (char*)w.qkv;
   char* kv = (char*)w.kv;
+  c.sargs = OdeArgs{};
+  c.sargs.stats_out = w.stats;
   FMD_TRY(timed(m, c.st, FMD_K_OTHER, 0, [&] {
     return launch_time_embed(c.st, t_ev, t_ev ? nullptr : w.desc, w.ctr, 0.f, t_ev ? (int)c.E : 1,
                              m->W_time, m->b_time, m->b_xin, cf.t_embed_dim, d, w.temb);
@@ -426,9 +441,9 @@ int net_forward(fmd_model* m, Call& c, const float* t_ev) {
                                  (T*)w.att, d, w.off, w.off);
     }));
     FMD_TRY(timed(m, c.st, FMD_K_GEMM_PROJ, 2.0 * Td * d * d, [&] {
-      return launch_gemm<T>(c.st, FMD_K_GEMM_PROJ, false, EPI_RESID, c.Tp, d, d, w.att, d,
-                            (const T*)B.Wo, B.bo, nullptr, nullptr, nullptr, w.H, d, nullptr,
-                            tile_for(m, TS_PROJ_RES, c.Tp, d));
+      return launch_gemm<T>(c.st, FMD_K_GEMM_PROJ, false, resid_epi(m), c.Tp, d, d, w.att, d,
+                            (const T*)B.Wo, B.bo, nullptr, nullptr, nullptr, w.H, d,
+                            m->fuse_stats ? &c.sargs : nullptr, tile_for(m, TS_PROJ_RES, c.Tp, d));
     }));
     FMD_TRY(row_stats(m, c));
     FMD_TRY(timed(m, c.st, FMD_K_GEMM_PROJ, 2.0 * Td * d * d, [&] {
@@ -443,9 +458,9 @@ int net_forward(fmd_model* m, Call& c, const float* t_ev) {
                                  (T*)w.att, d, w.off, w.off);
     }));
     FMD_TRY(timed(m, c.st, FMD_K_GEMM_PROJ, 2.0 * Td * d * d, [&] {
-      return launch_gemm<T>(c.st, FMD_K_GEMM_PROJ, false, EPI_RESID, c.Tp, d, d, w.att, d,
-                            (const T*)B.Woc, B.boc, nullptr, nullptr, nullptr, w.H, d, nullptr,
-                            tile_for(m, TS_PROJ_RES, c.Tp, d));
+      return launch_gemm<T>(c.st, FMD_K_GEMM_PROJ, false, resid_epi(m), c.Tp, d, d, w.att, d,
+                            (const T*)B.Woc, B.boc, nullptr, nullptr, nullptr, w.H, d,
+                            m->fuse_stats ? &c.sargs : nullptr, tile_for(m, TS_PROJ_RES, c.Tp, d));
     }));
     FMD_TRY(row_stats(m, c));
     FMD_TRY(timed(m, c.st, FMD_K_GEMM_UP, 2.0 * Td * d * 4 * d, [&] {
@@ -454,9 +469,9 @@ int net_forward(fmd_model* m, Call& c, const float* t_ev) {
                             tile_for(m, TS_UP, c.Tp, 4 * d));
     }));
     FMD_TRY(timed(m, c.st, FMD_K_GEMM_DOWN, 2.0 * Td * 4 * d * d, [&] {
-      return launch_gemm<T>(c.st, FMD_K_GEMM_DOWN, false, EPI_RESID, c.Tp, d, 4 * d, w.hid,
-                            4 * d, (const T*)B.Wdn, B.bdn, nullptr, nullptr, nullptr, w.H, d, nullptr,
-                            tile_for(m, TS_DOWN, c.Tp, d));
+      return launch_gemm<T>(c.st, FMD_K_GEMM_DOWN, false, resid_epi(m), c.Tp, d, 4 * d, w.hid,
+                            4 * d, (const T*)B.Wdn, B.bdn, nullptr, nullptr, nullptr, w.H, d,
+                            m->fuse_stats ? &c.sargs : nullptr, tile_for(m, TS_DOWN, c.Tp, d));
     }));
   }
   return FMD_OK;
@@ -691,6 +706,7 @@ int fmd_model_create(const fmd_model_config* cfg, const float* params, size_t n_
   fmd_model* m = new fmd_model();
   m->cfg = *cfg;
   std::memset(m->tune, -1, sizeof(m->tune));
+  m->fuse_stats = default_tile_rows(cfg->d_model) >= 0;
   std::memset(m->tune_us, 0, sizeof(m->tune_us));
   auto bail = [&](int s) {
     fmd_model_destroy(m);

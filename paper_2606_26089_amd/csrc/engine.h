@@ -88,6 +88,7 @@ struct fmd_model {
   const float *W_tin, *b_tin, *g_t, *s_t, *W_xin, *b_xin, *W_time, *b_time, *g_f, *s_f, *W_out,
       *b_out;
   fmd::Workspace ws;
+  bool fuse_stats = false;         // residual GEMMs emit the next LayerNorm's row statistics
   int autotune = 1;                // 1: time the candidate tilings on first use of a size bucket
   uint64_t tune_gen = 0;
   int graphs = 1;                  // 1: capture one ODE stage as a HIP graph and replay it

@@ -96,6 +96,7 @@ struct Call {
   int64_t E, T, Tp, items;
   double sum_n2;        // sum over events of N_e^2 (attention work)
   const float* u;       // truth features on device [T, 9]
+  OdeArgs sargs;        // epilogue arguments of the residual GEMMs (statistics output)
 };
 
 

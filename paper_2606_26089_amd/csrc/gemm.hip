@@ -13,7 +13,8 @@ hipError_t launch_gemm(hipStream_t st, int cls, bool ln, int epi, int64_t Mp, in
                        const OdeArgs* ode, int tile) {
   if (Mp % kGemmBM || K % 32 || N % 64) return hipErrorInvalidValue;
   if (ln && !stats) return hipErrorInvalidValue;
-  if ((epi == EPI_ODE) != (ode != nullptr)) return hipErrorInvalidValue;
+  if ((epi == EPI_ODE || epi == EPI_RESID_LN) != (ode != nullptr)) return hipErrorInvalidValue;
+  if (epi == EPI_RESID_LN && !ode->stats_out) return hipErrorInvalidValue;
   const OdeArgs none{};
   const OdeArgs& oa = ode ? *ode : none;
   if (tile < 0) tile = default_tile(N);
@@ -21,10 +22,17 @@ hipError_t launch_gemm(hipStream_t st, int cls, bool ln, int epi, int64_t Mp, in
                              ldc, oa);
 }
 
-bool tile_fits(int tile, int64_t Mp, int N, int K) {
+bool tile_fits(int tile, int64_t Mp, int N, int K, bool full_rows) {
   if (tile < 0 || tile >= kNumTiles) return false;
   const TileDims t = tile_dims(tile);
+  if (full_rows && (N != t.BN || t.TM % 2)) return false;
   return Mp % t.BM == 0 && N % t.BN == 0 && K % t.BK == 0;
+}
+
+int default_tile_rows(int N) {
+  for (int t = 0; t < kNumTiles; ++t)
+    if (tile_dims(t).BN == N && tile_dims(t).TM % 2 == 0) return t;
+  return -1;
 }
 
 // LayerNorm row statistics: one wave per row, the row held in registers for two passes.

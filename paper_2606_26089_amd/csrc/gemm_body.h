@@ -203,8 +203,9 @@ __device__ __forceinline__ void gemm_body(const void* __restrict__ A_, int lda,
 #undef FMD_STORE_TILES
 
   // epilogue
-  if constexpr (EPI == EPI_RESID) {
-    // per 32-row block, read the residual values first: the stores may alias later loads
+  if constexpr (EPI == EPI_RESID || EPI == EPI_RESID_LN) {
+    // per 32-row block, read the residual values first: the stores may alias later loads;
+    // the new values stay in acc for the statistics below
     float* C = (float*)C_;
 #pragma unroll
     for (int mi = 0; mi < TM; ++mi) {
@@ -225,8 +226,62 @@ __device__ __forceinline__ void gemm_body(const void* __restrict__ A_, int lda,
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
           const int64_t row = m0 + wm * TL::WTM + mi * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
-          C[row * ldc + col] = old[nj][r] + (acc[mi][nj][r] + bv);
+          const float nv = old[nj][r] + (acc[mi][nj][r] + bv);
+          acc[mi][nj][r] = nv;
+          C[row * ldc + col] = nv;
         }
+      }
+    }
+    if constexpr (EPI == EPI_RESID_LN) {
+      // LayerNorm statistics of the block's full rows (BN == N): per-wave partial sums by a
+      // transpose-reduction over the lanes, then across the WN column waves through LDS;
+      // two passes (mean, then squared deviations).
+      static_assert(TM % 2 == 0, "row statistics take 32-row groups per lane half");
+      __shared__ float red[TL::WN][BM];
+      __shared__ float srow[BM];
+      const int nn = n_tiles * BN;   // = N: the launcher checks n_tiles == 1
+      // row (within the block) of transposed slot j of group g for this lane
+      auto row_of = [&](int g, int j) {
+        const int mi = 2 * g + (j >> 4), r = j & 15;
+        return wm * TL::WTM + mi * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+      };
+#pragma unroll
+      for (int pass = 0; pass < 2; ++pass) {
+#pragma unroll
+        for (int g = 0; g < TM / 2; ++g) {
+          float v[32];
+#pragma unroll
+          for (int j = 0; j < 32; ++j) {
+            const int mi = 2 * g + (j >> 4), r = j & 15;
+            float s = 0.f;
+            if (pass == 0) {
+#pragma unroll
+              for (int nj = 0; nj < TN; ++nj) s += acc[mi][nj][r];
+            } else {
+              const float mu = srow[row_of(g, j)];
+#pragma unroll
+              for (int nj = 0; nj < TN; ++nj) {
+                const float dv = acc[mi][nj][r] - mu;
+                s = fmaf(dv, dv, s);
+              }
+            }
+            v[j] = s;
+          }
+          transpose_reduce32(v, lane);
+          red[wn][row_of(g, lane & 31)] = v[0];
+        }
+        __syncthreads();
+        for (int i = tid; i < BM; i += NT) {
+          float t = 0.f;
+#pragma unroll
+          for (int q = 0; q < TL::WN; ++q) t += red[q][i];
+          if (pass == 0) {
+            srow[i] = t / nn;
+          } else {
+            ode.stats_out[m0 + i] = make_float2(srow[i], rsqrtf(t / nn + kLnEps));
+          }
+        }
+        __syncthreads();
       }
     }
   } else {
@@ -285,12 +340,12 @@ __device__ __forceinline__ void gemm_body(const void* __restrict__ A_, int lda,
   X(6, 256, 256, 32, 2, 2)
 constexpr int kNumTiles = 7;
 
-struct TileDims { int BM, BN, BK, threads; };
+struct TileDims { int BM, BN, BK, threads, TM; };   // TM: 32-row blocks per wave
 __host__ __device__ constexpr TileDims tile_dims(int id) {
-  return id == 0 ? TileDims{128, 128, 32, 256} : id == 1 ? TileDims{128, 128, 64, 256}
-       : id == 2 ? TileDims{256, 128, 32, 512} : id == 3 ? TileDims{128, 256, 32, 512}
-       : id == 4 ? TileDims{128, 64, 32, 256}  : id == 5 ? TileDims{128, 128, 32, 128}
-       : TileDims{256, 256, 32, 256};
+  return id == 0 ? TileDims{128, 128, 32, 256, 2} : id == 1 ? TileDims{128, 128, 64, 256, 2}
+       : id == 2 ? TileDims{256, 128, 32, 512, 2} : id == 3 ? TileDims{128, 256, 32, 512, 2}
+       : id == 4 ? TileDims{128, 64, 32, 256, 2}  : id == 5 ? TileDims{128, 128, 32, 128, 4}
+       : TileDims{256, 256, 32, 256, 4};
 }
 
 // Per-T launcher over (class, LN, epilogue, tile); defined in gemm_f32.hip / gemm_bf16.hip.

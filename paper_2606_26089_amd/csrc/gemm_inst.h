@@ -56,12 +56,16 @@ static hipError_t dispatch_cls(hipStream_t st, int cls, bool ln, int epi, int64_
     case FMD_K_GEMM_PROJ:
       if (ln && epi == EPI_STORE) FMD_GO(k_gemm_proj, true, EPI_STORE);
       if (!ln && epi == EPI_RESID) FMD_GO(k_gemm_proj, false, EPI_RESID);
+      if constexpr (TL::TM % 2 == 0)
+        if (!ln && epi == EPI_RESID_LN) FMD_GO(k_gemm_proj, false, EPI_RESID_LN);
       break;
     case FMD_K_GEMM_UP:
       if (ln && epi == EPI_GELU) FMD_GO(k_gemm_up, true, EPI_GELU);
       break;
     case FMD_K_GEMM_DOWN:
       if (!ln && epi == EPI_RESID) FMD_GO(k_gemm_down, false, EPI_RESID);
+      if constexpr (TL::TM % 2 == 0)
+        if (!ln && epi == EPI_RESID_LN) FMD_GO(k_gemm_down, false, EPI_RESID_LN);
       break;
     default:
       if constexpr (ID == 0 || ID == 4) {
@@ -94,6 +98,7 @@ hipError_t launch_gemm_tile<FMD_GEMM_T>(hipStream_t st, int tile, int cls, bool 
 #define FMD_TILE_CASE(ID, BM_, BN_, BK_, WM_, WN_)                                             \
   case ID:                                                                                   \
     if (Mp % BM_ || N % BN_ || K % BK_) return hipErrorInvalidValue;                         \
+    if (epi == EPI_RESID_LN && N != BN_) return hipErrorInvalidValue;                        \
     return dispatch_cls<FMD_GEMM_T, ID, Tile<BM_, BN_, BK_, WM_, WN_>>(                      \
         st, cls, ln, epi, Mp, N, K, A, lda, Wt, bias, stats, g, s, C, ldc, ode);
     FMD_GEMM_TILES(FMD_TILE_CASE)

@@ -9,7 +9,9 @@
 
 namespace fmd {
 
-enum Epi { EPI_STORE = 0, EPI_GELU = 1, EPI_RESID = 2, EPI_ODE = 3 };
+// EPI_RESID_LN: EPI_RESID plus the LayerNorm statistics of every updated row, written to
+// OdeArgs::stats_out (needs one block per full row: tile BN == N).
+enum Epi { EPI_STORE = 0, EPI_GELU = 1, EPI_RESID = 2, EPI_ODE = 3, EPI_RESID_LN = 4 };
 
 // ODE update modes of the fused head kernel.
 enum UpdMode {
@@ -47,6 +49,7 @@ struct OdeArgs {
   const StageDesc* desc;
   const int32_t* ctr;
   const int32_t* tok_event;
+  float2* stats_out;   // EPI_RESID_LN only
 };
 constexpr int kGemmBM = 256;       // largest GEMM row tile; token buffers are padded to this
 
@@ -65,8 +68,10 @@ hipError_t launch_gemm(hipStream_t st, int cls, bool ln, int epi, int64_t Mp, in
 
 // Candidate GEMM tilings the autotuner chooses from, and whether one divides a shape.
 constexpr int kGemmTiles = 7;
-bool tile_fits(int tile, int64_t Mp, int N, int K);
+// full_rows: the tiling must give one block the whole row (BN == N), as EPI_RESID_LN needs.
+bool tile_fits(int tile, int64_t Mp, int N, int K, bool full_rows = false);
 int default_tile(int N);
+int default_tile_rows(int N);   // a full-row tiling for N, or -1
 
 // LayerNorm statistics of the rows of a float [M, ld] matrix over its first K columns:
 // stats[r] = (mean, 1/sqrt(biased var + eps)), two passes in registers, one wave per row.
