@@ -50,14 +50,26 @@ def time_path(fmd, torch, cfg, flat, off, feat_d, w, steps, warmup, timing):
     kern = {}
     if timing:
         for cls, name in enumerate(fmd.KERNEL_CLASSES):
-            ms, n, work = m.timing_read(cls)
-            kern[name] = {"ms": ms, "launches": n, "work": work, "kernel": m.kernel_name(cls)}
+            ms, n, work, nbytes = m.timing_read(cls)
+            kern[name] = {"ms": ms, "launches": n, "work": work, "bytes": nbytes,
+                          "kernel": m.kernel_name(cls)}
         m.timing_enable(False)
-    tiles = {e["site"]: f"{e['BM']}x{e['BN']}x{e['BK']}/{e['threads']}t"
-             for e in m.tuning_table()["entries"]}
+    table = m.tuning_table()["entries"]
+    for e in table:
+        log(f"  autotune {e['site']:14s} 2^{e['tokens_log2']} tokens: tile {e['tile']} "
+            f"({e['BM']}x{e['BN']}x{e['BK']}, {e['threads']} threads) {e['us']:.0f} us; "
+            f"candidates {e['candidates_us']}")
+    tiles = {e["site"]: f"{e['BM']}x{e['BN']}x{e['BK']}/{e['threads']}t" for e in table}
     kern["_tiles"] = tiles
     m.close()
     return dt, out.cpu().numpy(), kern
+
+
+def bound_of(k, dtype):
+    """The resource that bounds a kernel class at its algorithmic FLOPs and bytes: the one
+    whose peak takes longer to serve them."""
+    return "hbm" if k["bytes"] / (PEAK_HBM_GBS * 1e9) > k["work"] / (PEAK_TFLOPS[dtype] * 1e12) \
+        else "mfma"
 
 
 def roofline(kern, dtype):
@@ -66,13 +78,19 @@ def roofline(kern, dtype):
     name, k = max(gemm_attn.items(), key=lambda kv: kv[1]["ms"])
     avg_s = k["ms"] / k["launches"] * 1e-3
     flops = k["work"] / k["launches"]
-    achieved = flops / avg_s / 1e12
-    peak = PEAK_TFLOPS[dtype]
+    nbytes = k["bytes"] / k["launches"]
     total_ms = sum(v["ms"] for k_, v in kern.items() if not k_.startswith("_"))
-    return {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
+    bound = bound_of(k, dtype)
+    if bound == "hbm":
+        achieved, peak, unit = nbytes / avg_s / 1e9, PEAK_HBM_GBS, "GB/s"
+    else:
+        achieved, peak, unit = flops / avg_s / 1e12, PEAK_TFLOPS[dtype], "TFLOP/s"
+    return {"bound": bound, "achieved": round(achieved, 2), "peak": peak, "unit": unit,
             "frac": round(achieved / peak, 4), "traffic": None, "kernel": k["kernel"],
             "class": name, "avg_launch_ms": round(k["ms"] / k["launches"], 4),
-            "flop_per_launch": flops, "share_of_device_time": round(k["ms"] / total_ms, 3)}
+            "flop_per_launch": flops, "bytes_per_launch": nbytes,
+            "tflops": round(flops / avg_s / 1e12, 2), "gbps": round(nbytes / avg_s / 1e9, 1),
+            "share_of_device_time": round(k["ms"] / total_ms, 3)}
 
 
 def cpu_baseline(w, flat, off, feat, sample_events, processes):
@@ -159,6 +177,9 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-rates", default="1000,2000,5000")
     ap.add_argument("--serve-seconds", type=float, default=4.0)
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="first run a plain device-to-device copy of this many MiB three times "
+                         "(reference kernel of known traffic for HBM byte counters)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {a.gpus}): events are independent and "
@@ -170,6 +191,15 @@ def main():
 
     from paper_2606_26089_amd import fmd
     from workload import configs, errors, events, params
+
+    if a.copy_mib:
+        src = torch.ones(a.copy_mib << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copied {a.copy_mib} MiB three times")
+        del src, dst
 
     w = configs.BASE_BF16
     off, feat = events.for_workload(w)
@@ -187,7 +217,8 @@ def main():
         if name.startswith("_"):
             continue
         log(f"  {name:11s} {k['kernel']:14s} {k['ms'] / a.steps:9.1f} ms/step  {k['launches'] // a.steps:5d} "
-            f"launches/step  {k['work'] / max(k['ms'], 1e-9) / 1e9:8.1f} TFLOP/s")
+            f"launches/step  {k['work'] / max(k['ms'], 1e-9) / 1e9:8.1f} TFLOP/s "
+            f"{k['bytes'] / max(k['ms'], 1e-9) / 1e6:8.1f} GB/s  ({bound_of(k, 'bf16')}-bound)")
     rl = roofline(kern16, "bf16")
     log(f"dominant kernel {rl['kernel']}: {rl['achieved']} TFLOP/s ({rl['frac']:.3f} of peak)")
 

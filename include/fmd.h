@@ -171,19 +171,27 @@ int fmd_debug_philox(uint64_t key0, uint64_t key1, const uint64_t* counters, int
 /* ---- instrumentation ----------------------------------------------------------------- */
 
 /* Kernel classes timed by HIP events on the launch stream when timing is on. */
-enum { FMD_K_GEMM_QKV = 0, FMD_K_GEMM_PROJ = 1, FMD_K_GEMM_UP = 2, FMD_K_GEMM_DOWN = 3,
-       FMD_K_ATTN_SELF = 4, FMD_K_ATTN_CROSS = 5, FMD_K_OTHER = 6, FMD_K_COUNT = 7 };
+/* QKV: LN1 + [Q|K|V] projection (a GEMM, or the fused kernel); PROJ: self- and
+ * cross-attention output projections with the residual update; QC: LN2 + cross-attention
+ * query projection; UP: LN3 + MLP up + GELU; DOWN: MLP down with the residual update;
+ * FUSED_OQC: the fused kernel for PROJ (self) + QC; FUSED_MLP: the fused kernel for
+ * PROJ (cross) + UP + DOWN; OTHER: everything else (embedding, head with the state update,
+ * statistics, noise, truth encoding, bookkeeping). */
+enum { FMD_K_GEMM_QKV = 0, FMD_K_GEMM_PROJ = 1, FMD_K_GEMM_QC = 2, FMD_K_GEMM_UP = 3,
+       FMD_K_GEMM_DOWN = 4, FMD_K_FUSED_OQC = 5, FMD_K_FUSED_MLP = 6, FMD_K_ATTN_SELF = 7,
+       FMD_K_ATTN_CROSS = 8, FMD_K_OTHER = 9, FMD_K_COUNT = 10 };
 
 /* Turns on (1) or off (0) per-launch timing of the kernel classes above and clears the
  * counters. Timing brackets each launch with events and adds a little host overhead. */
 int fmd_timing_enable(fmd_model* m, int32_t enable);
 
-/* Reads the counters of one class: total device milliseconds, number of launches, and
- * algorithmic work. The work counts the FLOPs of the method, excluding padding and
- * recomputation, or the minimal HBM bytes for HBM-bound kernels.
+/* Reads the counters of one class: total device milliseconds, number of launches, and the
+ * algorithmic work summed over those launches: `flops` counts the method's floating-point
+ * operations (no padding rows, no recomputation), `bytes` the HBM traffic of reading every
+ * operand and writing every result exactly once. Any output pointer may be NULL.
  * Synchronises the device. */
 int fmd_timing_read(fmd_model* m, int32_t kernel_class, double* total_ms, int64_t* launches,
-                    double* work);
+                    double* flops, double* bytes);
 
 /* Name of the HIP kernel behind a class, as rocprofv3 reports it (static string). */
 const char* fmd_kernel_name(fmd_model* m, int32_t kernel_class);
@@ -197,6 +205,21 @@ const char* fmd_kernel_name(fmd_model* m, int32_t kernel_class);
  * the graph without re-capturing it. With timing on, or with graphs disabled, the same
  * kernels are launched one by one. Results are identical either way. */
 int fmd_graphs_enable(fmd_model* m, int32_t enable);
+
+/* Fused block kernels (BF16 models with d_model 256 and MLP ratio 4; on by default there).
+ * Each transformer block then runs as three matrix-core kernels around the two attention
+ * kernels: LN1 + QKV; the self-attention output projection with the residual update, LN2
+ * and the cross-attention query; the cross-attention output projection with the residual
+ * update, LN3 and the whole MLP with its residual update. Every 128-row tile keeps its FP32
+ * residual rows in registers and its LayerNorm / hidden activations in LDS, so the MLP
+ * hidden layer never reaches device memory. Results agree with the unfused kernels to BF16
+ * rounding, not bitwise (different summation order and LayerNorm statistics computed in
+ * the kernel). `mask` selects the segments that use their fused kernel (FMD_FUSED_*; the
+ * others run the GEMM kernels); 0 selects the GEMM kernels throughout. A mask outside
+ * [0, FMD_FUSED_ALL] is FMD_E_INVALID; a nonzero mask on a model without the fused kernels
+ * is FMD_E_UNSUPPORTED. */
+enum { FMD_FUSED_QKV = 1, FMD_FUSED_OQC = 2, FMD_FUSED_MLP = 4, FMD_FUSED_ALL = 7 };
+int fmd_fused_enable(fmd_model* m, int32_t mask);
 
 /* ---- tile autotuner ------------------------------------------------------------------- */
 

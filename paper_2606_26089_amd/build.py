@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libfmdet.so")
 
-SOURCES = ["gemm_bf16.hip", "gemm_f32.hip", "kernels_misc.hip", "gemm.hip", "attention.hip",
+SOURCES = ["gemm_bf16.hip", "gemm_f32.hip", "kernels_misc.hip", "gemm.hip", "attention.hip", "block_bf16.hip",
            "engine.cpp", "server.cpp"]
 HEADERS = ["common.h", "kernels.h", "engine.h", "engine_impl.h", "gemm_body.h", "gemm_inst.h",
            os.path.join("..", "..", "include", "fmd.h")]

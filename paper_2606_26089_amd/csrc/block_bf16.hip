@@ -1,0 +1,464 @@
+// Fused BF16 kernels of one transformer block of the velocity network (Sec. 3, the
+// pre-LayerNorm block: self-attention, cross-attention to the truth encoding, 4x GELU MLP),
+// written for model width d = 256 on gfx950.
+//
+// Every kernel works on 128 token rows with 8 waves. The rows' FP32 residual values live in
+// registers for the whole kernel, as a full-width accumulator: wave w holds columns
+// [32w, 32w + 32) of all 128 rows, in the 32x32 MFMA output layout (lane l, register r of
+// fragment mi: row 32 mi + 8 (r/4) + 4 (l/32) + r%4, column l%32). The A operands of the
+// products (an attention output tile, the LayerNorm of the residual rows, an MLP hidden
+// chunk) sit in LDS; the weights stream from L2 as pre-packed MFMA B fragments, 8 in flight
+// per wave, with no LDS staging and no barriers. LayerNorm statistics are computed inside
+// the kernel from the full rows (two passes: mean, then squared deviations).
+//
+//   k_fused_qkv  LN1(H) -> [Q|K|V]
+//   k_fused_oqc  H += att W_o + b_o;  qc = LN2(H) W_qc + b_qc
+//   k_fused_mlp  H += att_c W_oc + b_oc;  H += GELU(LN3(H) W_up + b_up) W_dn + b_dn,
+//                with the LayerNorm statistics of the final rows written for the next LN
+//
+// Weight fragment layout (k_pack_frag): for a K x N matrix W, fragment (nb, ks) of lane l
+// holds W[16 ks + 8 (l/32) + j][32 nb + l%32], j = 0..7, as 8 consecutive bf16; fragments
+// are stored [N/32][K/16][64 lanes], so one wave reads one contiguous kilobyte per fragment.
+
+#include "common.h"
+#include "kernels.h"
+
+namespace fmd {
+namespace {
+
+constexpr int kD = 256;              // model width
+constexpr int kBM = 128;             // token rows per workgroup
+constexpr int kWaves = 8;            // wave w owns columns [32w, 32w + 32) of a 256-wide slab
+constexpr int kThreads = 64 * kWaves;
+constexpr int kRing = 8;             // weight fragments in flight per wave
+constexpr int kLdA = kD + 8;         // LDS pitch (bf16) of the 128 x 256 activation tile
+constexpr int kBH = 128;             // MLP hidden units per chunk
+constexpr int kLdH = kBH + 8;        // LDS pitch (bf16) of a hidden chunk
+constexpr int kKs = kD / 16;         // fragments along K = 256
+
+__device__ __forceinline__ int acc_row(int mi, int r, int lane) {
+  return mi * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+}
+
+__device__ __forceinline__ bf16x8 as_bf16x8(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
+
+// acc[mi] += A[row0 + 32 mi + .., k] x B over `nks` fragments along K, A in LDS (pitch ld,
+// first K column 0). B fragments stream through a ring of kRing registers: on entry the
+// ring holds this phase's fragments 0 .. kRing-1; each consumed slot is refilled with the
+// fragment kRing positions ahead, taken from `cur` (this phase's fragment 0, wave-uniform)
+// or, in the last kRing steps, from the start of the next phase (`next`; with
+// kPrefetchNext false the ring is left empty instead). nks is a multiple of kRing.
+__device__ __forceinline__ void ring_fill(u32x4 (&ring)[kRing], const u32x4* __restrict__ src,
+                                          int lane) {
+#pragma unroll
+  for (int j = 0; j < kRing; ++j) ring[j] = src[j * 64 + lane];
+}
+
+template <int TM, bool kPrefetchNext = true>
+__device__ __forceinline__ void mfma_phase(f32x16 (&acc)[TM], const bf16* __restrict__ lds,
+                                           int ld, int row0, int nks, u32x4 (&ring)[kRing],
+                                           const u32x4* __restrict__ cur,
+                                           const u32x4* __restrict__ next, int lane) {
+  // compiler-only barrier: keeps the LDS reads of a tile that several phases read (the
+  // same LayerNorm tile for Q, K and V, or for every MLP chunk) inside their phase instead
+  // of hoisted out of the enclosing loop into hundreds of live registers
+  asm volatile("" ::: "memory");
+  const bf16* arow = lds + (row0 + (lane & 31)) * ld + (lane >> 5) * 8;
+  for (int g = 0; g < nks; g += kRing) {
+    const bool more = g + kRing < nks;
+    const u32x4* src = more ? cur + (g + kRing) * 64 : next;
+#pragma unroll
+    for (int j = 0; j < kRing; ++j) {
+      const int k = (g + j) * 16;
+      bf16x8 a[TM];
+#pragma unroll
+      for (int mi = 0; mi < TM; ++mi) a[mi] = *(const bf16x8*)(arow + mi * 32 * ld + k);
+      const bf16x8 b = as_bf16x8(ring[j]);
+      if (kPrefetchNext || more) ring[j] = src[j * 64 + lane];
+#pragma unroll
+      for (int mi = 0; mi < TM; ++mi)
+        acc[mi] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[mi], b, acc[mi], 0, 0, 0);
+    }
+  }
+}
+
+// Global row access in the accumulator layout. Element (mi, r) of a lane sits at byte
+// (32 mi + 8 (r/4) + r%4) * pitch + lane_off from the tile's first row, where
+// lane_off = (4 (lane/32) * ld + col) * sizeof(elem). The row-group part is added to a
+// wave-uniform base and r%4 becomes an immediate offset, so only one 32-bit per-lane
+// offset stays live instead of one 64-bit address per element.
+template <typename E, int LD>
+struct RowIo {
+  const char* base;     // wave-uniform: first row of the tile
+  uint32_t lane_off;
+  __device__ RowIo(const E* X, int64_t m0, int col, int lane)
+      : base((const char*)(X + m0 * LD)),
+        lane_off((uint32_t)((4 * (lane >> 5) * LD + col) * sizeof(E))) {
+    // opaque to the compiler: the addresses are formed here, where they are used, and not
+    // computed early and held live across the phases in between
+    asm volatile("" : "+v"(lane_off));
+  }
+  __device__ __forceinline__ E* at(int mi, int r) const {
+    const char* gb = base + (size_t)(mi * 32 + 8 * (r >> 2)) * LD * sizeof(E);
+    return (E*)(gb + lane_off + (r & 3) * LD * sizeof(E));
+  }
+};
+
+// acc = rows m0.. of X (FP32, pitch kD) at the wave's columns, plus bias (may be null).
+__device__ __forceinline__ void load_rows(f32x16 (&acc)[4], const float* __restrict__ X,
+                                          int64_t m0, int col,
+                                          const float* __restrict__ bias, int lane) {
+  const float bv = bias ? bias[col] : 0.f;
+  const RowIo<float, kD> io(X, m0, col, lane);
+#pragma unroll
+  for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[mi][r] = *io.at(mi, r) + bv;
+}
+
+__device__ __forceinline__ void zero(f32x16 (&acc)[4], const float* __restrict__ bias, int col) {
+  const float bv = bias ? bias[col] : 0.f;
+#pragma unroll
+  for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[mi][r] = bv;
+}
+
+// 128 x 256 BF16 tile of S (pitch lds_) at rows m0.. into LDS (pitch kLdA).
+__device__ __forceinline__ void tile_to_lds(bf16* __restrict__ A, const bf16* __restrict__ S,
+                                            int lds_, int64_t m0, int tid) {
+  constexpr int kChunks = kBM * kD / 8;                 // 16-byte chunks
+  constexpr int kPer = kChunks / kThreads;
+  u32x4 v[kPer];
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) {
+    const int idx = tid + i * kThreads;
+    v[i] = *(const u32x4*)((const char*)(S + m0 * lds_) +
+                           (uint32_t)(((idx / (kD / 8)) * lds_ + (idx % (kD / 8)) * 8) * 2));
+  }
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) {
+    const int idx = tid + i * kThreads;
+    *(u32x4*)(A + (idx / (kD / 8)) * kLdA + (idx % (kD / 8)) * 8) = v[i];
+  }
+}
+
+// Transpose-reduction over the 32 lanes of a half wave without data-dependent register
+// selection: at each step both halves of the value set are reduced with the partner lane
+// and the lane keeps the half its lane bit selects. Afterwards v[0] of lane l holds the sum
+// over the half wave of value (l & 31).
+__device__ __forceinline__ void transpose_reduce32_v2(float (&v)[32], int lane) {
+#pragma unroll
+  for (int m = 16, n = 32; m >= 1; m >>= 1, n >>= 1) {
+    const bool up = (lane & m) != 0;
+#pragma unroll
+    for (int i = 0; i < n / 2; ++i) {
+      const float ra = v[i] + __shfl_xor(v[i], m, kWave);
+      const float rb = v[i + n / 2] + __shfl_xor(v[i + n / 2], m, kWave);
+      v[i] = up ? rb : ra;
+    }
+  }
+}
+
+__device__ __forceinline__ void row_partials(float (&v)[32], float* __restrict__ red, int g,
+                                             int lane, int w) {
+  transpose_reduce32_v2(v, lane);
+  const int j = lane & 31;
+  red[w * kBM + acc_row(2 * g + (j >> 4), j & 15, lane)] = v[0];
+}
+
+// LayerNorm statistics of the 128 full rows held in acc: mean and 1/sqrt(biased variance +
+// eps) into mu[] / rs[] (LDS), optionally also to stats_out[m0 + row]. Per-wave partial
+// sums over the wave's 32 columns by a transpose-reduction, then across the 8 waves through
+// red[]. Ends with a barrier (mu/rs visible to all waves).
+__device__ __forceinline__ void row_stats(const f32x16 (&acc)[4], float* __restrict__ red,
+                                          float* __restrict__ mu, float* __restrict__ rs,
+                                          float2* __restrict__ stats_out, int64_t m0,
+                                          int lane, int w, int tid) {
+  // No multiply-add contraction here: a square fused into the lane exchange's add would be
+  // exact on the lane that keeps the partial sum and rounded on the lane that sends it, so
+  // the statistics would depend on the row's position in the tile.
+#pragma clang fp contract(off)
+  // pass 1: row sums
+#pragma unroll
+  for (int g = 0; g < 2; ++g) {
+    float v[32];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) v[h * 16 + r] = acc[2 * g + h][r];
+    row_partials(v, red, g, lane, w);
+  }
+  __syncthreads();
+  if (tid < kBM) {
+    float t = 0.f;
+#pragma unroll
+    for (int q = 0; q < kWaves; ++q) t += red[q * kBM + tid];
+    mu[tid] = t * (1.0f / kD);
+  }
+  __syncthreads();
+  // pass 2: sums of squared deviations
+#pragma unroll
+  for (int g = 0; g < 2; ++g) {
+    float v[32];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const float dv = acc[2 * g + h][r] - mu[acc_row(2 * g + h, r, lane)];
+        v[h * 16 + r] = dv * dv;
+      }
+    row_partials(v, red, g, lane, w);
+  }
+  __syncthreads();
+  if (tid < kBM) {
+    float t = 0.f;
+#pragma unroll
+    for (int q = 0; q < kWaves; ++q) t += red[q * kBM + tid];
+    rs[tid] = rsqrtf(t * (1.0f / kD) + kLnEps);
+    if (stats_out) stats_out[m0 + tid] = make_float2(mu[tid], rs[tid]);
+  }
+  __syncthreads();
+}
+
+// LDS tile A (pitch kLdA) = LayerNorm(acc rows) with gain g and shift s, in BF16.
+__device__ __forceinline__ void ln_to_lds(const f32x16 (&acc)[4], const float* __restrict__ mu,
+                                          const float* __restrict__ rs,
+                                          const float* __restrict__ g,
+                                          const float* __restrict__ s, bf16* __restrict__ A,
+                                          int col, int lane) {
+  const float gv = g[col], sv = s[col];
+#pragma unroll
+  for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = acc_row(mi, r, lane);
+      A[row * kLdA + col] = (bf16)((acc[mi][r] - mu[row]) * rs[row] * gv + sv);
+    }
+}
+
+__device__ __forceinline__ void store_rows_f32(const f32x16 (&acc)[4], float* __restrict__ X,
+                                               int64_t m0, int col, int lane) {
+  const RowIo<float, kD> io(X, m0, col, lane);
+#pragma unroll
+  for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) *io.at(mi, r) = acc[mi][r];
+}
+
+template <int LD>
+__device__ __forceinline__ void store_rows_bf16(const f32x16 (&acc)[4], bf16* __restrict__ X,
+                                                int64_t m0, int col, int lane) {
+  const RowIo<bf16, LD> io(X, m0, col, lane);
+#pragma unroll
+  for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) *io.at(mi, r) = (bf16)acc[mi][r];
+}
+
+// GELU(z) = z/2 (1 + erf(z / sqrt 2)) with erf by Abramowitz & Stegun 7.1.26 (absolute error
+// at most 1.5e-7, far below the BF16 rounding of the result): branch-free, unlike a
+// library erf, so that the 64 lanes of a wave stay converged in the MLP epilogue.
+__device__ __forceinline__ float gelu_as(float z) {
+  const float x = z * 0.70710678118654752f;
+  const float a = fabsf(x);
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, a, 1.0f));
+  const float poly =
+      t * fmaf(t, fmaf(t, fmaf(t, fmaf(t, 1.061405429f, -1.453152027f), 1.421413741f),
+                       -0.284496736f), 0.254829592f);
+  const float e = fmaf(-poly, __builtin_amdgcn_exp2f(-a * a * 1.4426950408889634f), 1.0f);
+  return 0.5f * z * (1.0f + copysignf(e, x));
+}
+
+struct SharedLn {
+  float red[kWaves * kBM];
+  float mu[kBM];
+  float rs[kBM];
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kThreads) void k_fused_qkv(const float* __restrict__ H,
+                                                        const float* __restrict__ g,
+                                                        const float* __restrict__ s,
+                                                        const u32x4* __restrict__ Wf,
+                                                        const float* __restrict__ bias,
+                                                        bf16* __restrict__ qkv) {
+  __shared__ __attribute__((aligned(16))) bf16 A[kBM * kLdA];
+  __shared__ SharedLn sl;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int64_t m0 = (int64_t)blockIdx.x * kBM;
+  const int col = w * 32 + (lane & 31);
+  const u32x4* wf = Wf + w * kKs * 64;            // slab s: + s * kWaves * kKs * 64
+  u32x4 ring[kRing];
+  ring_fill(ring, wf, lane);
+  f32x16 acc[4];
+  load_rows(acc, H, m0, col, nullptr, lane);
+  row_stats(acc, sl.red, sl.mu, sl.rs, nullptr, m0, lane, w, tid);
+  ln_to_lds(acc, sl.mu, sl.rs, g, s, A, col, lane);
+  __syncthreads();
+#pragma unroll 1
+  for (int slab = 0; slab < 3; ++slab) {
+    zero(acc, bias, slab * kD + col);
+    const u32x4* cur = wf + slab * kWaves * kKs * 64;
+    mfma_phase<4>(acc, A, kLdA, 0, kKs, ring, cur, slab < 2 ? cur + kWaves * kKs * 64 : cur,
+                  lane);
+    store_rows_bf16<3 * kD>(acc, qkv, m0, slab * kD + col, lane);
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_fused_oqc(
+    const bf16* __restrict__ att, const u32x4* __restrict__ Wf_o, const float* __restrict__ b_o,
+    float* __restrict__ H, const float* __restrict__ g, const float* __restrict__ s,
+    const u32x4* __restrict__ Wf_qc, const float* __restrict__ b_qc, bf16* __restrict__ qc) {
+  __shared__ __attribute__((aligned(16))) bf16 A[kBM * kLdA];
+  __shared__ SharedLn sl;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int64_t m0 = (int64_t)blockIdx.x * kBM;
+  const int col = w * 32 + (lane & 31);
+  const u32x4* wo = Wf_o + w * kKs * 64;
+  const u32x4* wq = Wf_qc + w * kKs * 64;
+  u32x4 ring[kRing];
+  ring_fill(ring, wo, lane);
+  tile_to_lds(A, att, kD, m0, tid);
+  f32x16 acc[4];
+  load_rows(acc, H, m0, col, b_o, lane);
+  __syncthreads();
+  mfma_phase<4, false>(acc, A, kLdA, 0, kKs, ring, wo, wo, lane);
+  store_rows_f32(acc, H, m0, col, lane);
+  row_stats(acc, sl.red, sl.mu, sl.rs, nullptr, m0, lane, w, tid);   // barrier: A reads done
+  ring_fill(ring, wq, lane);
+  ln_to_lds(acc, sl.mu, sl.rs, g, s, A, col, lane);
+  __syncthreads();
+  zero(acc, b_qc, col);
+  mfma_phase<4>(acc, A, kLdA, 0, kKs, ring, wq, wq, lane);
+  store_rows_bf16<kD>(acc, qc, m0, col, lane);
+}
+
+__global__ __launch_bounds__(kThreads) void k_fused_mlp(
+    const bf16* __restrict__ att, const u32x4* __restrict__ Wf_oc, const float* __restrict__ b_oc,
+    float* __restrict__ H, const float* __restrict__ g, const float* __restrict__ s,
+    const u32x4* __restrict__ Wf_up, const float* __restrict__ b_up,
+    const u32x4* __restrict__ Wf_dn, const float* __restrict__ b_dn,
+    float2* __restrict__ stats_out) {
+  __shared__ __attribute__((aligned(16))) bf16 A[kBM * kLdA];
+  __shared__ __attribute__((aligned(16))) bf16 Hc[2][kBM * kLdH];
+  __shared__ SharedLn sl;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = w >> 2, wn = w & 3;        // hidden-chunk products: 2 x 4 waves of 64 x 32
+  const int64_t m0 = (int64_t)blockIdx.x * kBM;
+  const int col = w * 32 + (lane & 31);
+  constexpr int kChunks = 4 * kD / kBH;      // 8
+  constexpr int kUpKs = kKs;                 // 16 fragments per up-projection chunk
+  constexpr int kDnKs = kBH / 16;            // 8 fragments per down-projection chunk
+  const u32x4* woc = Wf_oc + w * kKs * 64;
+  // chunk c: up-projection fragments of column block 4c + wn, down-projection fragments
+  // c * kDnKs .. of column block w (K = 4d)
+  const u32x4* wup = Wf_up + wn * kKs * 64;          // + c * 4 * kKs * 64
+  const u32x4* wdn = Wf_dn + w * (4 * kD / 16) * 64; // + c * kDnKs * 64
+  u32x4 ring[kRing];
+  ring_fill(ring, woc, lane);
+  tile_to_lds(A, att, kD, m0, tid);
+  f32x16 acc[4];
+  load_rows(acc, H, m0, col, b_oc, lane);
+  __syncthreads();
+  mfma_phase<4, false>(acc, A, kLdA, 0, kKs, ring, woc, woc, lane);
+  row_stats(acc, sl.red, sl.mu, sl.rs, nullptr, m0, lane, w, tid);   // barrier: A reads done
+  ring_fill(ring, wup, lane);
+  ln_to_lds(acc, sl.mu, sl.rs, g, s, A, col, lane);
+  __syncthreads();
+  const int hcol = wn * 32 + (lane & 31);
+#pragma unroll 1
+  for (int c = 0; c < kChunks; ++c) {
+    bf16* hb = Hc[c & 1];
+    f32x16 h2[2];
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) h2[mi][r] = 0.f;
+    const u32x4* up_c = wup + c * (kBH / 32) * kKs * 64;
+    const u32x4* dn_c = wdn + c * kDnKs * 64;
+    mfma_phase<2>(h2, A, kLdA, wm * 64, kUpKs, ring, up_c, dn_c, lane);
+    const float bv = b_up[c * kBH + hcol];
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+      for (int r = 0; r < 16; ++r)
+        hb[(wm * 64 + acc_row(mi, r, lane)) * kLdH + hcol] = (bf16)gelu_as(h2[mi][r] + bv);
+    __syncthreads();
+    mfma_phase<4>(acc, hb, kLdH, 0, kDnKs, ring, dn_c,
+                  c + 1 < kChunks ? up_c + (kBH / 32) * kKs * 64 : dn_c, lane);
+  }
+  const float bv = b_dn[col];
+#pragma unroll
+  for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[mi][r] += bv;
+  store_rows_f32(acc, H, m0, col, lane);
+  row_stats(acc, sl.red, sl.mu, sl.rs, stats_out, m0, lane, w, tid);
+}
+
+__global__ void k_pack_frag(const float* __restrict__ W, int K, int N, u32x4* __restrict__ Wf) {
+  const int nks = K / 16;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)(N / 32) * nks * 64) return;
+  const int lane = (int)(e % 64);
+  const int ks = (int)((e / 64) % nks);
+  const int nb = (int)(e / (64 * nks));
+  const int n = nb * 32 + (lane & 31);
+  bf16x8 v;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) v[j] = (bf16)W[(int64_t)(ks * 16 + (lane >> 5) * 8 + j) * N + n];
+  Wf[e] = __builtin_bit_cast(u32x4, v);
+}
+
+// ---------------------------------------------------------------------------------------
+
+bool fused_supported(int d_model, int mlp_ratio) { return d_model == kD && mlp_ratio == 4; }
+
+hipError_t launch_pack_frag(hipStream_t st, const float* W, int K, int N, void* Wf) {
+  if (K % 16 || N % 32) return hipErrorInvalidValue;
+  const int64_t n = (int64_t)(N / 32) * (K / 16) * 64;
+  hipLaunchKernelGGL(k_pack_frag, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, W, K, N,
+                     (u32x4*)Wf);
+  return hipGetLastError();
+}
+
+hipError_t launch_fused_qkv(hipStream_t st, int64_t Mp, const float* H, const float* g,
+                            const float* s, const void* Wf, const float* bias, void* qkv) {
+  if (Mp % kBM) return hipErrorInvalidValue;
+  if (Mp == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fused_qkv, dim3((unsigned)(Mp / kBM)), dim3(kThreads), 0, st, H, g, s,
+                     (const u32x4*)Wf, bias, (bf16*)qkv);
+  return hipGetLastError();
+}
+
+hipError_t launch_fused_oqc(hipStream_t st, int64_t Mp, const void* att, const void* Wf_o,
+                            const float* b_o, float* H, const float* g, const float* s,
+                            const void* Wf_qc, const float* b_qc, void* qc) {
+  if (Mp % kBM) return hipErrorInvalidValue;
+  if (Mp == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fused_oqc, dim3((unsigned)(Mp / kBM)), dim3(kThreads), 0, st,
+                     (const bf16*)att, (const u32x4*)Wf_o, b_o, H, g, s, (const u32x4*)Wf_qc,
+                     b_qc, (bf16*)qc);
+  return hipGetLastError();
+}
+
+hipError_t launch_fused_mlp(hipStream_t st, int64_t Mp, const void* att, const void* Wf_oc,
+                            const float* b_oc, float* H, const float* g, const float* s,
+                            const void* Wf_up, const float* b_up, const void* Wf_dn,
+                            const float* b_dn, float2* stats_out) {
+  if (Mp % kBM) return hipErrorInvalidValue;
+  if (Mp == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fused_mlp, dim3((unsigned)(Mp / kBM)), dim3(kThreads), 0, st,
+                     (const bf16*)att, (const u32x4*)Wf_oc, b_oc, H, g, s,
+                     (const u32x4*)Wf_up, b_up, (const u32x4*)Wf_dn, b_dn, stats_out);
+  return hipGetLastError();
+}
+
+}  // namespace fmd

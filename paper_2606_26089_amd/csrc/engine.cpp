@@ -231,6 +231,7 @@ void flush_timing(fmd_model* m) {
       m->t_ms[r.cls] += ms;
       m->t_n[r.cls] += 1;
       m->t_work[r.cls] += r.work;
+      m->t_bytes[r.cls] += r.bytes;
     }
     m->ev_pool.push_back(r.a);
     m->ev_pool.push_back(r.b);
@@ -338,7 +339,7 @@ hipError_t slot_gemm(fmd_model* m, Call& c, int slot, int tile, const DevBlock& 
                             (const T*)B.Wo, B.bo, nullptr, nullptr, nullptr, w.H, d,
                             m->fuse_stats ? &c.sargs : nullptr, tile);
     case TS_PROJ_LN:
-      return launch_gemm<T>(c.st, FMD_K_GEMM_PROJ, true, EPI_STORE, c.Tp, d, d, w.H, d,
+      return launch_gemm<T>(c.st, FMD_K_GEMM_QC, true, EPI_STORE, c.Tp, d, d, w.H, d,
                             (const T*)B.Wqc, B.bqc, w.stats, B.g2, B.s2, w.qc, d, nullptr, tile);
     case TS_UP:
       return launch_gemm<T>(c.st, FMD_K_GEMM_UP, true, EPI_GELU, c.Tp, 4 * d, d, w.H, d,
@@ -358,7 +359,7 @@ hipError_t slot_gemm(fmd_model* m, Call& c, int slot, int tile, const DevBlock& 
 // later (the residual stream is rebuilt by the next input embedding).
 template <typename T>
 int autotune(fmd_model* m, Call& c) {
-  if (!m->autotune || m->kind != 0) return FMD_OK;
+  if (!m->autotune || m->kind != 0 || m->fused == FMD_FUSED_ALL) return FMD_OK;   // fixed tiling
   const int b = bucket_of(c.Tp);
   const int d = m->cfg.d_model;
   const int N[TS_COUNT] = {3 * d, d, d, 4 * d, d};
@@ -394,6 +395,7 @@ int autotune(fmd_model* m, Call& c) {
         run_best = std::min(run_best, ms * 1e3f);
       }
       if (status != FMD_OK) break;
+      if (t < 8) m->tune_all[sl][b][t] = run_best;
       if (best < 0 || run_best < best_us) best = t, best_us = run_best;
     }
     m->tune[sl][b] = (int8_t)(best >= 0 ? best : full_row_slot(m, sl) ? default_tile_rows(N[sl])
@@ -415,6 +417,10 @@ int net_forward(fmd_model* m, Call& c, const float* t_ev) {
   const int d = cf.d_model, L = cf.n_blocks, Hh = cf.n_heads, dh = d / Hh;
   const double Td = (double)c.T;
   const size_t es = sizeof(T);
+  // algorithmic HBM bytes: a LayerNorm input (FP32 rows + statistics), a residual update
+  // (FP32 read and write, plus the next LayerNorm's statistics when fused)
+  const double ln_in = Td * (d * 4.0 + 8.0);
+  const double resid = Td * (d * 8.0 + (m->fuse_stats ? 8.0 : 0.0));
   char* qkv = (char*)w.qkv;
   char* kv = (char*)w.kv;
   c.sargs = OdeArgs{};
@@ -427,52 +433,78 @@ int net_forward(fmd_model* m, Call& c, const float* t_ev) {
     return launch_embed(c.st, w.xs, kStateLd, 9, c.T, t_ev ? w.tok_event : nullptr, w.temb,
                         m->W_xin, d, w.H, d, w.stats);
   }));
+  // fused BF16 kernels per block segment (bit 1: LN1 + QKV; bit 2: W_o + residual + LN2 +
+  // cross query; bit 4: W_oc + residual + LN3 + MLP + residual); the GEMM kernels otherwise
+  const int fz = std::is_same<T, bf16>::value ? m->fused : 0;
+  const double dd = (double)d;
   for (int l = 0; l < L; ++l) {
     const DevBlock& B = m->blk[l];
-    if (l > 0) FMD_TRY(row_stats(m, c));
-    FMD_TRY(timed(m, c.st, FMD_K_GEMM_QKV, 2.0 * Td * d * 3 * d, [&] {
-      return launch_gemm<T>(c.st, FMD_K_GEMM_QKV, true, EPI_STORE, c.Tp, 3 * d, d, w.H, d,
-                            (const T*)B.Wqkv, B.bqkv, w.stats, B.g1, B.s1, w.qkv, 3 * d, nullptr,
-                            tile_for(m, TS_QKV, c.Tp, 3 * d));
-    }));
-    FMD_TRY(timed(m, c.st, FMD_K_ATTN_SELF, 4.0 * c.sum_n2 * d, [&] {
+    if (fz & FMD_FUSED_QKV) {
+      FMD_TRY(timed(m, c.st, FMD_K_GEMM_QKV, 2.0 * Td * dd * 3 * dd,
+                    Td * dd * 4 + (Td + dd) * 3 * dd * es, [&] {
+        return launch_fused_qkv(c.st, c.Tp, w.H, B.g1, B.s1, B.Fqkv, B.bqkv, w.qkv);
+      }));
+    } else {
+      if (l > 0) FMD_TRY(row_stats(m, c));
+      FMD_TRY(timed(m, c.st, FMD_K_GEMM_QKV, 2.0 * Td * d * 3 * d, ln_in + (Td + d) * 3 * d * es, [&] {
+        return launch_gemm<T>(c.st, FMD_K_GEMM_QKV, true, EPI_STORE, c.Tp, 3 * d, d, w.H, d,
+                              (const T*)B.Wqkv, B.bqkv, w.stats, B.g1, B.s1, w.qkv, 3 * d, nullptr,
+                              tile_for(m, TS_QKV, c.Tp, 3 * d));
+      }));
+    }
+    FMD_TRY(timed(m, c.st, FMD_K_ATTN_SELF, 4.0 * c.sum_n2 * d, Td * 4 * d * es, [&] {
       return launch_attention<T>(c.st, false, dh, Hh, c.items, w.work, (const T*)qkv, 3 * d,
                                  (const T*)(qkv + d * es), (const T*)(qkv + 2 * d * es), 3 * d,
                                  (T*)w.att, d, w.off, w.off);
     }));
-    FMD_TRY(timed(m, c.st, FMD_K_GEMM_PROJ, 2.0 * Td * d * d, [&] {
-      return launch_gemm<T>(c.st, FMD_K_GEMM_PROJ, false, resid_epi(m), c.Tp, d, d, w.att, d,
-                            (const T*)B.Wo, B.bo, nullptr, nullptr, nullptr, w.H, d,
-                            m->fuse_stats ? &c.sargs : nullptr, tile_for(m, TS_PROJ_RES, c.Tp, d));
-    }));
-    FMD_TRY(row_stats(m, c));
-    FMD_TRY(timed(m, c.st, FMD_K_GEMM_PROJ, 2.0 * Td * d * d, [&] {
-      return launch_gemm<T>(c.st, FMD_K_GEMM_PROJ, true, EPI_STORE, c.Tp, d, d, w.H, d,
-                            (const T*)B.Wqc, B.bqc, w.stats, B.g2, B.s2, w.qc, d, nullptr,
-                            tile_for(m, TS_PROJ_LN, c.Tp, d));
-    }));
-    FMD_TRY(timed(m, c.st, FMD_K_ATTN_CROSS, 4.0 * c.sum_n2 * d, [&] {
+    if (fz & FMD_FUSED_OQC) {
+      FMD_TRY(timed(m, c.st, FMD_K_FUSED_OQC, 2.0 * Td * dd * dd * 2,
+                    Td * dd * (es + 8 + es) + 2 * dd * dd * es, [&] {
+        return launch_fused_oqc(c.st, c.Tp, w.att, B.Fo, B.bo, w.H, B.g2, B.s2, B.Fqc, B.bqc, w.qc);
+      }));
+    } else {
+      FMD_TRY(timed(m, c.st, FMD_K_GEMM_PROJ, 2.0 * Td * d * d, (Td + d) * d * es + resid, [&] {
+        return launch_gemm<T>(c.st, FMD_K_GEMM_PROJ, false, resid_epi(m), c.Tp, d, d, w.att, d,
+                              (const T*)B.Wo, B.bo, nullptr, nullptr, nullptr, w.H, d,
+                              m->fuse_stats ? &c.sargs : nullptr, tile_for(m, TS_PROJ_RES, c.Tp, d));
+      }));
+      FMD_TRY(row_stats(m, c));
+      FMD_TRY(timed(m, c.st, FMD_K_GEMM_QC, 2.0 * Td * d * d, ln_in + (Td + d) * d * es, [&] {
+        return launch_gemm<T>(c.st, FMD_K_GEMM_QC, true, EPI_STORE, c.Tp, d, d, w.H, d,
+                              (const T*)B.Wqc, B.bqc, w.stats, B.g2, B.s2, w.qc, d, nullptr,
+                              tile_for(m, TS_PROJ_LN, c.Tp, d));
+      }));
+    }
+    FMD_TRY(timed(m, c.st, FMD_K_ATTN_CROSS, 4.0 * c.sum_n2 * d, Td * 4 * d * es, [&] {
       const size_t o = (size_t)l * 2 * d * es;
       return launch_attention<T>(c.st, true, dh, Hh, c.items, w.work, (const T*)w.qc, d,
                                  (const T*)(kv + o), (const T*)(kv + o + d * es), 2 * d * L,
                                  (T*)w.att, d, w.off, w.off);
     }));
-    FMD_TRY(timed(m, c.st, FMD_K_GEMM_PROJ, 2.0 * Td * d * d, [&] {
-      return launch_gemm<T>(c.st, FMD_K_GEMM_PROJ, false, resid_epi(m), c.Tp, d, d, w.att, d,
-                            (const T*)B.Woc, B.boc, nullptr, nullptr, nullptr, w.H, d,
-                            m->fuse_stats ? &c.sargs : nullptr, tile_for(m, TS_PROJ_RES, c.Tp, d));
-    }));
-    FMD_TRY(row_stats(m, c));
-    FMD_TRY(timed(m, c.st, FMD_K_GEMM_UP, 2.0 * Td * d * 4 * d, [&] {
-      return launch_gemm<T>(c.st, FMD_K_GEMM_UP, true, EPI_GELU, c.Tp, 4 * d, d, w.H, d,
-                            (const T*)B.Wup, B.bup, w.stats, B.g3, B.s3, w.hid, 4 * d, nullptr,
-                            tile_for(m, TS_UP, c.Tp, 4 * d));
-    }));
-    FMD_TRY(timed(m, c.st, FMD_K_GEMM_DOWN, 2.0 * Td * 4 * d * d, [&] {
-      return launch_gemm<T>(c.st, FMD_K_GEMM_DOWN, false, resid_epi(m), c.Tp, d, 4 * d, w.hid,
-                            4 * d, (const T*)B.Wdn, B.bdn, nullptr, nullptr, nullptr, w.H, d,
-                            m->fuse_stats ? &c.sargs : nullptr, tile_for(m, TS_DOWN, c.Tp, d));
-    }));
+    if (fz & FMD_FUSED_MLP) {
+      FMD_TRY(timed(m, c.st, FMD_K_FUSED_MLP, 2.0 * Td * dd * dd * 9,
+                    Td * (dd * (es + 8) + 8) + 9 * dd * dd * es, [&] {
+        return launch_fused_mlp(c.st, c.Tp, w.att, B.Foc, B.boc, w.H, B.g3, B.s3, B.Fup, B.bup,
+                                B.Fdn, B.bdn, w.stats);
+      }));
+    } else {
+      FMD_TRY(timed(m, c.st, FMD_K_GEMM_PROJ, 2.0 * Td * d * d, (Td + d) * d * es + resid, [&] {
+        return launch_gemm<T>(c.st, FMD_K_GEMM_PROJ, false, resid_epi(m), c.Tp, d, d, w.att, d,
+                              (const T*)B.Woc, B.boc, nullptr, nullptr, nullptr, w.H, d,
+                              m->fuse_stats ? &c.sargs : nullptr, tile_for(m, TS_PROJ_RES, c.Tp, d));
+      }));
+      FMD_TRY(row_stats(m, c));
+      FMD_TRY(timed(m, c.st, FMD_K_GEMM_UP, 2.0 * Td * d * 4 * d, ln_in + (Td + d) * 4 * d * es, [&] {
+        return launch_gemm<T>(c.st, FMD_K_GEMM_UP, true, EPI_GELU, c.Tp, 4 * d, d, w.H, d,
+                              (const T*)B.Wup, B.bup, w.stats, B.g3, B.s3, w.hid, 4 * d, nullptr,
+                              tile_for(m, TS_UP, c.Tp, 4 * d));
+      }));
+      FMD_TRY(timed(m, c.st, FMD_K_GEMM_DOWN, 2.0 * Td * 4 * d * d, (Td + d) * 4 * d * es + resid, [&] {
+        return launch_gemm<T>(c.st, FMD_K_GEMM_DOWN, false, resid_epi(m), c.Tp, d, 4 * d, w.hid,
+                              4 * d, (const T*)B.Wdn, B.bdn, nullptr, nullptr, nullptr, w.H, d,
+                              m->fuse_stats ? &c.sargs : nullptr, tile_for(m, TS_DOWN, c.Tp, d));
+      }));
+    }
   }
   return FMD_OK;
 }
@@ -708,6 +740,7 @@ int fmd_model_create(const fmd_model_config* cfg, const float* params, size_t n_
   std::memset(m->tune, -1, sizeof(m->tune));
   m->fuse_stats = default_tile_rows(cfg->d_model) >= 0;
   std::memset(m->tune_us, 0, sizeof(m->tune_us));
+  std::memset(m->tune_all, 0, sizeof(m->tune_all));
   auto bail = [&](int s) {
     fmd_model_destroy(m);
     return s;
@@ -724,6 +757,9 @@ int fmd_model_create(const fmd_model_config* cfg, const float* params, size_t n_
   if (grow(m->bkv, (size_t)(L * 2 * d) * 4) != FMD_OK) return bail(FMD_E_NOMEM);
   if (grow(m->Wout_pk, (size_t)64 * d * 4) != FMD_OK) return bail(FMD_E_NOMEM);
   if (grow(m->bout_pk, (size_t)64 * 4) != FMD_OK) return bail(FMD_E_NOMEM);
+  m->fused_ok = cfg->precision == FMD_BF16 && fused_supported(cfg->d_model, cfg->mlp_ratio);
+  m->fused = m->fused_ok ? FMD_FUSED_ALL : 0;
+  if (m->fused_ok && grow(m->frag, (size_t)(L * blk_elems) * 2) != FMD_OK) return bail(FMD_E_NOMEM);
   m->blk.assign(L, DevBlock{});
   char* pk = (char*)m->packed;
   char* wkv = (char*)m->Wkv;
@@ -734,6 +770,17 @@ int fmd_model_create(const fmd_model_config* cfg, const float* params, size_t n_
                        ? launch_pack_weight<bf16>(nullptr, W, (int)rows, (int)cols, (bf16*)dst)
                        : launch_pack_weight<float>(nullptr, W, (int)rows, (int)cols, (float*)dst);
     if (e != hipSuccess && status == FMD_OK) status = fail(FMD_E_DEVICE, "weight packing failed");
+  };
+  // second copy of a block matrix in the fused kernels' fragment layout, at the same
+  // element offset inside the block as the packed copy
+  char* fr = (char*)m->frag;
+  auto pack_frag = [&](size_t off, int64_t rows, int64_t cols, int l, size_t elem_off,
+                       void** dst) {
+    if (!m->fused_ok) return;
+    *dst = fr + ((size_t)l * blk_elems + elem_off) * 2;
+    if (launch_pack_frag(nullptr, m->params + off, (int)rows, (int)cols, *dst) != hipSuccess &&
+        status == FMD_OK)
+      status = fail(FMD_E_DEVICE, "weight packing failed");
   };
   walk_params(*cfg, [&](int id, int l, size_t off, int64_t rows, int64_t cols) {
     const float* p = m->params + off;
@@ -760,12 +807,36 @@ int fmd_model_create(const fmd_model_config* cfg, const float* params, size_t n_
       case P_B_OC: B->boc = p; break;
       case P_B_UP: B->bup = p; break;
       case P_B_DN: B->bdn = p; break;
-      case P_W_QKV: B->Wqkv = base; pack(off, rows, cols, B->Wqkv); break;
-      case P_W_O: B->Wo = base + 3 * d * d * es; pack(off, rows, cols, B->Wo); break;
-      case P_W_QC: B->Wqc = base + 4 * d * d * es; pack(off, rows, cols, B->Wqc); break;
-      case P_W_OC: B->Woc = base + 5 * d * d * es; pack(off, rows, cols, B->Woc); break;
-      case P_W_UP: B->Wup = base + 6 * d * d * es; pack(off, rows, cols, B->Wup); break;
-      case P_W_DN: B->Wdn = base + 10 * d * d * es; pack(off, rows, cols, B->Wdn); break;
+      case P_W_QKV:
+        B->Wqkv = base;
+        pack(off, rows, cols, B->Wqkv);
+        pack_frag(off, rows, cols, l, 0, &B->Fqkv);
+        break;
+      case P_W_O:
+        B->Wo = base + 3 * d * d * es;
+        pack(off, rows, cols, B->Wo);
+        pack_frag(off, rows, cols, l, 3 * d * d, &B->Fo);
+        break;
+      case P_W_QC:
+        B->Wqc = base + 4 * d * d * es;
+        pack(off, rows, cols, B->Wqc);
+        pack_frag(off, rows, cols, l, 4 * d * d, &B->Fqc);
+        break;
+      case P_W_OC:
+        B->Woc = base + 5 * d * d * es;
+        pack(off, rows, cols, B->Woc);
+        pack_frag(off, rows, cols, l, 5 * d * d, &B->Foc);
+        break;
+      case P_W_UP:
+        B->Wup = base + 6 * d * d * es;
+        pack(off, rows, cols, B->Wup);
+        pack_frag(off, rows, cols, l, 6 * d * d, &B->Fup);
+        break;
+      case P_W_DN:
+        B->Wdn = base + 10 * d * d * es;
+        pack(off, rows, cols, B->Wdn);
+        pack_frag(off, rows, cols, l, 10 * d * d, &B->Fdn);
+        break;
       case P_W_KC: pack(off, rows, cols, wkv + (size_t)l * 2 * d * d * es); break;
       case P_W_VC: pack(off, rows, cols, wkv + ((size_t)l * 2 * d + d) * d * es); break;
       case P_B_KC:
@@ -832,6 +903,7 @@ int fmd_model_destroy(fmd_model* m) {
   free_ws(m->ws);
   if (m->params) (void)hipFree(m->params);
   if (m->packed) (void)hipFree(m->packed);
+  if (m->frag) (void)hipFree(m->frag);
   if (m->Wkv) (void)hipFree(m->Wkv);
   if (m->bkv) (void)hipFree(m->bkv);
   if (m->Wout_pk) (void)hipFree(m->Wout_pk);
@@ -924,11 +996,12 @@ int fmd_timing_enable(fmd_model* m, int32_t enable) {
   DeviceGuard guard(m->device);
   flush_timing(m);
   m->timing = enable != 0;
-  for (int k = 0; k < FMD_K_COUNT; ++k) m->t_ms[k] = 0, m->t_n[k] = 0, m->t_work[k] = 0;
+  for (int k = 0; k < FMD_K_COUNT; ++k) m->t_ms[k] = 0, m->t_n[k] = 0, m->t_work[k] = 0, m->t_bytes[k] = 0;
   return FMD_OK;
 }
 
-int fmd_timing_read(fmd_model* m, int32_t cls, double* total_ms, int64_t* launches, double* work) {
+int fmd_timing_read(fmd_model* m, int32_t cls, double* total_ms, int64_t* launches, double* work,
+                    double* bytes) {
   if (!m) return fail(FMD_E_INVALID, "null model");
   if (cls < 0 || cls >= FMD_K_COUNT) return fail(FMD_E_INVALID, "unknown kernel class");
   DeviceGuard guard(m->device);
@@ -936,19 +1009,35 @@ int fmd_timing_read(fmd_model* m, int32_t cls, double* total_ms, int64_t* launch
   if (total_ms) *total_ms = m->t_ms[cls];
   if (launches) *launches = m->t_n[cls];
   if (work) *work = m->t_work[cls];
+  if (bytes) *bytes = m->t_bytes[cls];
   return FMD_OK;
 }
 
 const char* fmd_kernel_name(fmd_model* m, int32_t cls) {
   (void)m;
-  static const char* names[FMD_K_COUNT] = {"k_gemm_qkv", "k_gemm_proj", "k_gemm_up", "k_gemm_down",
-                                           "k_attn_self", "k_attn_cross", "other"};
+  static const char* names[FMD_K_COUNT] = {"k_gemm_qkv",  "k_gemm_proj", "k_gemm_qc",
+                                           "k_gemm_up",   "k_gemm_down", "k_fused_oqc",
+                                           "k_fused_mlp", "k_attn_self", "k_attn_cross",
+                                           "other"};
+  if (cls == FMD_K_GEMM_QKV && m && (m->fused & FMD_FUSED_QKV)) return "k_fused_qkv";
   return cls >= 0 && cls < FMD_K_COUNT ? names[cls] : "";
 }
 
 int fmd_graphs_enable(fmd_model* m, int32_t enable) {
   if (!m) return fail(FMD_E_INVALID, "null model");
   m->graphs = enable != 0;
+  return FMD_OK;
+}
+
+int fmd_fused_enable(fmd_model* m, int32_t mask) {
+  if (!m) return fail(FMD_E_INVALID, "null model");
+  if (mask < 0 || mask > FMD_FUSED_ALL) return fail(FMD_E_INVALID, "fused mask %d not in [0, 7]", mask);
+  if (mask && !m->fused_ok)
+    return fail(FMD_E_UNSUPPORTED, "no fused kernels for this configuration (BF16, d_model 256 only)");
+  if (m->fused != mask) {
+    m->fused = mask;
+    m->tune_gen++;   // captured graphs hold the other kernel sequence
+  }
   return FMD_OK;
 }
 
@@ -972,10 +1061,18 @@ int fmd_tuning_table(fmd_model* m, char* buf, size_t cap, size_t* needed) {
       char e[256];
       snprintf(e, sizeof(e),
                "%s{\"site\": \"%s\", \"tokens_log2\": %d, \"tile\": %d, \"BM\": %d, \"BN\": %d, "
-               "\"BK\": %d, \"threads\": %d, \"us\": %.1f}",
+               "\"BK\": %d, \"threads\": %d, \"us\": %.1f, \"candidates_us\": {",
                first ? "" : ", ", slot_names[sl], b, (int)m->tune[sl][b], t.BM, t.BN, t.BK, t.threads,
                m->tune_us[sl][b]);
       js += e;
+      bool f2 = true;
+      for (int k = 0; k < 8; ++k)
+        if (m->tune_all[sl][b][k] > 0) {
+          snprintf(e, sizeof(e), "%s\"%d\": %.1f", f2 ? "" : ", ", k, m->tune_all[sl][b][k]);
+          js += e;
+          f2 = false;
+        }
+      js += "}}";
       first = false;
     }
   js += "]}";

@@ -17,6 +17,7 @@ struct DevBlock {
   const float *g1, *s1, *g2, *s2, *g3, *s3;
   const float *bqkv, *bo, *bqc, *boc, *bup, *bdn;
   void *Wqkv, *Wo, *Wqc, *Woc, *Wup, *Wdn;
+  void *Fqkv, *Fo, *Fqc, *Foc, *Fup, *Fdn;   // BF16 MFMA fragment layout (fused kernels)
 };
 
 // Device buffers of one call, grown on demand and reused across calls.
@@ -67,7 +68,7 @@ constexpr int kTuneBuckets = 40;   // floor(log2(padded token count))
 
 struct TimingRec {
   int cls;
-  double work;
+  double work, bytes;
   hipEvent_t a, b;
 };
 
@@ -80,6 +81,9 @@ struct fmd_model {
   int device = 0;
   float* params = nullptr;         // flat FP32 copy on device
   void* packed = nullptr;          // packed matrices in the compute type
+  void* frag = nullptr;            // fragment-layout BF16 matrices of the fused kernels
+  bool fused_ok = false;           // the fused block kernels exist for this configuration
+  int fused = 0;                   // segments that use them (FMD_FUSED_* bits)
   float* bkv = nullptr;            // [L * 2d] cross K/V biases
   float* Wout_pk = nullptr;        // [64][d] output head, transposed, rows >= f_reco zero (FP32)
   float* bout_pk = nullptr;        // [64] output bias, zero-padded
@@ -99,10 +103,12 @@ struct fmd_model {
   fmd_server* server = nullptr;    // attached server (the model's own calls are refused)
   int8_t tune[fmd::TS_COUNT][fmd::kTuneBuckets];   // chosen tiling, -1 = not tuned yet
   float tune_us[fmd::TS_COUNT][fmd::kTuneBuckets]; // its measured time
+  float tune_all[fmd::TS_COUNT][fmd::kTuneBuckets][8];   // every candidate's time (0: not run)
   bool timing = false;
   std::vector<fmd::TimingRec> trec;
   std::vector<hipEvent_t> ev_pool;
   double t_ms[FMD_K_COUNT] = {0};
   int64_t t_n[FMD_K_COUNT] = {0};
   double t_work[FMD_K_COUNT] = {0};
+  double t_bytes[FMD_K_COUNT] = {0};
 };

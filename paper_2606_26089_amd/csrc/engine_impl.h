@@ -72,7 +72,7 @@ hipEvent_t take_event(fmd_model* m);
 void flush_timing(fmd_model* m);
 
 template <typename F>
-int timed(fmd_model* m, hipStream_t st, int cls, double work, F&& launch) {
+int timed(fmd_model* m, hipStream_t st, int cls, double work, double bytes, F&& launch) {
   hipEvent_t a = nullptr, b = nullptr;
   if (m->timing) {
     if (m->trec.size() > 4096) flush_timing(m);
@@ -84,9 +84,14 @@ int timed(fmd_model* m, hipStream_t st, int cls, double work, F&& launch) {
   if (e != hipSuccess) return fail(FMD_E_DEVICE, "kernel launch (class %d): %s", cls, hipGetErrorString(e));
   if (m->timing && a && b) {
     (void)hipEventRecord(b, st);
-    m->trec.push_back(TimingRec{cls, work, a, b});
+    m->trec.push_back(TimingRec{cls, work, bytes, a, b});
   }
   return FMD_OK;
+}
+
+template <typename F>
+int timed(fmd_model* m, hipStream_t st, int cls, double work, F&& launch) {
+  return timed(m, st, cls, work, 0.0, launch);
 }
 
 

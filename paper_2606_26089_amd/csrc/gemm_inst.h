@@ -17,7 +17,8 @@ namespace fmd {
     gemm_body<T, LN, EPI, TL>(A, lda, Wt, K, bias, stats, g, s, C, ldc, n_tiles, ode);       \
   }
 FMD_GEMM_KERNEL(k_gemm_qkv)     // LN1 -> [Q|K|V]
-FMD_GEMM_KERNEL(k_gemm_proj)    // attention output projections (+ residual), LN2 -> cross Q
+FMD_GEMM_KERNEL(k_gemm_proj)    // attention output projections (+ residual)
+FMD_GEMM_KERNEL(k_gemm_qc)      // LN2 -> cross-attention query
 FMD_GEMM_KERNEL(k_gemm_up)      // LN3 -> MLP up + GELU
 FMD_GEMM_KERNEL(k_gemm_down)    // MLP down (+ residual)
 FMD_GEMM_KERNEL(k_gemm_head)    // LN_f -> output head + fused Euler/RK4 state update
@@ -54,10 +55,12 @@ static hipError_t dispatch_cls(hipStream_t st, int cls, bool ln, int epi, int64_
       if (ln && epi == EPI_STORE) FMD_GO(k_gemm_qkv, true, EPI_STORE);
       break;
     case FMD_K_GEMM_PROJ:
-      if (ln && epi == EPI_STORE) FMD_GO(k_gemm_proj, true, EPI_STORE);
       if (!ln && epi == EPI_RESID) FMD_GO(k_gemm_proj, false, EPI_RESID);
       if constexpr (TL::TM % 2 == 0)
         if (!ln && epi == EPI_RESID_LN) FMD_GO(k_gemm_proj, false, EPI_RESID_LN);
+      break;
+    case FMD_K_GEMM_QC:
+      if (ln && epi == EPI_STORE) FMD_GO(k_gemm_qc, true, EPI_STORE);
       break;
     case FMD_K_GEMM_UP:
       if (ln && epi == EPI_GELU) FMD_GO(k_gemm_up, true, EPI_GELU);

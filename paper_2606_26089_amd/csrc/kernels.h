@@ -129,6 +129,24 @@ hipError_t launch_linear_update(hipStream_t st, float alpha, float beta, const S
 template <typename T>
 hipError_t launch_pack_weight(hipStream_t st, const float* W, int K, int N, T* Wt);
 
+// Fused BF16 block kernels for d = 256 and a 4x MLP (block_bf16.hip). Row counts Mp are
+// multiples of 128; weights are in the fragment layout of launch_pack_frag.
+bool fused_supported(int d_model, int mlp_ratio);
+// W: FP32 K x N (y = x W) -> BF16 MFMA B fragments [N/32][K/16][64 lanes][8].
+hipError_t launch_pack_frag(hipStream_t st, const float* W, int K, int N, void* Wf);
+// qkv[Mp, 3d] = LN(H; g, s) Wqkv + b
+hipError_t launch_fused_qkv(hipStream_t st, int64_t Mp, const float* H, const float* g,
+                            const float* s, const void* Wf, const float* bias, void* qkv);
+// H += att Wo + b_o;  qc = LN(H; g, s) Wqc + b_qc
+hipError_t launch_fused_oqc(hipStream_t st, int64_t Mp, const void* att, const void* Wf_o,
+                            const float* b_o, float* H, const float* g, const float* s,
+                            const void* Wf_qc, const float* b_qc, void* qc);
+// H += att Woc + b_oc;  H += GELU(LN(H; g, s) Wup + b_up) Wdn + b_dn;  stats_out = LN stats of H
+hipError_t launch_fused_mlp(hipStream_t st, int64_t Mp, const void* att, const void* Wf_oc,
+                            const float* b_oc, float* H, const float* g, const float* s,
+                            const void* Wf_up, const float* b_up, const void* Wf_dn,
+                            const float* b_dn, float2* stats_out);
+
 // dst[i] = T(src[i]).
 template <typename T>
 hipError_t launch_convert(hipStream_t st, const float* src, int64_t n, T* dst);

@@ -17,9 +17,11 @@ OK, PENDING = 0, 1
 E_INVALID, E_NOMEM, E_BUDGET, E_UNSUPPORTED, E_DEVICE, E_STATE = -1, -2, -3, -4, -5, -6
 FP32, BF16 = 0, 1
 EULER, RK4 = 0, 1
-K_GEMM_QKV, K_GEMM_PROJ, K_GEMM_UP, K_GEMM_DOWN, K_ATTN_SELF, K_ATTN_CROSS, K_OTHER = range(7)
-KERNEL_CLASSES = ("gemm_qkv", "gemm_proj", "gemm_up", "gemm_down", "attn_self", "attn_cross",
-                  "other")
+(K_GEMM_QKV, K_GEMM_PROJ, K_GEMM_QC, K_GEMM_UP, K_GEMM_DOWN, K_FUSED_OQC, K_FUSED_MLP,
+ K_ATTN_SELF, K_ATTN_CROSS, K_OTHER) = range(10)
+FUSED_QKV, FUSED_OQC, FUSED_MLP, FUSED_ALL = 1, 2, 4, 7
+KERNEL_CLASSES = ("gemm_qkv", "gemm_proj", "gemm_qc", "gemm_up", "gemm_down", "fused_oqc",
+                  "fused_mlp", "attn_self", "attn_cross", "other")
 
 c_int32, c_int64, c_double, c_size_t, c_void_p = (ctypes.c_int32, ctypes.c_int64,
                                                     ctypes.c_double, ctypes.c_size_t,
@@ -101,10 +103,12 @@ def lib():
                                       c_void_p, c_void_p]),
         "fmd_timing_enable": (c_int32, [c_void_p, c_int32]),
         "fmd_timing_read": (c_int32, [c_void_p, c_int32, ctypes.POINTER(c_double),
-                                      ctypes.POINTER(c_int64), ctypes.POINTER(c_double)]),
+                                      ctypes.POINTER(c_int64), ctypes.POINTER(c_double),
+                                      ctypes.POINTER(c_double)]),
         "fmd_kernel_name": (ctypes.c_char_p, [c_void_p, c_int32]),
         "fmd_autotune_enable": (c_int32, [c_void_p, c_int32]),
         "fmd_graphs_enable": (c_int32, [c_void_p, c_int32]),
+        "fmd_fused_enable": (c_int32, [c_void_p, c_int32]),
         "fmd_tuning_table": (c_int32, [c_void_p, ctypes.c_char_p, c_size_t, ctypes.POINTER(c_size_t)]),
         "fmd_server_create": (c_int32, [c_void_p, ctypes.POINTER(ServerConfig), ctypes.POINTER(c_void_p)]),
         "fmd_server_submit": (c_int32, [c_void_p, ctypes.POINTER(EventsIn), ctypes.c_uint64,
@@ -271,13 +275,19 @@ class Model:
         _check(lib().fmd_timing_enable(self._h, int(bool(on))))
 
     def timing_read(self, cls):
-        ms, n, work = c_double(), c_int64(), c_double()
+        """(device ms, launches, algorithmic FLOPs, algorithmic HBM bytes) of one class."""
+        ms, n, work, nb = c_double(), c_int64(), c_double(), c_double()
         _check(lib().fmd_timing_read(self._h, int(cls), ctypes.byref(ms), ctypes.byref(n),
-                                     ctypes.byref(work)))
-        return ms.value, n.value, work.value
+                                     ctypes.byref(work), ctypes.byref(nb)))
+        return ms.value, n.value, work.value, nb.value
 
     def graphs_enable(self, on=True):
         _check(lib().fmd_graphs_enable(self._h, int(bool(on))))
+
+    def fused_enable(self, on=True):
+        """True: every fused block kernel; False: none; an int: FUSED_* bit mask."""
+        mask = FUSED_ALL if on is True else 0 if on is False else int(on)
+        _check(lib().fmd_fused_enable(self._h, mask))
 
     def autotune_enable(self, on=True):
         _check(lib().fmd_autotune_enable(self._h, int(bool(on))))
