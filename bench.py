@@ -28,6 +28,22 @@ import numpy as np  # noqa: E402
 
 PEAK_TFLOPS = {"bf16": 2500.0, "fp32": 157.3}    # MI355X dense matrix peaks
 PEAK_HBM_GBS = 8000.0
+# HBM bytes per launch measured with rocprofv3 byte counters (FETCH_SIZE, WRITE_SIZE), scaled
+# by the counts of a 1 GiB copy; valid while the kernel's source is unchanged
+TRAFFIC = os.path.join(ROOT, "profiles", "base-4096ev_hbm-traffic.json")
+
+
+def measured_traffic(kernel):
+    import hashlib
+    try:
+        with open(TRAFFIC) as f:
+            rec = json.load(f)["kernels"][kernel]
+        with open(os.path.join(ROOT, rec["source"]), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != rec["source_sha256"]:
+                return None
+        return rec["hbm_bytes_per_launch"]
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def log(*a):
@@ -85,8 +101,9 @@ def roofline(kern, dtype):
         achieved, peak, unit = nbytes / avg_s / 1e9, PEAK_HBM_GBS, "GB/s"
     else:
         achieved, peak, unit = flops / avg_s / 1e12, PEAK_TFLOPS[dtype], "TFLOP/s"
+    traffic = measured_traffic(k["kernel"]) if dtype == "bf16" else None
     return {"bound": bound, "achieved": round(achieved, 2), "peak": peak, "unit": unit,
-            "frac": round(achieved / peak, 4), "traffic": None, "kernel": k["kernel"],
+            "frac": round(achieved / peak, 4), "traffic": traffic, "kernel": k["kernel"],
             "class": name, "avg_launch_ms": round(k["ms"] / k["launches"], 4),
             "flop_per_launch": flops, "bytes_per_launch": nbytes,
             "tflops": round(flops / avg_s / 1e12, 2), "gbps": round(nbytes / avg_s / 1e9, 1),
@@ -173,7 +190,7 @@ def main():
     ap.add_argument("--fp32-steps", type=int, default=1)
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=0, help="oracle events (0: 2 per core)")
+    ap.add_argument("--cpu-sample", type=int, default=0, help="oracle events (0: 6 per core)")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-rates", default="1000,2000,5000")
     ap.add_argument("--serve-seconds", type=float, default=4.0)
@@ -220,7 +237,8 @@ def main():
             f"launches/step  {k['work'] / max(k['ms'], 1e-9) / 1e9:8.1f} TFLOP/s "
             f"{k['bytes'] / max(k['ms'], 1e-9) / 1e6:8.1f} GB/s  ({bound_of(k, 'bf16')}-bound)")
     rl = roofline(kern16, "bf16")
-    log(f"dominant kernel {rl['kernel']}: {rl['achieved']} TFLOP/s ({rl['frac']:.3f} of peak)")
+    log(f"dominant kernel {rl['kernel']}: {rl['achieved']} {rl['unit']} ({rl['frac']:.3f} of peak), "
+        f"HBM traffic {rl['traffic']} bytes/launch (algorithmic {rl['bytes_per_launch']:.0f})")
 
     fp32 = None
     out32 = None
@@ -237,7 +255,7 @@ def main():
     err = None
     if not a.no_cpu_baseline:
         cores = min(os.cpu_count() or 1, 16)
-        n = a.cpu_sample or 2 * cores
+        n = a.cpu_sample or 6 * cores
         dt_cpu, ref = cpu_baseline(w, flat, off, feat, n, cores)
         rows = int(off[n])
         cpu = {"value": round(n / dt_cpu, 4), "unit": "events/s", "cores": cores, "kind": "oracle",

@@ -208,6 +208,193 @@ FMD_ATTN_KERNEL(k_attn_self)
 FMD_ATTN_KERNEL(k_attn_cross)
 #undef FMD_ATTN_KERNEL
 
+// ---------------------------------------------------------------------------------------
+// BF16 with heads of 32: the same work split as above (one head of one 64-query tile per
+// workgroup, four waves of 16 queries), tuned for gfx950.
+//  - Chunks of 128 keys: most events fit in one, so the load -> barrier -> compute round
+//    trip is paid once. K rows are staged by waves 2-3 and V by waves 0-1, 4 loads each.
+//  - One-dimensional grid over (work item, head), heads fastest: the workgroups that read
+//    the two halves of a K/V cache line run together, so the line is fetched once. (The
+//    work list is sorted longest event first; dealing contiguous ranges of it to the XCDs
+//    would load one XCD with all the long events.)
+//  - V is staged transposed with packed 8-byte LDS stores (no two lanes write the same
+//    dword) and with a key permutation inside each 32-key group (key 16 hi + 4 g + r at
+//    position 8 g + 4 hi + r): the eight keys lane group g feeds to one MFMA are adjacent,
+//    so each V^T operand is one 16-byte LDS read.
+//  - The softmax runs on unscaled scores: one multiply-add forms the exp2 argument
+//    (s - max) * scale, masking happens only in an event's last, partial chunk, and the
+//    hardware exp2 is used (arguments <= 0). The row sums of P come from the P V product
+//    itself, through a third 16-row block of V^T whose first row is all ones.
+namespace {
+constexpr int kH32 = 32;
+constexpr int kKc2 = 128;           // keys per chunk
+constexpr int kLdK32 = kH32 + 8;    // Ks pitch (bf16)
+constexpr int kLdV32 = kKc2 + 8;    // Vt pitch (bf16)
+
+__device__ __forceinline__ int vt_pos(int k) {
+  const int grp = k >> 5, hi = (k >> 4) & 1, g = (k >> 2) & 3, r = k & 3;
+  return grp * 32 + 8 * g + 4 * hi + r;
+}
+}  // namespace
+
+__device__ __forceinline__ void attention32_body(
+    const bf16* __restrict__ Q, int ldq, const bf16* __restrict__ Kp,
+    const bf16* __restrict__ Vp, int ldkv, bf16* __restrict__ O, int ldo,
+    const int64_t* __restrict__ q_off, const int64_t* __restrict__ kv_off,
+    const int2* __restrict__ work, int n_heads, float sl2e) {
+  __shared__ __attribute__((aligned(16))) bf16 Ks[kKc2 * kLdK32];
+  __shared__ __attribute__((aligned(16))) bf16 Vt[kH32 * kLdV32];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, j = lane & 15;
+  const int L = blockIdx.x;
+  const int2 wk = work[L / n_heads];
+  const int h = L % n_heads;
+  const int e = wk.x;
+  const int64_t qs0 = q_off[e], ks0 = kv_off[e];
+  const int nq = (int)(q_off[e + 1] - qs0), nk = (int)(kv_off[e + 1] - ks0);
+  const int qbase = wk.y * QT + wave * 16;
+  const bool wave_active = qbase < nq;
+  const int qi = qbase + j;
+
+  bf16x8 qf;
+  {
+    const char* qc = (const char*)(Q + qs0 * ldq + h * kH32);
+    u32x4 v = *(const u32x4*)(qc + (uint32_t)((min(qi, nq - 1) * ldq + 8 * g) * 2));
+    if (qi >= nq) v = u32x4{0u, 0u, 0u, 0u};
+    qf = __builtin_bit_cast(bf16x8, v);
+  }
+  float m_run = -INFINITY;
+  // o[0], o[1]: output dims 0-15, 16-31; o[2] row 0 (lanes 0-15, register 0): sum of P
+  f32x4 o[3] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f},
+                f32x4{0.f, 0.f, 0.f, 0.f}};
+  // A operand of the row-sum block: V^T row 32 = ones (lanes 0 and 16 .. of row j = 0)
+  bf16x8 ones;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) ones[i] = (bf16)(j == 0 ? 1.f : 0.f);
+
+  for (int c0 = 0; c0 < nk; c0 += kKc2) {
+    // Rows past the event end are read clamped to its last row and zeroed.
+    const int lim = nk - 1 - c0;
+    if (wave >= 2) {   // K: 128 keys x 4 chunks of 16 bytes
+      const char* kc = (const char*)(Kp + (ks0 + c0) * ldkv + h * kH32);
+      const int t2 = tid - 128;
+      u32x4 v[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int idx = t2 + i * 128, row = idx >> 2, ch = idx & 3;
+        v[i] = *(const u32x4*)(kc + (uint32_t)((min(row, lim) * ldkv + ch * 8) * 2));
+        if (row > lim) v[i] = u32x4{0u, 0u, 0u, 0u};
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int idx = t2 + i * 128, row = idx >> 2, ch = idx & 3;
+        *(u32x4*)&Ks[row * kLdK32 + ch * 8] = v[i];
+      }
+    } else {           // V^T: thread = (4 consecutive keys, 8 consecutive dims)
+      const char* vc = (const char*)(Vp + (ks0 + c0) * ldkv + h * kH32);
+      const int kg = tid & 31, dg = tid >> 5;
+      u32x4 v[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int key = kg * 4 + r;
+        v[r] = *(const u32x4*)(vc + (uint32_t)((min(key, lim) * ldkv + dg * 8) * 2));
+        if (key > lim) v[r] = u32x4{0u, 0u, 0u, 0u};
+      }
+      const int pos = vt_pos(kg * 4);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        bf16x4 w4;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) w4[r] = __builtin_bit_cast(bf16x8, v[r])[i];
+        *(bf16x4*)&Vt[(dg * 8 + i) * kLdV32 + pos] = w4;
+      }
+    }
+    __syncthreads();
+    if (wave_active) {
+      const int nkb = min(kKc2, lim + 1 + 15) >> 4;   // 16-key blocks holding real keys
+      f32x4 s[8];
+#pragma unroll
+      for (int kb = 0; kb < 8; ++kb) {
+        s[kb] = f32x4{0.f, 0.f, 0.f, 0.f};
+        if (kb < nkb) {
+          const bf16x8 kf = *(const bf16x8*)&Ks[(kb * 16 + j) * kLdK32 + 8 * g];
+          s[kb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kf, qf, s[kb], 0, 0, 0);
+        }
+      }
+      if (lim < kKc2 - 1) {   // partial chunk: keys past the event end get -inf
+#pragma unroll
+        for (int kb = 0; kb < 8; ++kb)
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            if (kb * 16 + 4 * g + r > lim) s[kb][r] = -INFINITY;
+      }
+      float cmax = -INFINITY;
+#pragma unroll
+      for (int kb = 0; kb < 8; ++kb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) cmax = fmaxf(cmax, s[kb][r]);
+      cmax = fmaxf(cmax, __shfl_xor(cmax, 16, kWave));
+      cmax = fmaxf(cmax, __shfl_xor(cmax, 32, kWave));
+      const float m_new = fmaxf(m_run, cmax);       // finite: key c0 < nk is in this chunk
+      const float alpha = __builtin_amdgcn_exp2f((m_run - m_new) * sl2e);
+#pragma unroll
+      for (int db = 0; db < 3; ++db) o[db] *= alpha;
+      const float mb = -m_new * sl2e;
+#pragma unroll
+      for (int kb = 0; kb < 8; ++kb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) s[kb][r] = __builtin_amdgcn_exp2f(fmaf(s[kb][r], sl2e, mb));
+      m_run = m_new;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        if (2 * c >= nkb) break;
+        bf16x8 pb;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          pb[r] = (bf16)s[2 * c][r];
+          pb[4 + r] = (bf16)s[2 * c + 1][r];
+        }
+#pragma unroll
+        for (int db = 0; db < 2; ++db) {
+          const bf16x8 vf = *(const bf16x8*)&Vt[(db * 16 + j) * kLdV32 + 32 * c + 8 * g];
+          o[db] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vf, pb, o[db], 0, 0, 0);
+        }
+        o[2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ones, pb, o[2], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+
+  if (wave_active) {
+    // row 0 of the row-sum block sits in register 0 of lanes 0-15 (query j)
+    const float l = __shfl(o[2][0], j, kWave);
+    const float inv = 1.0f / l;
+    if (qi < nq) {
+      bf16* orow = O + (qs0 + qi) * ldo + h * kH32;
+#pragma unroll
+      for (int db = 0; db < 2; ++db) {
+        bf16x4 w4;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) w4[r] = (bf16)(o[db][r] * inv);
+        *(bf16x4*)(orow + db * 16 + 4 * g) = w4;
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_attn32_self(
+    const bf16* __restrict__ Q, int ldq, const bf16* __restrict__ K, const bf16* __restrict__ V,
+    int ldkv, bf16* __restrict__ O, int ldo, const int64_t* __restrict__ q_off,
+    const int64_t* __restrict__ kv_off, const int2* __restrict__ work, int n_heads, float sl2e) {
+  attention32_body(Q, ldq, K, V, ldkv, O, ldo, q_off, kv_off, work, n_heads, sl2e);
+}
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_attn32_cross(
+    const bf16* __restrict__ Q, int ldq, const bf16* __restrict__ K, const bf16* __restrict__ V,
+    int ldkv, bf16* __restrict__ O, int ldo, const int64_t* __restrict__ q_off,
+    const int64_t* __restrict__ kv_off, const int2* __restrict__ work, int n_heads, float sl2e) {
+  attention32_body(Q, ldq, K, V, ldkv, O, ldo, q_off, kv_off, work, n_heads, sl2e);
+}
+
 template <typename T, int DH>
 static hipError_t go_attn(bool cross, dim3 grid, hipStream_t st, const T* Q, int ldq,
                           const T* K, const T* V, int ldkv, T* O, int ldo, const int64_t* q_off,
@@ -221,6 +408,13 @@ static hipError_t go_attn(bool cross, dim3 grid, hipStream_t st, const T* Q, int
   return hipGetLastError();
 }
 
+int attention_query_tile(bool bf16, int dh, int n_heads) {
+  (void)bf16;
+  (void)dh;
+  (void)n_heads;
+  return QT;
+}
+
 template <typename T>
 hipError_t launch_attention(hipStream_t st, bool cross, int dh, int n_heads, int64_t n_items,
                             const int2* work, const T* Q, int ldq, const T* K, const T* V,
@@ -229,6 +423,21 @@ hipError_t launch_attention(hipStream_t st, bool cross, int dh, int n_heads, int
   if (n_items <= 0) return hipSuccess;
   if (n_items > 0x7fffffff) return hipErrorInvalidValue;
   const float sl2e = 1.4426950408889634f / sqrtf((float)dh);
+  if constexpr (std::is_same<T, bf16>::value) {
+    if (dh == kH32) {
+      // 16-byte row chunks: row pitches and head offsets are multiples of 8 elements
+      if (ldq % 8 || ldkv % 8 || ldo % 8) return hipErrorInvalidValue;
+      const int64_t blocks = n_items * n_heads;
+      if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+      if (cross)
+        hipLaunchKernelGGL(k_attn32_cross, dim3((unsigned)blocks), dim3(256), 0, st, Q, ldq, K,
+                           V, ldkv, O, ldo, q_off, kv_off, work, n_heads, sl2e);
+      else
+        hipLaunchKernelGGL(k_attn32_self, dim3((unsigned)blocks), dim3(256), 0, st, Q, ldq, K, V,
+                           ldkv, O, ldo, q_off, kv_off, work, n_heads, sl2e);
+      return hipGetLastError();
+    }
+  }
   const dim3 grid((unsigned)n_items, n_heads);
   switch (dh) {
     case 16: return go_attn<T, 16>(cross, grid, st, Q, ldq, K, V, ldkv, O, ldo, q_off, kv_off, work, sl2e);

@@ -246,7 +246,9 @@ void flush_timing(fmd_model* m) {
 int stage_events(fmd_model* m, const fmd_events_in* ev, Call& c) {
   Workspace& w = m->ws;
   const int64_t E = ev->n_events;
-  // work items: (event, 64-query tile), longest events first
+  // work items: (event, query tile), longest events first
+  const int qt = attention_query_tile(m->cfg.precision == FMD_BF16, m->cfg.d_model / std::max(m->cfg.n_heads, 1),
+                                      m->cfg.n_heads);
   std::vector<int64_t> order;
   order.reserve(E);
   int64_t items = 0;
@@ -254,7 +256,7 @@ int stage_events(fmd_model* m, const fmd_events_in* ev, Call& c) {
   for (int64_t e = 0; e < E; ++e) {
     const int64_t n = ev->offsets[e + 1] - ev->offsets[e];
     if (n > 0) order.push_back(e);
-    items += (n + 63) / 64;
+    items += (n + qt - 1) / qt;
     s2 += (double)n * (double)n;
   }
   std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
@@ -269,7 +271,7 @@ int stage_events(fmd_model* m, const fmd_events_in* ev, Call& c) {
   int64_t k = 0;
   for (int64_t e : order) {
     const int64_t n = ev->offsets[e + 1] - ev->offsets[e];
-    for (int64_t q = 0; q < (n + 63) / 64; ++q) w.h_work[k++] = make_int2((int)e, (int)q);
+    for (int64_t q = 0; q < (n + qt - 1) / qt; ++q) w.h_work[k++] = make_int2((int)e, (int)q);
   }
   HIP_TRY(hipMemcpyAsync(w.off, w.h_off, (size_t)(E + 1) * 8, hipMemcpyHostToDevice, c.st));
   if (items) HIP_TRY(hipMemcpyAsync(w.work, w.h_work, (size_t)items * sizeof(int2), hipMemcpyHostToDevice, c.st));
@@ -1020,6 +1022,9 @@ const char* fmd_kernel_name(fmd_model* m, int32_t cls) {
                                            "k_fused_mlp", "k_attn_self", "k_attn_cross",
                                            "other"};
   if (cls == FMD_K_GEMM_QKV && m && (m->fused & FMD_FUSED_QKV)) return "k_fused_qkv";
+  if ((cls == FMD_K_ATTN_SELF || cls == FMD_K_ATTN_CROSS) && m && m->kind == 0 &&
+      m->cfg.precision == FMD_BF16 && m->cfg.d_model == 32 * m->cfg.n_heads)
+    return cls == FMD_K_ATTN_SELF ? "k_attn32_self" : "k_attn32_cross";
   return cls >= 0 && cls < FMD_K_COUNT ? names[cls] : "";
 }
 
@@ -1155,11 +1160,12 @@ int fmd_debug_attention(int32_t precision, int64_t n_events, const int64_t* q_of
   if (n_heads < 1 || n_events < 0 || !q_offsets || !kv_offsets) return fail(FMD_E_INVALID, "bad arguments");
   if (q_offsets[0] != 0 || kv_offsets[0] != 0) return fail(FMD_E_INVALID, "offsets must start at 0");
   std::vector<int2> work;
+  const int qt = attention_query_tile(precision == FMD_BF16, dh, n_heads);
   for (int64_t e = 0; e < n_events; ++e) {
     const int64_t nq = q_offsets[e + 1] - q_offsets[e], nk = kv_offsets[e + 1] - kv_offsets[e];
     if (nq < 0 || nk < 0) return fail(FMD_E_INVALID, "offsets decrease");
     if (nq > 0 && nk == 0) return fail(FMD_E_INVALID, "event %lld has queries but no keys", (long long)e);
-    for (int64_t q = 0; q < (nq + 63) / 64; ++q) work.push_back(make_int2((int)e, (int)q));
+    for (int64_t q = 0; q < (nq + qt - 1) / qt; ++q) work.push_back(make_int2((int)e, (int)q));
   }
   const int64_t Tq = q_offsets[n_events], Tk = kv_offsets[n_events];
   if (work.empty()) return FMD_OK;

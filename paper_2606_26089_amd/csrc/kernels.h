@@ -78,6 +78,10 @@ int default_tile_rows(int N);   // a full-row tiling for N, or -1
 hipError_t launch_row_stats(hipStream_t st, const float* A, int ld, int K, int64_t M,
                             float2* stats);
 
+// Queries per attention work item (event, query tile) for a precision and head shape; the
+// work lists passed to launch_attention are built with this tile.
+int attention_query_tile(bool bf16, int dh, int n_heads);
+
 // Masked multi-head attention over CSR events. work: int2 (event, 64-query tile) items.
 template <typename T>
 hipError_t launch_attention(hipStream_t st, bool cross, int dh, int n_heads, int64_t n_items,

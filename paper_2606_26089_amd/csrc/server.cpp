@@ -170,6 +170,8 @@ template <typename T>
 int iterate(fmd_server* S, std::vector<Req*>& finished) {
   fmd_model* m = S->m;
   Workspace& w = m->ws;
+  const int qt = attention_query_tile(m->cfg.precision == FMD_BF16, m->cfg.d_model / m->cfg.n_heads,
+                                      m->cfg.n_heads);
   std::vector<Req*> res = S->resident;
   std::sort(res.begin(), res.end(), [](Req* a, Req* b) { return a->base < b->base; });
   // segments: dummy gaps and real events, in pool order
@@ -203,7 +205,7 @@ int iterate(fmd_server* S, std::vector<Req*>& finished) {
       desc.push_back(sd);
       tev.push_back(sd.t);
       pos += n;
-      items += (n + 63) / 64;
+      items += (n + qt - 1) / qt;
       sum_n2 += (double)n * (double)n;
     }
   }
@@ -217,7 +219,7 @@ int iterate(fmd_server* S, std::vector<Req*>& finished) {
   std::memcpy(w.h_off, off.data(), (size_t)(E + 1) * 8);
   int64_t k = 0;
   for (auto& pr : real)
-    for (int64_t q = 0; q < (pr.second + 63) / 64; ++q) w.h_work[k++] = make_int2((int)pr.first, (int)q);
+    for (int64_t q = 0; q < (pr.second + qt - 1) / qt; ++q) w.h_work[k++] = make_int2((int)pr.first, (int)q);
   if (E > w.cap_desc) {
     FMD_TRY(grow(w.desc, (size_t)E * sizeof(StageDesc)));
     FMD_TRY(grow_host(w.h_desc, (size_t)E * sizeof(StageDesc)));
