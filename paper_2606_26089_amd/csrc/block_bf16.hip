@@ -256,18 +256,52 @@ __device__ __forceinline__ void store_rows_bf16(const f32x16 (&acc)[4], bf16* __
     for (int r = 0; r < 16; ++r) *io.at(mi, r) = (bf16)acc[mi][r];
 }
 
-// GELU(z) = z/2 (1 + erf(z / sqrt 2)) with erf by Abramowitz & Stegun 7.1.26 (absolute error
-// at most 1.5e-7, far below the BF16 rounding of the result): branch-free, unlike a
-// library erf, so that the 64 lanes of a wave stay converged in the MLP epilogue.
+// GELU(z) = z/2 (1 + erf(z / sqrt 2)) with erf by Abramowitz & Stegun 7.1.25:
+// erf(x) = 1 - t (a1 + t (a2 + t a3)) exp(-x^2), t = 1 / (1 + p |x|), absolute error at most
+// 2.5e-5, far below the BF16 rounding of the result. Branch-free (a library erf branches on
+// |x|), with the hardware reciprocal and exp2: 13 vector instructions per value.
 __device__ __forceinline__ float gelu_as(float z) {
   const float x = z * 0.70710678118654752f;
-  const float a = fabsf(x);
-  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, a, 1.0f));
-  const float poly =
-      t * fmaf(t, fmaf(t, fmaf(t, fmaf(t, 1.061405429f, -1.453152027f), 1.421413741f),
-                       -0.284496736f), 0.254829592f);
-  const float e = fmaf(-poly, __builtin_amdgcn_exp2f(-a * a * 1.4426950408889634f), 1.0f);
-  return 0.5f * z * (1.0f + copysignf(e, x));
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.47047f, fabsf(x), 1.0f));
+  const float poly = t * fmaf(t, fmaf(t, 0.7478556f, -0.0958798f), 0.3480242f);
+  // exp(-x^2) = exp2(-z^2 log2(e) / 2)
+  const float ex = __builtin_amdgcn_exp2f(z * z * -0.72134752044448170f);
+  const float erf_abs = fmaf(-poly, ex, 1.0f);
+  const float hz = 0.5f * z;
+  return fmaf(hz, copysignf(erf_abs, x), hz);
+}
+
+// One up-projection chunk of the MLP (if UP): h2n = A[row0 + .., :] x W_up chunk (16
+// fragments from the ring; cur = the chunk's first fragment, next = the phase after it),
+// software-pipelined with the GELU of the previous chunk's products h2 (two values per
+// k step, + bias bv, BF16 into the LDS hidden tile hb). The MFMAs of one chunk and the
+// vector work of the other are independent, so they overlap in the SIMD.
+template <bool UP>
+__device__ __forceinline__ void up_and_gelu(f32x16 (&h2n)[2], const f32x16 (&h2)[2],
+                                            const bf16* __restrict__ A, int row0,
+                                            u32x4 (&ring)[kRing],
+                                            const u32x4* __restrict__ cur,
+                                            const u32x4* __restrict__ next, float bv,
+                                            bf16* __restrict__ hb, int hcol, int lane) {
+  asm volatile("" ::: "memory");
+  const bf16* arow = A + (row0 + (lane & 31)) * kLdA + (lane >> 5) * 8;
+#pragma unroll
+  for (int ks = 0; ks < kKs; ++ks) {
+    if constexpr (UP) {
+      const bf16x8 a0 = *(const bf16x8*)(arow + ks * 16);
+      const bf16x8 a1 = *(const bf16x8*)(arow + 32 * kLdA + ks * 16);
+      const bf16x8 b = as_bf16x8(ring[ks % kRing]);
+      const u32x4* src = ks + kRing < kKs ? cur + (ks + kRing) * 64 : next + (ks + kRing - kKs) * 64;
+      ring[ks % kRing] = src[lane];
+      h2n[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b, h2n[0], 0, 0, 0);
+      h2n[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b, h2n[1], 0, 0, 0);
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int v = 2 * ks + q, mi = v >> 4, r = v & 15;
+      hb[(row0 + acc_row(mi, r, lane)) * kLdH + hcol] = (bf16)gelu_as(h2[mi][r] + bv);
+    }
+  }
 }
 
 struct SharedLn {
@@ -373,26 +407,38 @@ __global__ __launch_bounds__(kThreads) void k_fused_mlp(
   ln_to_lds(acc, sl.mu, sl.rs, g, s, A, col, lane);
   __syncthreads();
   const int hcol = wn * 32 + (lane & 31);
+  auto up_c = [&](int c) { return wup + c * (kBH / 32) * kKs * 64; };
+  auto dn_c = [&](int c) { return wdn + c * kDnKs * 64; };
+  // chunk c: [up-projection of chunk c+1 | GELU of chunk c] -> barrier -> down-projection of
+  // chunk c. Weight stream order: up 0, up 1, down 0, up 2, down 1, ..., up 7, down 6, down 7.
+  f32x16 h2[2][2];
+#pragma unroll
+  for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) h2[0][mi][r] = 0.f;
+  mfma_phase<2>(h2[0], A, kLdA, wm * 64, kUpKs, ring, up_c(0), up_c(1), lane);
 #pragma unroll 1
-  for (int c = 0; c < kChunks; ++c) {
-    bf16* hb = Hc[c & 1];
-    f32x16 h2[2];
+  for (int c = 0; c < kChunks; c += 2) {
 #pragma unroll
-    for (int mi = 0; mi < 2; ++mi)
+    for (int u = 0; u < 2; ++u) {     // chunk c + u; h2[u] holds its products
+      const int cc = c + u;
+      bf16* hb = Hc[u];
+      const float bv = b_up[cc * kBH + hcol];
+      if (cc + 1 < kChunks) {
 #pragma unroll
-      for (int r = 0; r < 16; ++r) h2[mi][r] = 0.f;
-    const u32x4* up_c = wup + c * (kBH / 32) * kKs * 64;
-    const u32x4* dn_c = wdn + c * kDnKs * 64;
-    mfma_phase<2>(h2, A, kLdA, wm * 64, kUpKs, ring, up_c, dn_c, lane);
-    const float bv = b_up[c * kBH + hcol];
+        for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
-    for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-      for (int r = 0; r < 16; ++r)
-        hb[(wm * 64 + acc_row(mi, r, lane)) * kLdH + hcol] = (bf16)gelu_as(h2[mi][r] + bv);
-    __syncthreads();
-    mfma_phase<4>(acc, hb, kLdH, 0, kDnKs, ring, dn_c,
-                  c + 1 < kChunks ? up_c + (kBH / 32) * kKs * 64 : dn_c, lane);
+          for (int r = 0; r < 16; ++r) h2[u ^ 1][mi][r] = 0.f;
+        up_and_gelu<true>(h2[u ^ 1], h2[u], A, wm * 64, ring, up_c(cc + 1), dn_c(cc), bv, hb,
+                          hcol, lane);
+      } else {
+        up_and_gelu<false>(h2[u ^ 1], h2[u], A, wm * 64, ring, dn_c(cc), dn_c(cc), bv, hb,
+                           hcol, lane);
+      }
+      __syncthreads();
+      const u32x4* nxt = cc + 2 < kChunks ? up_c(cc + 2) : dn_c(cc + 1 < kChunks ? cc + 1 : cc);
+      mfma_phase<4>(acc, hb, kLdH, 0, kDnKs, ring, dn_c(cc), nxt, lane);
+    }
   }
   const float bv = b_dn[col];
 #pragma unroll
