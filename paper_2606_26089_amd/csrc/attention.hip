@@ -273,7 +273,8 @@ __device__ __forceinline__ void attention32_body(
   for (int i = 0; i < 8; ++i) ones[i] = (bf16)(j == 0 ? 1.f : 0.f);
 
   for (int c0 = 0; c0 < nk; c0 += kKc2) {
-    // Rows past the event end are read clamped to its last row and zeroed.
+    // Rows past the event end are read clamped to its last row: real, finite data whose
+    // scores are masked to -inf below, so their P is exactly 0 and 0 x V adds nothing.
     const int lim = nk - 1 - c0;
     if (wave >= 2) {   // K: 128 keys x 4 chunks of 16 bytes
       const char* kc = (const char*)(Kp + (ks0 + c0) * ldkv + h * kH32);
@@ -283,7 +284,6 @@ __device__ __forceinline__ void attention32_body(
       for (int i = 0; i < 4; ++i) {
         const int idx = t2 + i * 128, row = idx >> 2, ch = idx & 3;
         v[i] = *(const u32x4*)(kc + (uint32_t)((min(row, lim) * ldkv + ch * 8) * 2));
-        if (row > lim) v[i] = u32x4{0u, 0u, 0u, 0u};
       }
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
@@ -298,7 +298,6 @@ __device__ __forceinline__ void attention32_body(
       for (int r = 0; r < 4; ++r) {
         const int key = kg * 4 + r;
         v[r] = *(const u32x4*)(vc + (uint32_t)((min(key, lim) * ldkv + dg * 8) * 2));
-        if (key > lim) v[r] = u32x4{0u, 0u, 0u, 0u};
       }
       const int pos = vt_pos(kg * 4);
 #pragma unroll
@@ -311,15 +310,13 @@ __device__ __forceinline__ void attention32_body(
     }
     __syncthreads();
     if (wave_active) {
-      const int nkb = min(kKc2, lim + 1 + 15) >> 4;   // 16-key blocks holding real keys
+      // all 8 key blocks, also past the event end: no branches, and the zero accumulator
+      // is an inline constant
       f32x4 s[8];
 #pragma unroll
       for (int kb = 0; kb < 8; ++kb) {
-        s[kb] = f32x4{0.f, 0.f, 0.f, 0.f};
-        if (kb < nkb) {
-          const bf16x8 kf = *(const bf16x8*)&Ks[(kb * 16 + j) * kLdK32 + 8 * g];
-          s[kb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kf, qf, s[kb], 0, 0, 0);
-        }
+        const bf16x8 kf = *(const bf16x8*)&Ks[(kb * 16 + j) * kLdK32 + 8 * g];
+        s[kb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kf, qf, f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
       }
       if (lim < kKc2 - 1) {   // partial chunk: keys past the event end get -inf
 #pragma unroll
@@ -347,7 +344,6 @@ __device__ __forceinline__ void attention32_body(
       m_run = m_new;
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        if (2 * c >= nkb) break;
         bf16x8 pb;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {

@@ -105,29 +105,32 @@ struct RowIo {
 };
 
 // acc = rows m0.. of X (FP32, pitch kD) at the wave's columns, plus bias (may be null).
-__device__ __forceinline__ void load_rows(f32x16 (&acc)[4], const float* __restrict__ X,
+template <int TM>
+__device__ __forceinline__ void load_rows(f32x16 (&acc)[TM], const float* __restrict__ X,
                                           int64_t m0, int col,
                                           const float* __restrict__ bias, int lane) {
   const float bv = bias ? bias[col] : 0.f;
   const RowIo<float, kD> io(X, m0, col, lane);
 #pragma unroll
-  for (int mi = 0; mi < 4; ++mi)
+  for (int mi = 0; mi < TM; ++mi)
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[mi][r] = *io.at(mi, r) + bv;
 }
 
-__device__ __forceinline__ void zero(f32x16 (&acc)[4], const float* __restrict__ bias, int col) {
+template <int TM>
+__device__ __forceinline__ void zero(f32x16 (&acc)[TM], const float* __restrict__ bias, int col) {
   const float bv = bias ? bias[col] : 0.f;
 #pragma unroll
-  for (int mi = 0; mi < 4; ++mi)
+  for (int mi = 0; mi < TM; ++mi)
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[mi][r] = bv;
 }
 
-// 128 x 256 BF16 tile of S (pitch lds_) at rows m0.. into LDS (pitch kLdA).
+// ROWS x 256 BF16 tile of S (pitch lds_) at rows m0.. into LDS (pitch kLdA).
+template <int ROWS>
 __device__ __forceinline__ void tile_to_lds(bf16* __restrict__ A, const bf16* __restrict__ S,
                                             int lds_, int64_t m0, int tid) {
-  constexpr int kChunks = kBM * kD / 8;                 // 16-byte chunks
+  constexpr int kChunks = ROWS * kD / 8;                // 16-byte chunks
   constexpr int kPer = kChunks / kThreads;
   u32x4 v[kPer];
 #pragma unroll
@@ -160,18 +163,20 @@ __device__ __forceinline__ void transpose_reduce32_v2(float (&v)[32], int lane) 
   }
 }
 
+template <int ROWS>
 __device__ __forceinline__ void row_partials(float (&v)[32], float* __restrict__ red, int g,
                                              int lane, int w) {
   transpose_reduce32_v2(v, lane);
   const int j = lane & 31;
-  red[w * kBM + acc_row(2 * g + (j >> 4), j & 15, lane)] = v[0];
+  red[w * ROWS + acc_row(2 * g + (j >> 4), j & 15, lane)] = v[0];
 }
 
-// LayerNorm statistics of the 128 full rows held in acc: mean and 1/sqrt(biased variance +
+// LayerNorm statistics of the 32 TM full rows held in acc: mean and 1/sqrt(biased variance +
 // eps) into mu[] / rs[] (LDS), optionally also to stats_out[m0 + row]. Per-wave partial
 // sums over the wave's 32 columns by a transpose-reduction, then across the 8 waves through
 // red[]. Ends with a barrier (mu/rs visible to all waves).
-__device__ __forceinline__ void row_stats(const f32x16 (&acc)[4], float* __restrict__ red,
+template <int TM>
+__device__ __forceinline__ void row_stats(const f32x16 (&acc)[TM], float* __restrict__ red,
                                           float* __restrict__ mu, float* __restrict__ rs,
                                           float2* __restrict__ stats_out, int64_t m0,
                                           int lane, int w, int tid) {
@@ -179,27 +184,29 @@ __device__ __forceinline__ void row_stats(const f32x16 (&acc)[4], float* __restr
   // exact on the lane that keeps the partial sum and rounded on the lane that sends it, so
   // the statistics would depend on the row's position in the tile.
 #pragma clang fp contract(off)
+  static_assert(TM % 2 == 0, "row statistics take 32-value groups of two fragments");
+  constexpr int ROWS = 32 * TM;
   // pass 1: row sums
 #pragma unroll
-  for (int g = 0; g < 2; ++g) {
+  for (int g = 0; g < TM / 2; ++g) {
     float v[32];
 #pragma unroll
     for (int h = 0; h < 2; ++h)
 #pragma unroll
       for (int r = 0; r < 16; ++r) v[h * 16 + r] = acc[2 * g + h][r];
-    row_partials(v, red, g, lane, w);
+    row_partials<ROWS>(v, red, g, lane, w);
   }
   __syncthreads();
-  if (tid < kBM) {
+  if (tid < ROWS) {
     float t = 0.f;
 #pragma unroll
-    for (int q = 0; q < kWaves; ++q) t += red[q * kBM + tid];
+    for (int q = 0; q < kWaves; ++q) t += red[q * ROWS + tid];
     mu[tid] = t * (1.0f / kD);
   }
   __syncthreads();
   // pass 2: sums of squared deviations
 #pragma unroll
-  for (int g = 0; g < 2; ++g) {
+  for (int g = 0; g < TM / 2; ++g) {
     float v[32];
 #pragma unroll
     for (int h = 0; h < 2; ++h)
@@ -208,13 +215,13 @@ __device__ __forceinline__ void row_stats(const f32x16 (&acc)[4], float* __restr
         const float dv = acc[2 * g + h][r] - mu[acc_row(2 * g + h, r, lane)];
         v[h * 16 + r] = dv * dv;
       }
-    row_partials(v, red, g, lane, w);
+    row_partials<ROWS>(v, red, g, lane, w);
   }
   __syncthreads();
-  if (tid < kBM) {
+  if (tid < ROWS) {
     float t = 0.f;
 #pragma unroll
-    for (int q = 0; q < kWaves; ++q) t += red[q * kBM + tid];
+    for (int q = 0; q < kWaves; ++q) t += red[q * ROWS + tid];
     rs[tid] = rsqrtf(t * (1.0f / kD) + kLnEps);
     if (stats_out) stats_out[m0 + tid] = make_float2(mu[tid], rs[tid]);
   }
@@ -222,14 +229,15 @@ __device__ __forceinline__ void row_stats(const f32x16 (&acc)[4], float* __restr
 }
 
 // LDS tile A (pitch kLdA) = LayerNorm(acc rows) with gain g and shift s, in BF16.
-__device__ __forceinline__ void ln_to_lds(const f32x16 (&acc)[4], const float* __restrict__ mu,
+template <int TM>
+__device__ __forceinline__ void ln_to_lds(const f32x16 (&acc)[TM], const float* __restrict__ mu,
                                           const float* __restrict__ rs,
                                           const float* __restrict__ g,
                                           const float* __restrict__ s, bf16* __restrict__ A,
                                           int col, int lane) {
   const float gv = g[col], sv = s[col];
 #pragma unroll
-  for (int mi = 0; mi < 4; ++mi)
+  for (int mi = 0; mi < TM; ++mi)
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int row = acc_row(mi, r, lane);
@@ -237,21 +245,22 @@ __device__ __forceinline__ void ln_to_lds(const f32x16 (&acc)[4], const float* _
     }
 }
 
-__device__ __forceinline__ void store_rows_f32(const f32x16 (&acc)[4], float* __restrict__ X,
+template <int TM>
+__device__ __forceinline__ void store_rows_f32(const f32x16 (&acc)[TM], float* __restrict__ X,
                                                int64_t m0, int col, int lane) {
   const RowIo<float, kD> io(X, m0, col, lane);
 #pragma unroll
-  for (int mi = 0; mi < 4; ++mi)
+  for (int mi = 0; mi < TM; ++mi)
 #pragma unroll
     for (int r = 0; r < 16; ++r) *io.at(mi, r) = acc[mi][r];
 }
 
-template <int LD>
-__device__ __forceinline__ void store_rows_bf16(const f32x16 (&acc)[4], bf16* __restrict__ X,
+template <int LD, int TM>
+__device__ __forceinline__ void store_rows_bf16(const f32x16 (&acc)[TM], bf16* __restrict__ X,
                                                 int64_t m0, int col, int lane) {
   const RowIo<bf16, LD> io(X, m0, col, lane);
 #pragma unroll
-  for (int mi = 0; mi < 4; ++mi)
+  for (int mi = 0; mi < TM; ++mi)
 #pragma unroll
     for (int r = 0; r < 16; ++r) *io.at(mi, r) = (bf16)acc[mi][r];
 }
@@ -314,22 +323,24 @@ struct SharedLn {
 
 // ---------------------------------------------------------------------------------------
 
+template <int TM>
 __global__ __launch_bounds__(kThreads) void k_fused_qkv(const float* __restrict__ H,
                                                         const float* __restrict__ g,
                                                         const float* __restrict__ s,
                                                         const u32x4* __restrict__ Wf,
                                                         const float* __restrict__ bias,
                                                         bf16* __restrict__ qkv) {
-  __shared__ __attribute__((aligned(16))) bf16 A[kBM * kLdA];
+  constexpr int ROWS = 32 * TM;
+  __shared__ __attribute__((aligned(16))) bf16 A[ROWS * kLdA];
   __shared__ SharedLn sl;
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int64_t m0 = (int64_t)blockIdx.x * kBM;
+  const int64_t m0 = (int64_t)blockIdx.x * ROWS;
   const int col = w * 32 + (lane & 31);
   const u32x4* wf = Wf + w * kKs * 64;            // slab s: + s * kWaves * kKs * 64
   u32x4 ring[kRing];
   ring_fill(ring, wf, lane);
-  f32x16 acc[4];
+  f32x16 acc[TM];
   load_rows(acc, H, m0, col, nullptr, lane);
   row_stats(acc, sl.red, sl.mu, sl.rs, nullptr, m0, lane, w, tid);
   ln_to_lds(acc, sl.mu, sl.rs, g, s, A, col, lane);
@@ -338,38 +349,40 @@ __global__ __launch_bounds__(kThreads) void k_fused_qkv(const float* __restrict_
   for (int slab = 0; slab < 3; ++slab) {
     zero(acc, bias, slab * kD + col);
     const u32x4* cur = wf + slab * kWaves * kKs * 64;
-    mfma_phase<4>(acc, A, kLdA, 0, kKs, ring, cur, slab < 2 ? cur + kWaves * kKs * 64 : cur,
+    mfma_phase<TM>(acc, A, kLdA, 0, kKs, ring, cur, slab < 2 ? cur + kWaves * kKs * 64 : cur,
                   lane);
     store_rows_bf16<3 * kD>(acc, qkv, m0, slab * kD + col, lane);
   }
 }
 
+template <int TM>
 __global__ __launch_bounds__(kThreads) void k_fused_oqc(
     const bf16* __restrict__ att, const u32x4* __restrict__ Wf_o, const float* __restrict__ b_o,
     float* __restrict__ H, const float* __restrict__ g, const float* __restrict__ s,
     const u32x4* __restrict__ Wf_qc, const float* __restrict__ b_qc, bf16* __restrict__ qc) {
-  __shared__ __attribute__((aligned(16))) bf16 A[kBM * kLdA];
+  constexpr int ROWS = 32 * TM;
+  __shared__ __attribute__((aligned(16))) bf16 A[ROWS * kLdA];
   __shared__ SharedLn sl;
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int64_t m0 = (int64_t)blockIdx.x * kBM;
+  const int64_t m0 = (int64_t)blockIdx.x * ROWS;
   const int col = w * 32 + (lane & 31);
   const u32x4* wo = Wf_o + w * kKs * 64;
   const u32x4* wq = Wf_qc + w * kKs * 64;
   u32x4 ring[kRing];
   ring_fill(ring, wo, lane);
-  tile_to_lds(A, att, kD, m0, tid);
-  f32x16 acc[4];
+  tile_to_lds<ROWS>(A, att, kD, m0, tid);
+  f32x16 acc[TM];
   load_rows(acc, H, m0, col, b_o, lane);
   __syncthreads();
-  mfma_phase<4, false>(acc, A, kLdA, 0, kKs, ring, wo, wo, lane);
+  mfma_phase<TM, false>(acc, A, kLdA, 0, kKs, ring, wo, wo, lane);
   store_rows_f32(acc, H, m0, col, lane);
   row_stats(acc, sl.red, sl.mu, sl.rs, nullptr, m0, lane, w, tid);   // barrier: A reads done
   ring_fill(ring, wq, lane);
   ln_to_lds(acc, sl.mu, sl.rs, g, s, A, col, lane);
   __syncthreads();
   zero(acc, b_qc, col);
-  mfma_phase<4>(acc, A, kLdA, 0, kKs, ring, wq, wq, lane);
+  mfma_phase<TM>(acc, A, kLdA, 0, kKs, ring, wq, wq, lane);
   store_rows_bf16<kD>(acc, qc, m0, col, lane);
 }
 
@@ -397,7 +410,7 @@ __global__ __launch_bounds__(kThreads) void k_fused_mlp(
   const u32x4* wdn = Wf_dn + w * (4 * kD / 16) * 64; // + c * kDnKs * 64
   u32x4 ring[kRing];
   ring_fill(ring, woc, lane);
-  tile_to_lds(A, att, kD, m0, tid);
+  tile_to_lds<kBM>(A, att, kD, m0, tid);
   f32x16 acc[4];
   load_rows(acc, H, m0, col, b_oc, lane);
   __syncthreads();
@@ -475,11 +488,15 @@ hipError_t launch_pack_frag(hipStream_t st, const float* W, int K, int N, void* 
   return hipGetLastError();
 }
 
+// 64-row tiles for the two HBM-bound kernels: half the accumulator, so two workgroups share a
+// CU and one's loads overlap the other's products
+constexpr int kTmIo = 2;
+
 hipError_t launch_fused_qkv(hipStream_t st, int64_t Mp, const float* H, const float* g,
                             const float* s, const void* Wf, const float* bias, void* qkv) {
-  if (Mp % kBM) return hipErrorInvalidValue;
+  if (Mp % (32 * kTmIo)) return hipErrorInvalidValue;
   if (Mp == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fused_qkv, dim3((unsigned)(Mp / kBM)), dim3(kThreads), 0, st, H, g, s,
+  hipLaunchKernelGGL(k_fused_qkv<kTmIo>, dim3((unsigned)(Mp / (32 * kTmIo))), dim3(kThreads), 0, st, H, g, s,
                      (const u32x4*)Wf, bias, (bf16*)qkv);
   return hipGetLastError();
 }
@@ -487,9 +504,9 @@ hipError_t launch_fused_qkv(hipStream_t st, int64_t Mp, const float* H, const fl
 hipError_t launch_fused_oqc(hipStream_t st, int64_t Mp, const void* att, const void* Wf_o,
                             const float* b_o, float* H, const float* g, const float* s,
                             const void* Wf_qc, const float* b_qc, void* qc) {
-  if (Mp % kBM) return hipErrorInvalidValue;
+  if (Mp % (32 * kTmIo)) return hipErrorInvalidValue;
   if (Mp == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fused_oqc, dim3((unsigned)(Mp / kBM)), dim3(kThreads), 0, st,
+  hipLaunchKernelGGL(k_fused_oqc<kTmIo>, dim3((unsigned)(Mp / (32 * kTmIo))), dim3(kThreads), 0, st,
                      (const bf16*)att, (const u32x4*)Wf_o, b_o, H, g, s, (const u32x4*)Wf_qc,
                      b_qc, (bf16*)qc);
   return hipGetLastError();
