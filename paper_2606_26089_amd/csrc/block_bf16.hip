@@ -285,8 +285,8 @@ __device__ __forceinline__ float gelu_as(float z) {
 // software-pipelined with the GELU of the previous chunk's products h2 (two values per
 // k step, + bias bv, BF16 into the LDS hidden tile hb). The MFMAs of one chunk and the
 // vector work of the other are independent, so they overlap in the SIMD.
-template <bool UP>
-__device__ __forceinline__ void up_and_gelu(f32x16 (&h2n)[2], const f32x16 (&h2)[2],
+template <bool UP, int TA>
+__device__ __forceinline__ void up_and_gelu(f32x16 (&h2n)[TA], const f32x16 (&h2)[TA],
                                             const bf16* __restrict__ A, int row0,
                                             u32x4 (&ring)[kRing],
                                             const u32x4* __restrict__ cur,
@@ -297,17 +297,19 @@ __device__ __forceinline__ void up_and_gelu(f32x16 (&h2n)[2], const f32x16 (&h2)
 #pragma unroll
   for (int ks = 0; ks < kKs; ++ks) {
     if constexpr (UP) {
-      const bf16x8 a0 = *(const bf16x8*)(arow + ks * 16);
-      const bf16x8 a1 = *(const bf16x8*)(arow + 32 * kLdA + ks * 16);
+      bf16x8 a[TA];
+#pragma unroll
+      for (int mi = 0; mi < TA; ++mi) a[mi] = *(const bf16x8*)(arow + mi * 32 * kLdA + ks * 16);
       const bf16x8 b = as_bf16x8(ring[ks % kRing]);
       const u32x4* src = ks + kRing < kKs ? cur + (ks + kRing) * 64 : next + (ks + kRing - kKs) * 64;
       ring[ks % kRing] = src[lane];
-      h2n[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b, h2n[0], 0, 0, 0);
-      h2n[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b, h2n[1], 0, 0, 0);
+#pragma unroll
+      for (int mi = 0; mi < TA; ++mi)
+        h2n[mi] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[mi], b, h2n[mi], 0, 0, 0);
     }
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int v = 2 * ks + q, mi = v >> 4, r = v & 15;
+    for (int q = 0; q < TA; ++q) {     // 16 TA values of h2 over the 16 k steps
+      const int v = TA * ks + q, mi = v >> 4, r = v & 15;
       hb[(row0 + acc_row(mi, r, lane)) * kLdH + hcol] = (bf16)gelu_as(h2[mi][r] + bv);
     }
   }
@@ -386,19 +388,21 @@ __global__ __launch_bounds__(kThreads) void k_fused_oqc(
   store_rows_bf16<kD>(acc, qc, m0, col, lane);
 }
 
+template <int TM>
 __global__ __launch_bounds__(kThreads) void k_fused_mlp(
     const bf16* __restrict__ att, const u32x4* __restrict__ Wf_oc, const float* __restrict__ b_oc,
     float* __restrict__ H, const float* __restrict__ g, const float* __restrict__ s,
     const u32x4* __restrict__ Wf_up, const float* __restrict__ b_up,
     const u32x4* __restrict__ Wf_dn, const float* __restrict__ b_dn,
     float2* __restrict__ stats_out) {
-  __shared__ __attribute__((aligned(16))) bf16 A[kBM * kLdA];
-  __shared__ __attribute__((aligned(16))) bf16 Hc[2][kBM * kLdH];
+  constexpr int ROWS = 32 * TM, TA = TM / 2;   // hidden-chunk products: 2 x 4 waves
+  __shared__ __attribute__((aligned(16))) bf16 A[ROWS * kLdA];
+  __shared__ __attribute__((aligned(16))) bf16 Hc[2][ROWS * kLdH];
   __shared__ SharedLn sl;
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int wm = w >> 2, wn = w & 3;        // hidden-chunk products: 2 x 4 waves of 64 x 32
-  const int64_t m0 = (int64_t)blockIdx.x * kBM;
+  const int wm = w >> 2, wn = w & 3;        // of ROWS/2 x 32
+  const int64_t m0 = (int64_t)blockIdx.x * ROWS;
   const int col = w * 32 + (lane & 31);
   constexpr int kChunks = 4 * kD / kBH;      // 8
   constexpr int kUpKs = kKs;                 // 16 fragments per up-projection chunk
@@ -410,11 +414,11 @@ __global__ __launch_bounds__(kThreads) void k_fused_mlp(
   const u32x4* wdn = Wf_dn + w * (4 * kD / 16) * 64; // + c * kDnKs * 64
   u32x4 ring[kRing];
   ring_fill(ring, woc, lane);
-  tile_to_lds<kBM>(A, att, kD, m0, tid);
-  f32x16 acc[4];
+  tile_to_lds<ROWS>(A, att, kD, m0, tid);
+  f32x16 acc[TM];
   load_rows(acc, H, m0, col, b_oc, lane);
   __syncthreads();
-  mfma_phase<4, false>(acc, A, kLdA, 0, kKs, ring, woc, woc, lane);
+  mfma_phase<TM, false>(acc, A, kLdA, 0, kKs, ring, woc, woc, lane);
   row_stats(acc, sl.red, sl.mu, sl.rs, nullptr, m0, lane, w, tid);   // barrier: A reads done
   ring_fill(ring, wup, lane);
   ln_to_lds(acc, sl.mu, sl.rs, g, s, A, col, lane);
@@ -424,12 +428,12 @@ __global__ __launch_bounds__(kThreads) void k_fused_mlp(
   auto dn_c = [&](int c) { return wdn + c * kDnKs * 64; };
   // chunk c: [up-projection of chunk c+1 | GELU of chunk c] -> barrier -> down-projection of
   // chunk c. Weight stream order: up 0, up 1, down 0, up 2, down 1, ..., up 7, down 6, down 7.
-  f32x16 h2[2][2];
+  f32x16 h2[2][TA];
 #pragma unroll
-  for (int mi = 0; mi < 2; ++mi)
+  for (int mi = 0; mi < TA; ++mi)
 #pragma unroll
     for (int r = 0; r < 16; ++r) h2[0][mi][r] = 0.f;
-  mfma_phase<2>(h2[0], A, kLdA, wm * 64, kUpKs, ring, up_c(0), up_c(1), lane);
+  mfma_phase<TA>(h2[0], A, kLdA, wm * 16 * TM, kUpKs, ring, up_c(0), up_c(1), lane);
 #pragma unroll 1
   for (int c = 0; c < kChunks; c += 2) {
 #pragma unroll
@@ -439,23 +443,23 @@ __global__ __launch_bounds__(kThreads) void k_fused_mlp(
       const float bv = b_up[cc * kBH + hcol];
       if (cc + 1 < kChunks) {
 #pragma unroll
-        for (int mi = 0; mi < 2; ++mi)
+        for (int mi = 0; mi < TA; ++mi)
 #pragma unroll
           for (int r = 0; r < 16; ++r) h2[u ^ 1][mi][r] = 0.f;
-        up_and_gelu<true>(h2[u ^ 1], h2[u], A, wm * 64, ring, up_c(cc + 1), dn_c(cc), bv, hb,
-                          hcol, lane);
+        up_and_gelu<true>(h2[u ^ 1], h2[u], A, wm * 16 * TM, ring, up_c(cc + 1), dn_c(cc), bv,
+                          hb, hcol, lane);
       } else {
-        up_and_gelu<false>(h2[u ^ 1], h2[u], A, wm * 64, ring, dn_c(cc), dn_c(cc), bv, hb,
+        up_and_gelu<false>(h2[u ^ 1], h2[u], A, wm * 16 * TM, ring, dn_c(cc), dn_c(cc), bv, hb,
                            hcol, lane);
       }
       __syncthreads();
       const u32x4* nxt = cc + 2 < kChunks ? up_c(cc + 2) : dn_c(cc + 1 < kChunks ? cc + 1 : cc);
-      mfma_phase<4>(acc, hb, kLdH, 0, kDnKs, ring, dn_c(cc), nxt, lane);
+      mfma_phase<TM>(acc, hb, kLdH, 0, kDnKs, ring, dn_c(cc), nxt, lane);
     }
   }
   const float bv = b_dn[col];
 #pragma unroll
-  for (int mi = 0; mi < 4; ++mi)
+  for (int mi = 0; mi < TM; ++mi)
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[mi][r] += bv;
   store_rows_f32(acc, H, m0, col, lane);
@@ -491,6 +495,9 @@ hipError_t launch_pack_frag(hipStream_t st, const float* W, int K, int N, void* 
 // 64-row tiles for the two HBM-bound kernels: half the accumulator, so two workgroups share a
 // CU and one's loads overlap the other's products
 constexpr int kTmIo = 2;
+// The MLP kernel stays on 128-row tiles: at 64 rows it needs ~180 registers (one workgroup
+// per CU either way) and reads the weights twice as often; measured 15% slower.
+constexpr int kTmMlp = 4;
 
 hipError_t launch_fused_qkv(hipStream_t st, int64_t Mp, const float* H, const float* g,
                             const float* s, const void* Wf, const float* bias, void* qkv) {
@@ -516,9 +523,9 @@ hipError_t launch_fused_mlp(hipStream_t st, int64_t Mp, const void* att, const v
                             const float* b_oc, float* H, const float* g, const float* s,
                             const void* Wf_up, const float* b_up, const void* Wf_dn,
                             const float* b_dn, float2* stats_out) {
-  if (Mp % kBM) return hipErrorInvalidValue;
+  if (Mp % (32 * kTmMlp)) return hipErrorInvalidValue;
   if (Mp == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fused_mlp, dim3((unsigned)(Mp / kBM)), dim3(kThreads), 0, st,
+  hipLaunchKernelGGL(k_fused_mlp<kTmMlp>, dim3((unsigned)(Mp / (32 * kTmMlp))), dim3(kThreads), 0, st,
                      (const bf16*)att, (const u32x4*)Wf_oc, b_oc, H, g, s,
                      (const u32x4*)Wf_up, b_up, (const u32x4*)Wf_dn, b_dn, stats_out);
   return hipGetLastError();
