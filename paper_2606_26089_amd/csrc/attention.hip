@@ -222,9 +222,10 @@ FMD_ATTN_KERNEL(k_attn_cross)
 //    position 8 g + 4 hi + r): the eight keys lane group g feeds to one MFMA are adjacent,
 //    so each V^T operand is one 16-byte LDS read.
 //  - The softmax runs on unscaled scores: one multiply-add forms the exp2 argument
-//    (s - max) * scale, masking happens only in an event's last, partial chunk, and the
-//    hardware exp2 is used (arguments <= 0). The row sums of P come from the P V product
-//    itself, through a third 16-row block of V^T whose first row is all ones.
+//    (s - max) * scale, and the hardware exp2 is used (arguments <= 0). The row sums of P
+//    come from the P V product itself, through a third 16-row block of V^T whose first row
+//    is the key validity. Keys past the event end repeat its last key (clamped reads) and
+//    have zero V and validity, so there is no per-score masking.
 namespace {
 constexpr int kH32 = 32;
 constexpr int kKc2 = 128;           // keys per chunk
@@ -243,9 +244,12 @@ __device__ __forceinline__ void attention32_body(
     const int64_t* __restrict__ q_off, const int64_t* __restrict__ kv_off,
     const int2* __restrict__ work, int n_heads, float sl2e) {
   __shared__ __attribute__((aligned(16))) bf16 Ks[kKc2 * kLdK32];
-  __shared__ __attribute__((aligned(16))) bf16 Vt[kH32 * kLdV32];
+  // V^T rows 0-31; row 32 = key validity (1 for a key of the event, 0 past its end), rows
+  // 33-47 = 0: the A operand of the row-sum block of P V
+  __shared__ __attribute__((aligned(16))) bf16 Vt[(kH32 + 16) * kLdV32];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, j = lane & 15;
+  for (int i = tid; i < 15 * kLdV32; i += 256) Vt[(kH32 + 1) * kLdV32 + i] = (bf16)0.f;
   const int L = blockIdx.x;
   const int2 wk = work[L / n_heads];
   const int h = L % n_heads;
@@ -267,14 +271,11 @@ __device__ __forceinline__ void attention32_body(
   // o[0], o[1]: output dims 0-15, 16-31; o[2] row 0 (lanes 0-15, register 0): sum of P
   f32x4 o[3] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f},
                 f32x4{0.f, 0.f, 0.f, 0.f}};
-  // A operand of the row-sum block: V^T row 32 = ones (lanes 0 and 16 .. of row j = 0)
-  bf16x8 ones;
-#pragma unroll
-  for (int i = 0; i < 8; ++i) ones[i] = (bf16)(j == 0 ? 1.f : 0.f);
 
   for (int c0 = 0; c0 < nk; c0 += kKc2) {
-    // Rows past the event end are read clamped to its last row: real, finite data whose
-    // scores are masked to -inf below, so their P is exactly 0 and 0 x V adds nothing.
+    // Keys past the event end are read clamped to its last key: their scores repeat a real
+    // score (the running max is unchanged), and their V rows and validity are zero, so they
+    // add nothing to P V or to the row sums. No per-score masking is needed.
     const int lim = nk - 1 - c0;
     if (wave >= 2) {   // K: 128 keys x 4 chunks of 16 bytes
       const char* kc = (const char*)(Kp + (ks0 + c0) * ldkv + h * kH32);
@@ -298,8 +299,15 @@ __device__ __forceinline__ void attention32_body(
       for (int r = 0; r < 4; ++r) {
         const int key = kg * 4 + r;
         v[r] = *(const u32x4*)(vc + (uint32_t)((min(key, lim) * ldkv + dg * 8) * 2));
+        if (key > lim) v[r] = u32x4{0u, 0u, 0u, 0u};
       }
       const int pos = vt_pos(kg * 4);
+      if (dg == 0) {
+        bf16x4 valid;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) valid[r] = (bf16)(kg * 4 + r <= lim ? 1.f : 0.f);
+        *(bf16x4*)&Vt[kH32 * kLdV32 + pos] = valid;
+      }
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
         bf16x4 w4;
@@ -317,13 +325,6 @@ __device__ __forceinline__ void attention32_body(
       for (int kb = 0; kb < 8; ++kb) {
         const bf16x8 kf = *(const bf16x8*)&Ks[(kb * 16 + j) * kLdK32 + 8 * g];
         s[kb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kf, qf, f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
-      }
-      if (lim < kKc2 - 1) {   // partial chunk: keys past the event end get -inf
-#pragma unroll
-        for (int kb = 0; kb < 8; ++kb)
-#pragma unroll
-          for (int r = 0; r < 4; ++r)
-            if (kb * 16 + 4 * g + r > lim) s[kb][r] = -INFINITY;
       }
       float cmax = -INFINITY;
 #pragma unroll
@@ -355,7 +356,8 @@ __device__ __forceinline__ void attention32_body(
           const bf16x8 vf = *(const bf16x8*)&Vt[(db * 16 + j) * kLdV32 + 32 * c + 8 * g];
           o[db] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vf, pb, o[db], 0, 0, 0);
         }
-        o[2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ones, pb, o[2], 0, 0, 0);
+        const bf16x8 vld = *(const bf16x8*)&Vt[(kH32 + j) * kLdV32 + 32 * c + 8 * g];
+        o[2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vld, pb, o[2], 0, 0, 0);
       }
     }
     __syncthreads();
