@@ -15,6 +15,9 @@
 //   FP32: v_mfma_f32_16x16x4_f32 (one k per lane; lane group g = l/16 holds k = g)
 //   BF16: v_mfma_f32_16x16x32_bf16 (8 consecutive k per lane group), or 16x16x16 for dh 16
 // Accumulator layout: lane l, register r holds row 4(l/16) + r, column l%16.
+#include <algorithm>
+#include <vector>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -242,7 +245,7 @@ __device__ __forceinline__ void attention32_body(
     const bf16* __restrict__ Q, int ldq, const bf16* __restrict__ Kp,
     const bf16* __restrict__ Vp, int ldkv, bf16* __restrict__ O, int ldo,
     const int64_t* __restrict__ q_off, const int64_t* __restrict__ kv_off,
-    const int2* __restrict__ work, int n_heads, float sl2e) {
+    const int2* __restrict__ work, const AttnBins& bins, int n_heads, float sl2e) {
   __shared__ __attribute__((aligned(16))) bf16 Ks[kKc2 * kLdK32];
   // V^T rows 0-31; row 32 = key validity (1 for a key of the event, 0 past its end), rows
   // 33-47 = 0: the A operand of the row-sum block of P V
@@ -250,9 +253,12 @@ __device__ __forceinline__ void attention32_body(
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, j = lane & 15;
   for (int i = tid; i < 15 * kLdV32; i += 256) Vt[(kH32 + 1) * kLdV32 + i] = (bf16)0.f;
-  const int L = blockIdx.x;
-  const int2 wk = work[L / n_heads];
-  const int h = L % n_heads;
+  // workgroup b: bin b % kAttnBins (so one XCD), unit k = b / kAttnBins of that bin
+  const int bin = blockIdx.x % kAttnBins, k = blockIdx.x / kAttnBins;
+  const int item = k / n_heads;
+  if (item >= bins.len[bin]) return;     // the bin is shorter than the longest one
+  const int2 wk = work[bins.start[bin] + item];
+  const int h = k % n_heads;
   const int e = wk.x;
   const int64_t qs0 = q_off[e], ks0 = kv_off[e];
   const int nq = (int)(q_off[e + 1] - qs0), nk = (int)(kv_off[e + 1] - ks0);
@@ -383,14 +389,16 @@ __device__ __forceinline__ void attention32_body(
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_attn32_self(
     const bf16* __restrict__ Q, int ldq, const bf16* __restrict__ K, const bf16* __restrict__ V,
     int ldkv, bf16* __restrict__ O, int ldo, const int64_t* __restrict__ q_off,
-    const int64_t* __restrict__ kv_off, const int2* __restrict__ work, int n_heads, float sl2e) {
-  attention32_body(Q, ldq, K, V, ldkv, O, ldo, q_off, kv_off, work, n_heads, sl2e);
+    const int64_t* __restrict__ kv_off, const int2* __restrict__ work, AttnBins bins,
+    int n_heads, float sl2e) {
+  attention32_body(Q, ldq, K, V, ldkv, O, ldo, q_off, kv_off, work, bins, n_heads, sl2e);
 }
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_attn32_cross(
     const bf16* __restrict__ Q, int ldq, const bf16* __restrict__ K, const bf16* __restrict__ V,
     int ldkv, bf16* __restrict__ O, int ldo, const int64_t* __restrict__ q_off,
-    const int64_t* __restrict__ kv_off, const int2* __restrict__ work, int n_heads, float sl2e) {
-  attention32_body(Q, ldq, K, V, ldkv, O, ldo, q_off, kv_off, work, n_heads, sl2e);
+    const int64_t* __restrict__ kv_off, const int2* __restrict__ work, AttnBins bins,
+    int n_heads, float sl2e) {
+  attention32_body(Q, ldq, K, V, ldkv, O, ldo, q_off, kv_off, work, bins, n_heads, sl2e);
 }
 
 template <typename T, int DH>
@@ -406,6 +414,42 @@ static hipError_t go_attn(bool cross, dim3 grid, hipStream_t st, const T* Q, int
   return hipGetLastError();
 }
 
+int64_t build_attention_work(const int64_t* ids, const int64_t* lens, int64_t n, int qt,
+                             int2* items, AttnBins* bins) {
+  // longest-processing-time assignment of whole events to bins; cost = query tiles x keys
+  std::vector<int64_t> order;
+  order.reserve((size_t)n);
+  for (int64_t k = 0; k < n; ++k)
+    if (lens[k] > 0) order.push_back(k);
+  auto cost = [&](int64_t k) { return ((lens[k] + qt - 1) / qt) * lens[k]; };
+  std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return cost(a) > cost(b); });
+  std::vector<int64_t> bin_of(order.size());
+  int64_t load[kAttnBins] = {0};
+  int64_t cnt[kAttnBins] = {0};
+  for (size_t i = 0; i < order.size(); ++i) {
+    int best = 0;
+    for (int b = 1; b < kAttnBins; ++b)
+      if (load[b] < load[best]) best = b;
+    bin_of[i] = best;
+    load[best] += cost(order[i]);
+    cnt[best] += (lens[order[i]] + qt - 1) / qt;
+  }
+  int64_t pos = 0;
+  bins->max_len = 0;
+  for (int b = 0; b < kAttnBins; ++b) {
+    bins->start[b] = (int32_t)pos;
+    bins->len[b] = (int32_t)cnt[b];
+    bins->max_len = std::max<int32_t>(bins->max_len, (int32_t)cnt[b]);
+    for (size_t i = 0; i < order.size(); ++i) {
+      if (bin_of[i] != b) continue;
+      const int64_t k = order[i];
+      for (int64_t q = 0; q < (lens[k] + qt - 1) / qt; ++q)
+        items[pos++] = make_int2((int)ids[k], (int)q);
+    }
+  }
+  return pos;
+}
+
 int attention_query_tile(bool bf16, int dh, int n_heads) {
   (void)bf16;
   (void)dh;
@@ -415,7 +459,7 @@ int attention_query_tile(bool bf16, int dh, int n_heads) {
 
 template <typename T>
 hipError_t launch_attention(hipStream_t st, bool cross, int dh, int n_heads, int64_t n_items,
-                            const int2* work, const T* Q, int ldq, const T* K, const T* V,
+                            const AttnBins& bins, const int2* work, const T* Q, int ldq, const T* K, const T* V,
                             int ldkv, T* O, int ldo, const int64_t* q_off,
                             const int64_t* kv_off) {
   if (n_items <= 0) return hipSuccess;
@@ -425,14 +469,15 @@ hipError_t launch_attention(hipStream_t st, bool cross, int dh, int n_heads, int
     if (dh == kH32) {
       // 16-byte row chunks: row pitches and head offsets are multiples of 8 elements
       if (ldq % 8 || ldkv % 8 || ldo % 8) return hipErrorInvalidValue;
-      const int64_t blocks = n_items * n_heads;
+      const int64_t blocks = (int64_t)kAttnBins * bins.max_len * n_heads;
       if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+      if (blocks == 0) return hipSuccess;
       if (cross)
         hipLaunchKernelGGL(k_attn32_cross, dim3((unsigned)blocks), dim3(256), 0, st, Q, ldq, K,
-                           V, ldkv, O, ldo, q_off, kv_off, work, n_heads, sl2e);
+                           V, ldkv, O, ldo, q_off, kv_off, work, bins, n_heads, sl2e);
       else
         hipLaunchKernelGGL(k_attn32_self, dim3((unsigned)blocks), dim3(256), 0, st, Q, ldq, K, V,
-                           ldkv, O, ldo, q_off, kv_off, work, n_heads, sl2e);
+                           ldkv, O, ldo, q_off, kv_off, work, bins, n_heads, sl2e);
       return hipGetLastError();
     }
   }
@@ -445,10 +490,12 @@ hipError_t launch_attention(hipStream_t st, bool cross, int dh, int n_heads, int
   }
 }
 
-template hipError_t launch_attention<float>(hipStream_t, bool, int, int, int64_t, const int2*,
+template hipError_t launch_attention<float>(hipStream_t, bool, int, int, int64_t,
+                                            const AttnBins&, const int2*,
                                             const float*, int, const float*, const float*, int,
                                             float*, int, const int64_t*, const int64_t*);
-template hipError_t launch_attention<bf16>(hipStream_t, bool, int, int, int64_t, const int2*,
+template hipError_t launch_attention<bf16>(hipStream_t, bool, int, int, int64_t,
+                                           const AttnBins&, const int2*,
                                            const bf16*, int, const bf16*, const bf16*, int,
                                            bf16*, int, const int64_t*, const int64_t*);
 

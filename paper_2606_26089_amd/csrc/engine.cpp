@@ -246,33 +246,26 @@ void flush_timing(fmd_model* m) {
 int stage_events(fmd_model* m, const fmd_events_in* ev, Call& c) {
   Workspace& w = m->ws;
   const int64_t E = ev->n_events;
-  // work items: (event, query tile), longest events first
+  // work items: (event, query tile), in bins of whole events balanced by attention work
   const int qt = attention_query_tile(m->cfg.precision == FMD_BF16, m->cfg.d_model / std::max(m->cfg.n_heads, 1),
                                       m->cfg.n_heads);
-  std::vector<int64_t> order;
-  order.reserve(E);
+  std::vector<int64_t> ids((size_t)E), lens((size_t)E);
   int64_t items = 0;
   double s2 = 0;
   for (int64_t e = 0; e < E; ++e) {
     const int64_t n = ev->offsets[e + 1] - ev->offsets[e];
-    if (n > 0) order.push_back(e);
+    ids[e] = e;
+    lens[e] = n;
     items += (n + qt - 1) / qt;
     s2 += (double)n * (double)n;
   }
-  std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
-    return ev->offsets[a + 1] - ev->offsets[a] > ev->offsets[b + 1] - ev->offsets[b];
-  });
   c.items = items;
   c.sum_n2 = s2;
   FMD_TRY(ensure_ws(m, c.T, E, items));
   // The pinned staging buffers may still feed the previous call's copies.
   HIP_TRY(hipStreamSynchronize(c.st));
   std::memcpy(w.h_off, ev->offsets, (size_t)(E + 1) * 8);
-  int64_t k = 0;
-  for (int64_t e : order) {
-    const int64_t n = ev->offsets[e + 1] - ev->offsets[e];
-    for (int64_t q = 0; q < (n + qt - 1) / qt; ++q) w.h_work[k++] = make_int2((int)e, (int)q);
-  }
+  build_attention_work(ids.data(), lens.data(), E, qt, w.h_work, &c.bins);
   HIP_TRY(hipMemcpyAsync(w.off, w.h_off, (size_t)(E + 1) * 8, hipMemcpyHostToDevice, c.st));
   if (items) HIP_TRY(hipMemcpyAsync(w.work, w.h_work, (size_t)items * sizeof(int2), hipMemcpyHostToDevice, c.st));
   FMD_TRY(timed(m, c.st, FMD_K_OTHER, 0, [&] { return launch_token_map(c.st, w.off, E, c.T, w.tok_event); }));
@@ -455,7 +448,7 @@ int net_forward(fmd_model* m, Call& c, const float* t_ev) {
       }));
     }
     FMD_TRY(timed(m, c.st, FMD_K_ATTN_SELF, 4.0 * c.sum_n2 * d, Td * 4 * d * es, [&] {
-      return launch_attention<T>(c.st, false, dh, Hh, c.items, w.work, (const T*)qkv, 3 * d,
+      return launch_attention<T>(c.st, false, dh, Hh, c.items, c.bins, w.work, (const T*)qkv, 3 * d,
                                  (const T*)(qkv + d * es), (const T*)(qkv + 2 * d * es), 3 * d,
                                  (T*)w.att, d, w.off, w.off);
     }));
@@ -479,7 +472,7 @@ int net_forward(fmd_model* m, Call& c, const float* t_ev) {
     }
     FMD_TRY(timed(m, c.st, FMD_K_ATTN_CROSS, 4.0 * c.sum_n2 * d, Td * 4 * d * es, [&] {
       const size_t o = (size_t)l * 2 * d * es;
-      return launch_attention<T>(c.st, true, dh, Hh, c.items, w.work, (const T*)w.qc, d,
+      return launch_attention<T>(c.st, true, dh, Hh, c.items, c.bins, w.work, (const T*)w.qc, d,
                                  (const T*)(kv + o), (const T*)(kv + o + d * es), 2 * d * L,
                                  (T*)w.att, d, w.off, w.off);
     }));
@@ -576,7 +569,7 @@ int run_stages(fmd_model* m, Call& c, int n_stages, float* out, int ldo) {
     for (int i = 0; i < n_stages; ++i) FMD_TRY(run_stage<T>(m, c, out, ldo));
     return FMD_OK;
   }
-  const GraphKey key{c.Tp, c.T, c.E, c.items, out, ldo, m->ws.generation, m->tune_gen};
+  const GraphKey key{c.Tp, c.T, c.E, c.items, out, ldo, m->ws.generation, m->tune_gen, c.bins};
   if (!m->gexec || !(key == m->gkey)) {
     if (m->gexec) (void)hipGraphExecDestroy(m->gexec);
     m->gexec = nullptr;
@@ -1159,14 +1152,20 @@ int fmd_debug_attention(int32_t precision, int64_t n_events, const int64_t* q_of
   if (dh != 16 && dh != 32 && dh != 64) return fail(FMD_E_UNSUPPORTED, "dh must be 16, 32 or 64");
   if (n_heads < 1 || n_events < 0 || !q_offsets || !kv_offsets) return fail(FMD_E_INVALID, "bad arguments");
   if (q_offsets[0] != 0 || kv_offsets[0] != 0) return fail(FMD_E_INVALID, "offsets must start at 0");
-  std::vector<int2> work;
   const int qt = attention_query_tile(precision == FMD_BF16, dh, n_heads);
+  std::vector<int64_t> ids((size_t)n_events), lens((size_t)n_events);
+  int64_t n_items = 0;
   for (int64_t e = 0; e < n_events; ++e) {
     const int64_t nq = q_offsets[e + 1] - q_offsets[e], nk = kv_offsets[e + 1] - kv_offsets[e];
     if (nq < 0 || nk < 0) return fail(FMD_E_INVALID, "offsets decrease");
     if (nq > 0 && nk == 0) return fail(FMD_E_INVALID, "event %lld has queries but no keys", (long long)e);
-    for (int64_t q = 0; q < (nq + qt - 1) / qt; ++q) work.push_back(make_int2((int)e, (int)q));
+    ids[e] = e;
+    lens[e] = nq;
+    n_items += (nq + qt - 1) / qt;
   }
+  std::vector<int2> work((size_t)n_items);
+  AttnBins bins{};
+  build_attention_work(ids.data(), lens.data(), n_events, qt, work.data(), &bins);
   const int64_t Tq = q_offsets[n_events], Tk = kv_offsets[n_events];
   if (work.empty()) return FMD_OK;
   if (!Q || !K || !V || !O) return fail(FMD_E_INVALID, "null operand");
@@ -1190,12 +1189,12 @@ int fmd_debug_attention(int32_t precision, int64_t n_events, const int64_t* q_of
       if (e == hipSuccess) e = launch_convert<bf16>(st, K, Tk * ld, (bf16*)Kp);
       if (e == hipSuccess) e = launch_convert<bf16>(st, V, Tk * ld, (bf16*)Vp);
       if (e == hipSuccess)
-        e = launch_attention<bf16>(st, false, dh, n_heads, (int64_t)work.size(), wk, (const bf16*)Qp, ld,
+        e = launch_attention<bf16>(st, false, dh, n_heads, (int64_t)work.size(), bins, wk, (const bf16*)Qp, ld,
                                    (const bf16*)Kp, (const bf16*)Vp, ld, (bf16*)Op, ld, qo, ko);
       if (e == hipSuccess) e = launch_to_f32<bf16>(st, (const bf16*)Op, Tq * ld, O);
     } else {
       if (e == hipSuccess)
-        e = launch_attention<float>(st, false, dh, n_heads, (int64_t)work.size(), wk, Q, ld, K, V, ld, O, ld, qo, ko);
+        e = launch_attention<float>(st, false, dh, n_heads, (int64_t)work.size(), bins, wk, Q, ld, K, V, ld, O, ld, qo, ko);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) status = fail(FMD_E_DEVICE, "debug attention: %s", hipGetErrorString(e));

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cstring>
 #include <string>
 #include <vector>
 
@@ -56,9 +57,11 @@ struct GraphKey {
   const float* out;
   int ldo;
   uint64_t ws_gen, tune_gen;
+  AttnBins bins;  // kernel arguments and grid size of the attention launches
   bool operator==(const GraphKey& o) const {
     return Tp == o.Tp && T == o.T && E == o.E && items == o.items && out == o.out &&
-           ldo == o.ldo && ws_gen == o.ws_gen && tune_gen == o.tune_gen;
+           ldo == o.ldo && ws_gen == o.ws_gen && tune_gen == o.tune_gen &&
+           std::memcmp(&bins, &o.bins, sizeof(AttnBins)) == 0;
   }
 };
 

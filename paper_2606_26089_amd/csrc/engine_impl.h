@@ -99,6 +99,7 @@ int timed(fmd_model* m, hipStream_t st, int cls, double work, F&& launch) {
 struct Call {
   hipStream_t st;
   int64_t E, T, Tp, items;
+  AttnBins bins;        // bins of the attention work list
   double sum_n2;        // sum over events of N_e^2 (attention work)
   const float* u;       // truth features on device [T, 9]
   OdeArgs sargs;        // epilogue arguments of the residual GEMMs (statistics output)

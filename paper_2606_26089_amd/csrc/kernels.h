@@ -82,9 +82,25 @@ hipError_t launch_row_stats(hipStream_t st, const float* A, int ld, int K, int64
 // work lists passed to launch_attention are built with this tile.
 int attention_query_tile(bool bf16, int dh, int n_heads);
 
+// Attention work list split into kAttnBins bins of whole events with about equal work, each
+// bin's items stored contiguously (bin i: items [start[i], start[i] + len[i])). Workgroup b
+// of the BF16 kernel takes bin b % kAttnBins, so that all workgroups of an event land on one
+// XCD (workgroups are dealt to the 8 XCDs round-robin) and share its L2.
+constexpr int kAttnBins = 8;
+struct AttnBins {
+  int32_t start[kAttnBins], len[kAttnBins];
+  int32_t max_len;
+};
+// Fills `items` (capacity >= sum over events of ceil(n / qt)) from per-event lengths:
+// events longest first within each bin, bins balanced by attention work (longest-processing-
+// time assignment). ids[k], lens[k]: event id and length; returns the item count.
+int64_t build_attention_work(const int64_t* ids, const int64_t* lens, int64_t n, int qt,
+                             int2* items, AttnBins* bins);
+
 // Masked multi-head attention over CSR events. work: int2 (event, 64-query tile) items.
 template <typename T>
 hipError_t launch_attention(hipStream_t st, bool cross, int dh, int n_heads, int64_t n_items,
+                            const AttnBins& bins,
                             const int2* work, const T* Q, int ldq, const T* K, const T* V,
                             int ldkv, T* O, int ldo, const int64_t* q_off,
                             const int64_t* kv_off);

@@ -212,14 +212,13 @@ int iterate(fmd_server* S, std::vector<Req*>& finished) {
   const int64_t E = (int64_t)desc.size(), span = pos;
   if (span == 0) return FMD_OK;
   FMD_TRY(ensure_ws(m, span, E, items));
-  std::stable_sort(real.begin(), real.end(),
-                   [](const std::pair<int64_t, int64_t>& a, const std::pair<int64_t, int64_t>& b) {
-                     return a.second > b.second;
-                   });
   std::memcpy(w.h_off, off.data(), (size_t)(E + 1) * 8);
-  int64_t k = 0;
-  for (auto& pr : real)
-    for (int64_t q = 0; q < (pr.second + qt - 1) / qt; ++q) w.h_work[k++] = make_int2((int)pr.first, (int)q);
+  AttnBins bins{};
+  {
+    std::vector<int64_t> ids(real.size()), lens(real.size());
+    for (size_t i = 0; i < real.size(); ++i) ids[i] = real[i].first, lens[i] = real[i].second;
+    build_attention_work(ids.data(), lens.data(), (int64_t)real.size(), qt, w.h_work, &bins);
+  }
   if (E > w.cap_desc) {
     FMD_TRY(grow(w.desc, (size_t)E * sizeof(StageDesc)));
     FMD_TRY(grow_host(w.h_desc, (size_t)E * sizeof(StageDesc)));
@@ -238,6 +237,7 @@ int iterate(fmd_server* S, std::vector<Req*>& finished) {
   c.T = span;
   c.Tp = round_up(span, kGemmBM);
   c.items = items;
+  c.bins = bins;
   c.sum_n2 = sum_n2;
   c.u = w.u;
   HIP_TRY(launch_token_map(S->st, w.off, E, span, w.tok_event));

@@ -122,3 +122,24 @@ def test_fused_kernels_only_where_they_exist(env):
     m = fmd.Model(CFG, params.draw(CFG, 0))
     assert m.kernel_name(fmd.K_GEMM_QKV) == "k_fused_qkv"
     m.close()
+
+
+def test_graph_recaptured_when_only_event_lengths_change(env):
+    # same event and token counts, different lengths: the attention work bins differ, so a
+    # cached graph must not be replayed
+    torch, fmd = env
+    flat = params.draw(CFG, 4, perturbed=True)
+    sched = configs.Schedule(configs.RK4, 2)
+    m = fmd.Model(CFG, flat)
+    outs = {}
+    for sizes in ([400, 10, 10, 10], [10, 10, 10, 400], [108, 108, 108, 106]):
+        off = np.r_[0, np.cumsum(sizes)].astype(np.int64)
+        feat = events.particles(np.random.default_rng(3), int(off[-1]))
+        res = []
+        for g in (False, True):
+            m.graphs_enable(g)
+            res.append(m.simulate(off, dev(torch, feat), 8, sched).cpu().numpy())
+        outs[tuple(sizes)] = res
+    m.close()
+    for eager, graph in outs.values():
+        assert np.array_equal(eager, graph)
