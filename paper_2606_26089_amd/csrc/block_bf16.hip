@@ -146,27 +146,49 @@ __device__ __forceinline__ void tile_to_lds(bf16* __restrict__ A, const bf16* __
   }
 }
 
-// Transpose-reduction over the 32 lanes of a half wave without data-dependent register
-// selection: at each step both halves of the value set are reduced with the partner lane
-// and the lane keeps the half its lane bit selects. Afterwards v[0] of lane l holds the sum
-// over the half wave of value (l & 31).
-__device__ __forceinline__ void transpose_reduce32_v2(float (&v)[32], int lane) {
+// Cross-lane data movement inside 16-lane rows (DPP controls).
+constexpr int kDppXor1 = 0xB1;        // quad_perm [1,0,3,2]: lane i <- lane i ^ 1
+constexpr int kDppXor2 = 0x4E;        // quad_perm [2,3,0,1]: lane i <- lane i ^ 2
+constexpr int kDppHalfMirror = 0x141; // lane i <- lane 7 - i within each group of 8
+constexpr int kDppRor8 = 0x128;       // lane i <- lane (i + 8) mod 16, i.e. i ^ 8
+
+// One halving step of the transpose-reduction: lanes pair up across lane bit `bit` (the DPP
+// partner differs from the lane in that bit and agrees in every bit already reduced); of the
+// value pairs (v[i], v[i + N/2]) both lanes sum the pair with the partner's copy and keep the
+// half their bit selects.
+template <int CTRL, int N>
+__device__ __forceinline__ void reduce_step(float (&v)[32], bool up) {
 #pragma unroll
-  for (int m = 16, n = 32; m >= 1; m >>= 1, n >>= 1) {
-    const bool up = (lane & m) != 0;
-#pragma unroll
-    for (int i = 0; i < n / 2; ++i) {
-      const float ra = v[i] + __shfl_xor(v[i], m, kWave);
-      const float rb = v[i + n / 2] + __shfl_xor(v[i + n / 2], m, kWave);
-      v[i] = up ? rb : ra;
-    }
+  for (int i = 0; i < N / 2; ++i) {
+    const float ra = v[i] + __builtin_amdgcn_update_dpp(0.f, v[i], CTRL, 0xF, 0xF, false);
+    const float rb = v[i + N / 2] + __builtin_amdgcn_update_dpp(0.f, v[i + N / 2], CTRL, 0xF, 0xF, false);
+    v[i] = up ? rb : ra;
   }
+}
+
+// Transpose-reduction over the 32 lanes of a half wave, in vector instructions only: lane
+// bit 4 by a row swap (v_permlane16_swap exchanges the upper row of one register with the
+// lower row of the other, so a single add leaves v[i] summed over lanes l, l ^ 16 in the
+// lower row and v[i + 16] in the upper row), bits 3..0 by DPP. Afterwards v[0] of lane l
+// holds the sum over the half wave of value (l & 31). Every value is summed in the same
+// tree of column groups, so the result does not depend on which value slot a row uses.
+__device__ __forceinline__ void transpose_reduce32(float (&v)[32], int lane) {
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v[i]), __float_as_uint(v[i + 16]),
+                                                    false, false);
+    v[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+  reduce_step<kDppRor8, 16>(v, (lane & 8) != 0);
+  reduce_step<kDppHalfMirror, 8>(v, (lane & 4) != 0);
+  reduce_step<kDppXor2, 4>(v, (lane & 2) != 0);
+  reduce_step<kDppXor1, 2>(v, (lane & 1) != 0);
 }
 
 template <int ROWS>
 __device__ __forceinline__ void row_partials(float (&v)[32], float* __restrict__ red, int g,
                                              int lane, int w) {
-  transpose_reduce32_v2(v, lane);
+  transpose_reduce32(v, lane);
   const int j = lane & 31;
   red[w * ROWS + acc_row(2 * g + (j >> 4), j & 15, lane)] = v[0];
 }
