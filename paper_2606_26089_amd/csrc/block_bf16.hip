@@ -185,50 +185,61 @@ __device__ __forceinline__ void transpose_reduce32(float (&v)[32], int lane) {
   reduce_step<kDppXor1, 2>(v, (lane & 1) != 0);
 }
 
-template <int ROWS>
-__device__ __forceinline__ void row_partials(float (&v)[32], float* __restrict__ red, int g,
-                                             int lane, int w) {
-  transpose_reduce32(v, lane);
+// Row-statistics scratch: per-pass partial sums [row][wave] and each wave's own copy of
+// the row means and inverse deviations (a wave writes and reads only its copy, so no
+// barrier is needed after they are formed).
+struct SharedLn {
+  float red[2][kBM * kWaves];
+  float mu[kWaves][kBM];
+  float rs[kWaves][kBM];
+};
+
+// Partial sums over the wave's 32 columns of the 32 TM rows in acc, one 32-value group of
+// two fragments at a time; lane l ends with the row own(g, l) of group g.
+__device__ __forceinline__ int own_row(int g, int lane) {
   const int j = lane & 31;
-  red[w * ROWS + acc_row(2 * g + (j >> 4), j & 15, lane)] = v[0];
+  return acc_row(2 * g + (j >> 4), j & 15, lane);
 }
 
 // LayerNorm statistics of the 32 TM full rows held in acc: mean and 1/sqrt(biased variance +
-// eps) into mu[] / rs[] (LDS), optionally also to stats_out[m0 + row]. Per-wave partial
-// sums over the wave's 32 columns by a transpose-reduction, then across the 8 waves through
-// red[]. Ends with a barrier (mu/rs visible to all waves).
+// eps) into this wave's sl.mu[w] / sl.rs[w], optionally also to stats_out[m0 + row]. Per
+// pass: a transpose-reduction over the wave's columns, partials to LDS, one barrier, then
+// every lane adds the 8 wave partials of its own rows in wave order. Contains two barriers.
 template <int TM>
-__device__ __forceinline__ void row_stats(const f32x16 (&acc)[TM], float* __restrict__ red,
-                                          float* __restrict__ mu, float* __restrict__ rs,
-                                          float2* __restrict__ stats_out, int64_t m0,
-                                          int lane, int w, int tid) {
+__device__ __forceinline__ void row_stats(const f32x16 (&acc)[TM], SharedLn& sl,
+                                          float2* __restrict__ stats_out, int64_t m0, int lane,
+                                          int w) {
   // No multiply-add contraction here: a square fused into the lane exchange's add would be
-  // exact on the lane that keeps the partial sum and rounded on the lane that sends it, so
-  // the statistics would depend on the row's position in the tile.
+  // exact on one lane of a pair and rounded on the other, so the statistics would depend on
+  // the row's position in the tile.
 #pragma clang fp contract(off)
   static_assert(TM % 2 == 0, "row statistics take 32-value groups of two fragments");
-  constexpr int ROWS = 32 * TM;
+  constexpr int G = TM / 2;
+  float* mu = sl.mu[w];
+  float* rs = sl.rs[w];
   // pass 1: row sums
 #pragma unroll
-  for (int g = 0; g < TM / 2; ++g) {
+  for (int g = 0; g < G; ++g) {
     float v[32];
 #pragma unroll
     for (int h = 0; h < 2; ++h)
 #pragma unroll
       for (int r = 0; r < 16; ++r) v[h * 16 + r] = acc[2 * g + h][r];
-    row_partials<ROWS>(v, red, g, lane, w);
+    transpose_reduce32(v, lane);
+    sl.red[0][own_row(g, lane) * kWaves + w] = v[0];
   }
   __syncthreads();
-  if (tid < ROWS) {
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    const float* p = &sl.red[0][own_row(g, lane) * kWaves];
     float t = 0.f;
 #pragma unroll
-    for (int q = 0; q < kWaves; ++q) t += red[q * ROWS + tid];
-    mu[tid] = t * (1.0f / kD);
+    for (int q = 0; q < kWaves; ++q) t += p[q];
+    mu[own_row(g, lane)] = t * (1.0f / kD);
   }
-  __syncthreads();
-  // pass 2: sums of squared deviations
+  // pass 2: sums of squared deviations (mu read back from this wave's own copy)
 #pragma unroll
-  for (int g = 0; g < TM / 2; ++g) {
+  for (int g = 0; g < G; ++g) {
     float v[32];
 #pragma unroll
     for (int h = 0; h < 2; ++h)
@@ -237,17 +248,21 @@ __device__ __forceinline__ void row_stats(const f32x16 (&acc)[TM], float* __rest
         const float dv = acc[2 * g + h][r] - mu[acc_row(2 * g + h, r, lane)];
         v[h * 16 + r] = dv * dv;
       }
-    row_partials<ROWS>(v, red, g, lane, w);
+    transpose_reduce32(v, lane);
+    sl.red[1][own_row(g, lane) * kWaves + w] = v[0];
   }
   __syncthreads();
-  if (tid < ROWS) {
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    const int row = own_row(g, lane);
+    const float* p = &sl.red[1][row * kWaves];
     float t = 0.f;
 #pragma unroll
-    for (int q = 0; q < kWaves; ++q) t += red[q * ROWS + tid];
-    rs[tid] = rsqrtf(t * (1.0f / kD) + kLnEps);
-    if (stats_out) stats_out[m0 + tid] = make_float2(mu[tid], rs[tid]);
+    for (int q = 0; q < kWaves; ++q) t += p[q];
+    const float r = rsqrtf(t * (1.0f / kD) + kLnEps);
+    rs[row] = r;
+    if (stats_out && w == 0) stats_out[m0 + row] = make_float2(mu[row], r);
   }
-  __syncthreads();
 }
 
 // LDS tile A (pitch kLdA) = LayerNorm(acc rows) with gain g and shift s, in BF16.
@@ -337,12 +352,6 @@ __device__ __forceinline__ void up_and_gelu(f32x16 (&h2n)[TA], const f32x16 (&h2
   }
 }
 
-struct SharedLn {
-  float red[kWaves * kBM];
-  float mu[kBM];
-  float rs[kBM];
-};
-
 }  // namespace
 
 // ---------------------------------------------------------------------------------------
@@ -366,8 +375,8 @@ __global__ __launch_bounds__(kThreads) void k_fused_qkv(const float* __restrict_
   ring_fill(ring, wf, lane);
   f32x16 acc[TM];
   load_rows(acc, H, m0, col, nullptr, lane);
-  row_stats(acc, sl.red, sl.mu, sl.rs, nullptr, m0, lane, w, tid);
-  ln_to_lds(acc, sl.mu, sl.rs, g, s, A, col, lane);
+  row_stats(acc, sl, nullptr, m0, lane, w);
+  ln_to_lds(acc, sl.mu[w], sl.rs[w], g, s, A, col, lane);
   __syncthreads();
 #pragma unroll 1
   for (int slab = 0; slab < 3; ++slab) {
@@ -401,9 +410,9 @@ __global__ __launch_bounds__(kThreads) void k_fused_oqc(
   __syncthreads();
   mfma_phase<TM, false>(acc, A, kLdA, 0, kKs, ring, wo, wo, lane);
   store_rows_f32(acc, H, m0, col, lane);
-  row_stats(acc, sl.red, sl.mu, sl.rs, nullptr, m0, lane, w, tid);   // barrier: A reads done
+  row_stats(acc, sl, nullptr, m0, lane, w);   // barrier: A reads done
   ring_fill(ring, wq, lane);
-  ln_to_lds(acc, sl.mu, sl.rs, g, s, A, col, lane);
+  ln_to_lds(acc, sl.mu[w], sl.rs[w], g, s, A, col, lane);
   __syncthreads();
   zero(acc, b_qc, col);
   mfma_phase<TM>(acc, A, kLdA, 0, kKs, ring, wq, wq, lane);
@@ -441,9 +450,9 @@ __global__ __launch_bounds__(kThreads) void k_fused_mlp(
   load_rows(acc, H, m0, col, b_oc, lane);
   __syncthreads();
   mfma_phase<TM, false>(acc, A, kLdA, 0, kKs, ring, woc, woc, lane);
-  row_stats(acc, sl.red, sl.mu, sl.rs, nullptr, m0, lane, w, tid);   // barrier: A reads done
+  row_stats(acc, sl, nullptr, m0, lane, w);   // barrier: A reads done
   ring_fill(ring, wup, lane);
-  ln_to_lds(acc, sl.mu, sl.rs, g, s, A, col, lane);
+  ln_to_lds(acc, sl.mu[w], sl.rs[w], g, s, A, col, lane);
   __syncthreads();
   const int hcol = wn * 32 + (lane & 31);
   auto up_c = [&](int c) { return wup + c * (kBH / 32) * kKs * 64; };
@@ -485,7 +494,7 @@ __global__ __launch_bounds__(kThreads) void k_fused_mlp(
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[mi][r] += bv;
   store_rows_f32(acc, H, m0, col, lane);
-  row_stats(acc, sl.red, sl.mu, sl.rs, stats_out, m0, lane, w, tid);
+  row_stats(acc, sl, stats_out, m0, lane, w);
 }
 
 __global__ void k_pack_frag(const float* __restrict__ W, int K, int N, u32x4* __restrict__ Wf) {
