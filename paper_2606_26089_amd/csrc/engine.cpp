@@ -518,6 +518,8 @@ int head(fmd_model* m, Call& c, bool direct, int mode, float* out, int ldo) {
   const OdeArgs ode{w.x, w.acc, w.xs, out, c.T, kStateLd, ldo, 9, mode, 0.f,
                     direct ? nullptr : w.desc, w.ctr, nullptr};
   return timed(m, c.st, FMD_K_OTHER, 2.0 * c.T * d * 9, [&] {
+    if (head256_supported(d, 9))
+      return launch_head256(c.st, w.H, w.stats, m->g_f, m->s_f, m->Wout_pk, m->bout_pk, ode);
     return launch_gemm<float>(c.st, FMD_K_OTHER, true, EPI_ODE, c.Tp, 64, d, w.H, d, m->Wout_pk,
                               m->bout_pk, w.stats, m->g_f, m->s_f, nullptr, 0, &ode);
   });

@@ -141,6 +141,12 @@ hipError_t launch_embed(hipStream_t st, const float* xs, int ldx, int f, int64_t
 
 // v = (alpha + beta t) xs, then the same ODE update, with t, h, mode and the output write
 // taken from desc[*ctr].
+// Output head for d_model 256 and 9 features: ode-update(LN(H; stats, g, s) Wt^T + b) over
+// the ode.m_valid valid rows, Wt float [>= 9, 256] (row c: weights of output c).
+bool head256_supported(int d, int nf);
+hipError_t launch_head256(hipStream_t st, const float* H, const float2* stats, const float* g,
+                          const float* s, const float* Wt, const float* b, const OdeArgs& ode);
+
 hipError_t launch_linear_update(hipStream_t st, float alpha, float beta, const StageDesc* desc,
                                 const int32_t* ctr, int64_t T, int f, float* x, float* acc,
                                 float* xs, int ldx, float* out, int ldo);

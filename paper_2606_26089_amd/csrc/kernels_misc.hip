@@ -280,10 +280,77 @@ __global__ __launch_bounds__(256) void k_embed(const float* __restrict__ xs, int
   if (lane == 0) stats[r] = make_float2(mean, rsqrtf(var + kLnEps));
 }
 
+// The same for d = 256 and 9 input features, built for memory-level parallelism: a wave
+// embeds kEmbTok consecutive tokens, lane l owning columns 4l .. 4l + 3 (16-byte loads and
+// stores), with W_xin kept in registers across the tokens and the token inputs read by
+// scalar loads. Each output is formed in the same order as above (temb first, then the
+// features in order), so H is identical; the statistics reductions of all tokens of the
+// wave run side by side.
+constexpr int kEmbTok = 8;
+constexpr int kEmbF = 9;
+__global__ __launch_bounds__(256) void k_embed256(const float* __restrict__ xs, int ldx,
+                                                  int64_t T, const int32_t* __restrict__ tok_event,
+                                                  const float* __restrict__ temb,
+                                                  const float* __restrict__ W,
+                                                  float* __restrict__ H, int ldh,
+                                                  float2* __restrict__ stats) {
+  constexpr int D = 256;
+  const int lane = threadIdx.x & 63;
+  const int64_t r0 =
+      ((int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) * kEmbTok;
+  if (r0 >= T) return;
+  float4 w[kEmbF];
+#pragma unroll
+  for (int k = 0; k < kEmbF; ++k) w[k] = *(const float4*)(W + k * D + 4 * lane);
+  float4 a[kEmbTok];
+  float part[kEmbTok];
+#pragma unroll
+  for (int t = 0; t < kEmbTok; ++t) {
+    const int64_t r = r0 + t;
+    a[t] = make_float4(0.f, 0.f, 0.f, 0.f);
+    part[t] = 0.f;
+    if (r < T) {
+      const float* te = temb + (tok_event ? (int64_t)tok_event[r] * D : 0);
+      float4 v = *(const float4*)(te + 4 * lane);
+#pragma unroll
+      for (int k = 0; k < kEmbF; ++k) {
+        const float x = xs[r * ldx + k];
+        v.x = fmaf(x, w[k].x, v.x);
+        v.y = fmaf(x, w[k].y, v.y);
+        v.z = fmaf(x, w[k].z, v.z);
+        v.w = fmaf(x, w[k].w, v.w);
+      }
+      *(float4*)(H + r * ldh + 4 * lane) = v;
+      a[t] = v;
+      part[t] = (v.x + v.y) + (v.z + v.w);
+    }
+  }
+  float mean[kEmbTok];
+#pragma unroll
+  for (int t = 0; t < kEmbTok; ++t) mean[t] = wave_sum(part[t]) * (1.0f / D);
+#pragma unroll
+  for (int t = 0; t < kEmbTok; ++t) {
+    const float dx = a[t].x - mean[t], dy = a[t].y - mean[t], dz = a[t].z - mean[t],
+                dw = a[t].w - mean[t];
+    part[t] = fmaf(dw, dw, fmaf(dz, dz, fmaf(dy, dy, dx * dx)));
+  }
+#pragma unroll
+  for (int t = 0; t < kEmbTok; ++t) {
+    const float var = wave_sum(part[t]) * (1.0f / D);
+    if (lane == 0 && r0 + t < T) stats[r0 + t] = make_float2(mean[t], rsqrtf(var + kLnEps));
+  }
+}
+
 hipError_t launch_embed(hipStream_t st, const float* xs, int ldx, int f, int64_t T,
                         const int32_t* tok_event, const float* temb, const float* W_xin,
                         int d, float* H, int ldh, float2* stats) {
   if (T <= 0) return hipSuccess;
+  if (d == 256 && f == kEmbF && ldh % 4 == 0) {
+    const int64_t waves = (T + kEmbTok - 1) / kEmbTok;
+    hipLaunchKernelGGL(k_embed256, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, xs, ldx,
+                       T, tok_event, temb, W_xin, H, ldh, stats);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_embed, dim3((unsigned)((T + 3) / 4)), dim3(256), 0, st, xs, ldx, f, T,
                      tok_event, temb, W_xin, d, H, ldh, stats);
   return hipGetLastError();
@@ -426,6 +493,127 @@ hipError_t launch_pack_padded(hipStream_t st, const float* padded, const int32_t
   const int64_t n = E * n_max * f;
   hipLaunchKernelGGL(k_scatter_rows, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, padded,
                      lengths, off_out, E, n_max, f, feat_out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
+// Output head for d = 256 and 9 features: v = LN_f(H) W_out + b_out followed by the ODE
+// update of the state (the same update as the GEMM head's epilogue). The product has only
+// nine columns, so it runs on the vector ALUs in FP32 instead of a matrix tile padded to 64
+// columns: half a wave per token (lane i of the half owns columns 4i .. 4i+3 and 128 + 4i ..
+// 131 + 4i, coalesced 16-byte loads), W_out, gain and shift in registers, the nine dot
+// products reduced over the half wave by DPP rotations inside 16-lane rows and one
+// permlane16 swap between the two rows. Lanes 0..8 of a half then update feature i.
+namespace {
+constexpr int kHeadIter = 4;     // token pairs per wave
+constexpr int kHeadF = 9;
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_add(float v) {
+  return v + __builtin_amdgcn_update_dpp(0.f, v, CTRL, 0xF, 0xF, false);
+}
+
+// Sum over the 32 lanes of each half wave, left in every lane of the half; the same
+// addition tree for both halves and for every lane.
+__device__ __forceinline__ float half_wave_sum(float v) {
+  v = dpp_add<0x128>(v);   // row_ror 8
+  v = dpp_add<0x124>(v);   // row_ror 4
+  v = dpp_add<0x122>(v);   // row_ror 2
+  v = dpp_add<0x121>(v);   // row_ror 1
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false,
+                                                  false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+}  // namespace
+
+__global__ __launch_bounds__(256) void k_head256(const float* __restrict__ H,
+                                                 const float2* __restrict__ stats,
+                                                 const float* __restrict__ g,
+                                                 const float* __restrict__ s,
+                                                 const float* __restrict__ Wt,
+                                                 const float* __restrict__ b, OdeArgs ode) {
+  constexpr int D = 256;
+  const int lane = threadIdx.x & 63, half = lane >> 5, i = lane & 31;
+  const int64_t p0 =
+      ((int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) * kHeadIter;
+  const int64_t T = ode.m_valid;
+  if (2 * p0 >= T) return;
+  float4 hv[kHeadIter][2];
+  float2 st[kHeadIter];
+#pragma unroll
+  for (int it = 0; it < kHeadIter; ++it) {
+    const int64_t r = min(2 * (p0 + it) + half, T - 1);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) hv[it][j] = *(const float4*)(H + r * D + 128 * j + 4 * i);
+    st[it] = stats[r];
+  }
+  float4 gv[2], sv[2], w[kHeadF][2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    gv[j] = *(const float4*)(g + 128 * j + 4 * i);
+    sv[j] = *(const float4*)(s + 128 * j + 4 * i);
+#pragma unroll
+    for (int c = 0; c < kHeadF; ++c) w[c][j] = *(const float4*)(Wt + c * D + 128 * j + 4 * i);
+  }
+  int mode = ode.mode;
+  float h = ode.h;
+  float* out = ode.out;
+  if (ode.desc && !ode.tok_event) {
+    const StageDesc sd = ode.desc[*ode.ctr];
+    mode = sd.mode;
+    h = sd.h;
+    if (!sd.write_out) out = nullptr;
+  }
+  const float bias = i < kHeadF ? b[i] : 0.f;
+#pragma unroll
+  for (int it = 0; it < kHeadIter; ++it) {
+    const int64_t r = 2 * (p0 + it) + half;
+    float part[kHeadF];
+#pragma unroll
+    for (int c = 0; c < kHeadF; ++c) part[c] = 0.f;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const float y[4] = {fmaf((hv[it][j].x - st[it].x) * st[it].y, gv[j].x, sv[j].x),
+                          fmaf((hv[it][j].y - st[it].x) * st[it].y, gv[j].y, sv[j].y),
+                          fmaf((hv[it][j].z - st[it].x) * st[it].y, gv[j].z, sv[j].z),
+                          fmaf((hv[it][j].w - st[it].x) * st[it].y, gv[j].w, sv[j].w)};
+#pragma unroll
+      for (int c = 0; c < kHeadF; ++c) {
+        part[c] = fmaf(y[0], w[c][j].x, part[c]);
+        part[c] = fmaf(y[1], w[c][j].y, part[c]);
+        part[c] = fmaf(y[2], w[c][j].z, part[c]);
+        part[c] = fmaf(y[3], w[c][j].w, part[c]);
+      }
+    }
+    float v = 0.f;
+#pragma unroll
+    for (int c = 0; c < kHeadF; ++c) {
+      const float tot = half_wave_sum(part[c]);
+      v = i == c ? tot : v;
+    }
+    if (i < kHeadF && r < T) {
+      const int64_t o = r * ode.ldx + i;
+      if (ode.tok_event) {
+        const StageDesc sd = ode.desc[ode.tok_event[r]];
+        ode_update(sd.mode, sd.h, v + bias, ode.x + o, ode.acc + o, ode.xs + o,
+                   out && sd.write_out ? out + r * ode.ldo + i : nullptr);
+      } else {
+        ode_update(mode, h, v + bias, ode.x + o, ode.acc + o, ode.xs + o,
+                   out ? out + r * ode.ldo + i : nullptr);
+      }
+    }
+  }
+}
+
+bool head256_supported(int d, int nf) { return d == 256 && nf == kHeadF; }
+
+hipError_t launch_head256(hipStream_t st, const float* H, const float2* stats, const float* g,
+                          const float* s, const float* Wt, const float* b, const OdeArgs& ode) {
+  if (ode.nf != kHeadF) return hipErrorInvalidValue;
+  if (ode.m_valid <= 0) return hipSuccess;
+  const int64_t waves = (ode.m_valid + 2 * kHeadIter - 1) / (2 * kHeadIter);
+  hipLaunchKernelGGL(k_head256, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, H, stats, g,
+                     s, Wt, b, ode);
   return hipGetLastError();
 }
 
