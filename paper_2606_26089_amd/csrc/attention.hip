@@ -242,8 +242,8 @@ __device__ __forceinline__ int vt_pos(int k) {
 }  // namespace
 
 __device__ __forceinline__ void attention32_body(
-    const bf16* __restrict__ Q, int ldq, const bf16* __restrict__ Kp,
-    const bf16* __restrict__ Vp, int ldkv, bf16* __restrict__ O, int ldo,
+    const bf16* __restrict__ Q, int ldq, int64_t hsq, const bf16* __restrict__ Kp,
+    const bf16* __restrict__ Vp, int ldkv, int64_t hskv, bf16* __restrict__ O, int ldo,
     const int64_t* __restrict__ q_off, const int64_t* __restrict__ kv_off,
     const int2* __restrict__ work, const AttnBins& bins, int n_heads, float sl2e) {
   __shared__ __attribute__((aligned(16))) bf16 Ks[kKc2 * kLdK32];
@@ -268,7 +268,7 @@ __device__ __forceinline__ void attention32_body(
 
   bf16x8 qf;
   {
-    const char* qc = (const char*)(Q + qs0 * ldq + h * kH32);
+    const char* qc = (const char*)(Q + qs0 * ldq + h * hsq);
     u32x4 v = *(const u32x4*)(qc + (uint32_t)((min(qi, nq - 1) * ldq + 8 * g) * 2));
     if (qi >= nq) v = u32x4{0u, 0u, 0u, 0u};
     qf = __builtin_bit_cast(bf16x8, v);
@@ -284,7 +284,7 @@ __device__ __forceinline__ void attention32_body(
     // add nothing to P V or to the row sums. No per-score masking is needed.
     const int lim = nk - 1 - c0;
     if (wave >= 2) {   // K: 128 keys x 4 chunks of 16 bytes
-      const char* kc = (const char*)(Kp + (ks0 + c0) * ldkv + h * kH32);
+      const char* kc = (const char*)(Kp + (ks0 + c0) * ldkv + h * hskv);
       const int t2 = tid - 128;
       u32x4 v[4];
 #pragma unroll
@@ -298,7 +298,7 @@ __device__ __forceinline__ void attention32_body(
         *(u32x4*)&Ks[row * kLdK32 + ch * 8] = v[i];
       }
     } else {           // V^T: thread = (4 consecutive keys, 8 consecutive dims)
-      const char* vc = (const char*)(Vp + (ks0 + c0) * ldkv + h * kH32);
+      const char* vc = (const char*)(Vp + (ks0 + c0) * ldkv + h * hskv);
       const int kg = tid & 31, dg = tid >> 5;
       u32x4 v[4];
 #pragma unroll
@@ -387,18 +387,20 @@ __device__ __forceinline__ void attention32_body(
 }
 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_attn32_self(
-    const bf16* __restrict__ Q, int ldq, const bf16* __restrict__ K, const bf16* __restrict__ V,
-    int ldkv, bf16* __restrict__ O, int ldo, const int64_t* __restrict__ q_off,
-    const int64_t* __restrict__ kv_off, const int2* __restrict__ work, AttnBins bins,
-    int n_heads, float sl2e) {
-  attention32_body(Q, ldq, K, V, ldkv, O, ldo, q_off, kv_off, work, bins, n_heads, sl2e);
+    const bf16* __restrict__ Q, int ldq, int64_t hsq, const bf16* __restrict__ K,
+    const bf16* __restrict__ V, int ldkv, int64_t hskv, bf16* __restrict__ O, int ldo,
+    const int64_t* __restrict__ q_off, const int64_t* __restrict__ kv_off,
+    const int2* __restrict__ work, AttnBins bins, int n_heads, float sl2e) {
+  attention32_body(Q, ldq, hsq, K, V, ldkv, hskv, O, ldo, q_off, kv_off, work, bins, n_heads,
+                   sl2e);
 }
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_attn32_cross(
-    const bf16* __restrict__ Q, int ldq, const bf16* __restrict__ K, const bf16* __restrict__ V,
-    int ldkv, bf16* __restrict__ O, int ldo, const int64_t* __restrict__ q_off,
-    const int64_t* __restrict__ kv_off, const int2* __restrict__ work, AttnBins bins,
-    int n_heads, float sl2e) {
-  attention32_body(Q, ldq, K, V, ldkv, O, ldo, q_off, kv_off, work, bins, n_heads, sl2e);
+    const bf16* __restrict__ Q, int ldq, int64_t hsq, const bf16* __restrict__ K,
+    const bf16* __restrict__ V, int ldkv, int64_t hskv, bf16* __restrict__ O, int ldo,
+    const int64_t* __restrict__ q_off, const int64_t* __restrict__ kv_off,
+    const int2* __restrict__ work, AttnBins bins, int n_heads, float sl2e) {
+  attention32_body(Q, ldq, hsq, K, V, ldkv, hskv, O, ldo, q_off, kv_off, work, bins, n_heads,
+                   sl2e);
 }
 
 template <typename T, int DH>
@@ -459,28 +461,31 @@ int attention_query_tile(bool bf16, int dh, int n_heads) {
 
 template <typename T>
 hipError_t launch_attention(hipStream_t st, bool cross, int dh, int n_heads, int64_t n_items,
-                            const AttnBins& bins, const int2* work, const T* Q, int ldq, const T* K, const T* V,
-                            int ldkv, T* O, int ldo, const int64_t* q_off,
-                            const int64_t* kv_off) {
+                            const AttnBins& bins, const int2* work, const T* Q, int ldq,
+                            int64_t hsq, const T* K, const T* V, int ldkv, int64_t hskv, T* O,
+                            int ldo, const int64_t* q_off, const int64_t* kv_off) {
   if (n_items <= 0) return hipSuccess;
   if (n_items > 0x7fffffff) return hipErrorInvalidValue;
   const float sl2e = 1.4426950408889634f / sqrtf((float)dh);
   if constexpr (std::is_same<T, bf16>::value) {
     if (dh == kH32) {
       // 16-byte row chunks: row pitches and head offsets are multiples of 8 elements
-      if (ldq % 8 || ldkv % 8 || ldo % 8) return hipErrorInvalidValue;
+      if (ldq % 8 || ldkv % 8 || ldo % 8 || hsq % 8 || hskv % 8 || hsq < dh || hskv < dh)
+        return hipErrorInvalidValue;
       const int64_t blocks = (int64_t)kAttnBins * bins.max_len * n_heads;
       if (blocks > 0x7fffffff) return hipErrorInvalidValue;
       if (blocks == 0) return hipSuccess;
       if (cross)
-        hipLaunchKernelGGL(k_attn32_cross, dim3((unsigned)blocks), dim3(256), 0, st, Q, ldq, K,
-                           V, ldkv, O, ldo, q_off, kv_off, work, bins, n_heads, sl2e);
+        hipLaunchKernelGGL(k_attn32_cross, dim3((unsigned)blocks), dim3(256), 0, st, Q, ldq, hsq,
+                           K, V, ldkv, hskv, O, ldo, q_off, kv_off, work, bins, n_heads, sl2e);
       else
-        hipLaunchKernelGGL(k_attn32_self, dim3((unsigned)blocks), dim3(256), 0, st, Q, ldq, K, V,
-                           ldkv, O, ldo, q_off, kv_off, work, bins, n_heads, sl2e);
+        hipLaunchKernelGGL(k_attn32_self, dim3((unsigned)blocks), dim3(256), 0, st, Q, ldq, hsq,
+                           K, V, ldkv, hskv, O, ldo, q_off, kv_off, work, bins, n_heads, sl2e);
       return hipGetLastError();
     }
   }
+  // the general kernel takes row-major operands only
+  if (hsq != dh || hskv != dh) return hipErrorInvalidValue;
   const dim3 grid((unsigned)n_items, n_heads);
   switch (dh) {
     case 16: return go_attn<T, 16>(cross, grid, st, Q, ldq, K, V, ldkv, O, ldo, q_off, kv_off, work, sl2e);
@@ -491,12 +496,12 @@ hipError_t launch_attention(hipStream_t st, bool cross, int dh, int n_heads, int
 }
 
 template hipError_t launch_attention<float>(hipStream_t, bool, int, int, int64_t,
-                                            const AttnBins&, const int2*,
-                                            const float*, int, const float*, const float*, int,
+                                            const AttnBins&, const int2*, const float*, int,
+                                            int64_t, const float*, const float*, int, int64_t,
                                             float*, int, const int64_t*, const int64_t*);
 template hipError_t launch_attention<bf16>(hipStream_t, bool, int, int, int64_t,
-                                           const AttnBins&, const int2*,
-                                           const bf16*, int, const bf16*, const bf16*, int,
+                                           const AttnBins&, const int2*, const bf16*, int,
+                                           int64_t, const bf16*, const bf16*, int, int64_t,
                                            bf16*, int, const int64_t*, const int64_t*);
 
 }  // namespace fmd

@@ -27,6 +27,7 @@ namespace fmd {
 namespace {
 
 constexpr int kD = 256;              // model width
+constexpr int kDh = 32;              // head width: wave w of a 256-wide slab = head w
 constexpr int kBM = 128;             // token rows per workgroup
 constexpr int kWaves = 8;            // wave w owns columns [32w, 32w + 32) of a 256-wide slab
 constexpr int kThreads = 64 * kWaves;
@@ -369,6 +370,7 @@ __global__ __launch_bounds__(kThreads) void k_fused_qkv(const float* __restrict_
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int64_t m0 = (int64_t)blockIdx.x * ROWS;
+  const int64_t plane = (int64_t)gridDim.x * ROWS * kDh;   // Mp rows x 32 per head
   const int col = w * 32 + (lane & 31);
   const u32x4* wf = Wf + w * kKs * 64;            // slab s: + s * kWaves * kKs * 64
   u32x4 ring[kRing];
@@ -384,7 +386,8 @@ __global__ __launch_bounds__(kThreads) void k_fused_qkv(const float* __restrict_
     const u32x4* cur = wf + slab * kWaves * kKs * 64;
     mfma_phase<TM>(acc, A, kLdA, 0, kKs, ring, cur, slab < 2 ? cur + kWaves * kKs * 64 : cur,
                   lane);
-    store_rows_bf16<3 * kD>(acc, qkv, m0, slab * kD + col, lane);
+    // head-major: wave w of slab s (Q, K, V) writes head w's plane (8 s + w), rows contiguous
+    store_rows_bf16<kDh>(acc, qkv + (int64_t)(slab * kWaves + w) * plane, m0, lane & 31, lane);
   }
 }
 
@@ -399,6 +402,7 @@ __global__ __launch_bounds__(kThreads) void k_fused_oqc(
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int64_t m0 = (int64_t)blockIdx.x * ROWS;
+  const int64_t plane = (int64_t)gridDim.x * ROWS * kDh;   // Mp rows x 32 per head
   const int col = w * 32 + (lane & 31);
   const u32x4* wo = Wf_o + w * kKs * 64;
   const u32x4* wq = Wf_qc + w * kKs * 64;
@@ -416,7 +420,7 @@ __global__ __launch_bounds__(kThreads) void k_fused_oqc(
   __syncthreads();
   zero(acc, b_qc, col);
   mfma_phase<TM>(acc, A, kLdA, 0, kKs, ring, wq, wq, lane);
-  store_rows_bf16<kD>(acc, qc, m0, col, lane);
+  store_rows_bf16<kDh>(acc, qc + (int64_t)w * plane, m0, lane & 31, lane);   // head-major
 }
 
 template <int TM>

@@ -448,9 +448,16 @@ int net_forward(fmd_model* m, Call& c, const float* t_ev) {
       }));
     }
     FMD_TRY(timed(m, c.st, FMD_K_ATTN_SELF, 4.0 * c.sum_n2 * d, Td * 4 * d * es, [&] {
+      if (fz & FMD_FUSED_QKV) {   // head-major [3][heads][Tp][dh]
+        const int64_t pl = c.Tp * dh;
+        return launch_attention<T>(c.st, false, dh, Hh, c.items, c.bins, w.work, (const T*)qkv, dh,
+                                   pl, (const T*)(qkv + Hh * pl * es),
+                                   (const T*)(qkv + 2 * Hh * pl * es), dh, pl, (T*)w.att, d,
+                                   w.off, w.off);
+      }
       return launch_attention<T>(c.st, false, dh, Hh, c.items, c.bins, w.work, (const T*)qkv, 3 * d,
-                                 (const T*)(qkv + d * es), (const T*)(qkv + 2 * d * es), 3 * d,
-                                 (T*)w.att, d, w.off, w.off);
+                                 dh, (const T*)(qkv + d * es), (const T*)(qkv + 2 * d * es), 3 * d,
+                                 dh, (T*)w.att, d, w.off, w.off);
     }));
     if (fz & FMD_FUSED_OQC) {
       FMD_TRY(timed(m, c.st, FMD_K_FUSED_OQC, 2.0 * Td * dd * dd * 2,
@@ -472,9 +479,12 @@ int net_forward(fmd_model* m, Call& c, const float* t_ev) {
     }
     FMD_TRY(timed(m, c.st, FMD_K_ATTN_CROSS, 4.0 * c.sum_n2 * d, Td * 4 * d * es, [&] {
       const size_t o = (size_t)l * 2 * d * es;
-      return launch_attention<T>(c.st, true, dh, Hh, c.items, c.bins, w.work, (const T*)w.qc, d,
-                                 (const T*)(kv + o), (const T*)(kv + o + d * es), 2 * d * L,
-                                 (T*)w.att, d, w.off, w.off);
+      // the cross query is head-major [heads][Tp][dh] when the fused kernel formed it
+      const bool hm = (fz & FMD_FUSED_OQC) != 0;
+      return launch_attention<T>(c.st, true, dh, Hh, c.items, c.bins, w.work, (const T*)w.qc,
+                                 hm ? dh : d, hm ? c.Tp * dh : dh, (const T*)(kv + o),
+                                 (const T*)(kv + o + d * es), 2 * d * L, dh, (T*)w.att, d, w.off,
+                                 w.off);
     }));
     if (fz & FMD_FUSED_MLP) {
       FMD_TRY(timed(m, c.st, FMD_K_FUSED_MLP, 2.0 * Td * dd * dd * 9,
@@ -1192,11 +1202,12 @@ int fmd_debug_attention(int32_t precision, int64_t n_events, const int64_t* q_of
       if (e == hipSuccess) e = launch_convert<bf16>(st, V, Tk * ld, (bf16*)Vp);
       if (e == hipSuccess)
         e = launch_attention<bf16>(st, false, dh, n_heads, (int64_t)work.size(), bins, wk, (const bf16*)Qp, ld,
-                                   (const bf16*)Kp, (const bf16*)Vp, ld, (bf16*)Op, ld, qo, ko);
+                                   dh, (const bf16*)Kp, (const bf16*)Vp, ld, dh, (bf16*)Op, ld, qo, ko);
       if (e == hipSuccess) e = launch_to_f32<bf16>(st, (const bf16*)Op, Tq * ld, O);
     } else {
       if (e == hipSuccess)
-        e = launch_attention<float>(st, false, dh, n_heads, (int64_t)work.size(), bins, wk, Q, ld, K, V, ld, O, ld, qo, ko);
+        e = launch_attention<float>(st, false, dh, n_heads, (int64_t)work.size(), bins, wk, Q, ld, dh, K, V, ld,
+                                    dh, O, ld, qo, ko);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) status = fail(FMD_E_DEVICE, "debug attention: %s", hipGetErrorString(e));

@@ -98,12 +98,15 @@ int64_t build_attention_work(const int64_t* ids, const int64_t* lens, int64_t n,
                              int2* items, AttnBins* bins);
 
 // Masked multi-head attention over CSR events. work: int2 (event, 64-query tile) items.
+// Element (row, head, dim) of Q sits at Q[row * ldq + head * hsq + dim], of K / V at
+// [row * ldkv + head * hskv + dim]: hs = dh for row-major [rows, heads x dh] operands,
+// ld = dh and hs = plane size for head-major ones (BF16 with dh 32 only). O is row-major.
 template <typename T>
 hipError_t launch_attention(hipStream_t st, bool cross, int dh, int n_heads, int64_t n_items,
                             const AttnBins& bins,
-                            const int2* work, const T* Q, int ldq, const T* K, const T* V,
-                            int ldkv, T* O, int ldo, const int64_t* q_off,
-                            const int64_t* kv_off);
+                            const int2* work, const T* Q, int ldq, int64_t hsq, const T* K,
+                            const T* V, int ldkv, int64_t hskv, T* O, int ldo,
+                            const int64_t* q_off, const int64_t* kv_off);
 
 hipError_t launch_token_map(hipStream_t st, const int64_t* off, int64_t E, int64_t T,
                             int32_t* tok_event);
@@ -160,10 +163,10 @@ hipError_t launch_pack_weight(hipStream_t st, const float* W, int K, int N, T* W
 bool fused_supported(int d_model, int mlp_ratio);
 // W: FP32 K x N (y = x W) -> BF16 MFMA B fragments [N/32][K/16][64 lanes][8].
 hipError_t launch_pack_frag(hipStream_t st, const float* W, int K, int N, void* Wf);
-// qkv[Mp, 3d] = LN(H; g, s) Wqkv + b
+// [Q | K | V] = LN(H; g, s) Wqkv + b, head-major: qkv [3][8 heads][Mp][32] (plane = Mp x 32)
 hipError_t launch_fused_qkv(hipStream_t st, int64_t Mp, const float* H, const float* g,
                             const float* s, const void* Wf, const float* bias, void* qkv);
-// H += att Wo + b_o;  qc = LN(H; g, s) Wqc + b_qc
+// H += att Wo + b_o;  qc = LN(H; g, s) Wqc + b_qc, head-major: qc [8 heads][Mp][32]
 hipError_t launch_fused_oqc(hipStream_t st, int64_t Mp, const void* att, const void* Wf_o,
                             const float* b_o, float* H, const float* g, const float* s,
                             const void* Wf_qc, const float* b_qc, void* qc);
