@@ -32,8 +32,8 @@ template <> struct AttnPad<bf16> { static constexpr int v = 8; };
 template <typename T, int DH>
 __device__ __forceinline__ void attention_body(
     const T* __restrict__ Q, int ldq, const T* __restrict__ Kp, const T* __restrict__ Vp,
-    int ldkv, T* __restrict__ O, int ldo, const int64_t* __restrict__ q_off,
-    const int64_t* __restrict__ kv_off, const int2* __restrict__ work, float scale_log2e) {
+    int ldkv, T* __restrict__ O, int ldo, const AttnItem* __restrict__ work,
+    float scale_log2e) {
   constexpr bool BF = sizeof(T) == 2;
   constexpr int PAD = AttnPad<T>::v;
   constexpr int DB = DH / 16;                 // 16-wide output blocks along dh
@@ -44,11 +44,11 @@ __device__ __forceinline__ void attention_body(
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, j = lane & 15;
-  const int2 wk = work[blockIdx.x];
-  const int e = wk.x, h = blockIdx.y;
-  const int64_t qs = q_off[e], ks = kv_off[e];
-  const int nq = (int)(q_off[e + 1] - qs), nk = (int)(kv_off[e + 1] - ks);
-  const int qbase = wk.y * QT + wave * 16;
+  const AttnItem wk = work[blockIdx.x];     // rows are those of the item's query tile
+  const int h = blockIdx.y;
+  const int64_t qs = wk.q0, ks = wk.k0;
+  const int nq = wk.nq, nk = wk.nk;
+  const int qbase = wave * 16;
   const bool wave_active = qbase < nq;
   const int qi = qbase + j;
   const bool qvalid = qi < nq;
@@ -203,9 +203,8 @@ __device__ __forceinline__ void attention_body(
   template <typename T, int DH>                                                               \
   __global__ __launch_bounds__(256) void NAME(                                                \
       const T* __restrict__ Q, int ldq, const T* __restrict__ K, const T* __restrict__ V,     \
-      int ldkv, T* __restrict__ O, int ldo, const int64_t* __restrict__ q_off,                \
-      const int64_t* __restrict__ kv_off, const int2* __restrict__ work, float sl2e) {        \
-    attention_body<T, DH>(Q, ldq, K, V, ldkv, O, ldo, q_off, kv_off, work, sl2e);             \
+      int ldkv, T* __restrict__ O, int ldo, const AttnItem* __restrict__ work, float sl2e) {  \
+    attention_body<T, DH>(Q, ldq, K, V, ldkv, O, ldo, work, sl2e);                            \
   }
 FMD_ATTN_KERNEL(k_attn_self)
 FMD_ATTN_KERNEL(k_attn_cross)
@@ -244,8 +243,7 @@ __device__ __forceinline__ int vt_pos(int k) {
 __device__ __forceinline__ void attention32_body(
     const bf16* __restrict__ Q, int ldq, int64_t hsq, const bf16* __restrict__ Kp,
     const bf16* __restrict__ Vp, int ldkv, int64_t hskv, bf16* __restrict__ O, int ldo,
-    const int64_t* __restrict__ q_off, const int64_t* __restrict__ kv_off,
-    const int2* __restrict__ work, const AttnBins& bins, int n_heads, float sl2e) {
+    const AttnItem* __restrict__ work, const AttnBins& bins, int n_heads, float sl2e) {
   __shared__ __attribute__((aligned(16))) bf16 Ks[kKc2 * kLdK32];
   // V^T rows 0-31; row 32 = key validity (1 for a key of the event, 0 past its end), rows
   // 33-47 = 0: the A operand of the row-sum block of P V
@@ -257,12 +255,12 @@ __device__ __forceinline__ void attention32_body(
   const int bin = blockIdx.x % kAttnBins, k = blockIdx.x / kAttnBins;
   const int item = k / n_heads;
   if (item >= bins.len[bin]) return;     // the bin is shorter than the longest one
-  const int2 wk = work[bins.start[bin] + item];
+  // the item carries its rows: no dependent loads of event offsets before the data loads
+  const AttnItem wk = work[bins.start[bin] + item];
   const int h = k % n_heads;
-  const int e = wk.x;
-  const int64_t qs0 = q_off[e], ks0 = kv_off[e];
-  const int nq = (int)(q_off[e + 1] - qs0), nk = (int)(kv_off[e + 1] - ks0);
-  const int qbase = wk.y * QT + wave * 16;
+  const int64_t qs0 = wk.q0, ks0 = wk.k0;
+  const int nq = wk.nq, nk = wk.nk;
+  const int qbase = wave * 16;
   const bool wave_active = qbase < nq;
   const int qi = qbase + j;
 
@@ -389,43 +387,45 @@ __device__ __forceinline__ void attention32_body(
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_attn32_self(
     const bf16* __restrict__ Q, int ldq, int64_t hsq, const bf16* __restrict__ K,
     const bf16* __restrict__ V, int ldkv, int64_t hskv, bf16* __restrict__ O, int ldo,
-    const int64_t* __restrict__ q_off, const int64_t* __restrict__ kv_off,
-    const int2* __restrict__ work, AttnBins bins, int n_heads, float sl2e) {
-  attention32_body(Q, ldq, hsq, K, V, ldkv, hskv, O, ldo, q_off, kv_off, work, bins, n_heads,
-                   sl2e);
+    const AttnItem* __restrict__ work, AttnBins bins, int n_heads, float sl2e) {
+  attention32_body(Q, ldq, hsq, K, V, ldkv, hskv, O, ldo, work, bins, n_heads, sl2e);
 }
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_attn32_cross(
     const bf16* __restrict__ Q, int ldq, int64_t hsq, const bf16* __restrict__ K,
     const bf16* __restrict__ V, int ldkv, int64_t hskv, bf16* __restrict__ O, int ldo,
-    const int64_t* __restrict__ q_off, const int64_t* __restrict__ kv_off,
-    const int2* __restrict__ work, AttnBins bins, int n_heads, float sl2e) {
-  attention32_body(Q, ldq, hsq, K, V, ldkv, hskv, O, ldo, q_off, kv_off, work, bins, n_heads,
-                   sl2e);
+    const AttnItem* __restrict__ work, AttnBins bins, int n_heads, float sl2e) {
+  attention32_body(Q, ldq, hsq, K, V, ldkv, hskv, O, ldo, work, bins, n_heads, sl2e);
 }
 
 template <typename T, int DH>
 static hipError_t go_attn(bool cross, dim3 grid, hipStream_t st, const T* Q, int ldq,
-                          const T* K, const T* V, int ldkv, T* O, int ldo, const int64_t* q_off,
-                          const int64_t* kv_off, const int2* work, float sl2e) {
+                          const T* K, const T* V, int ldkv, T* O, int ldo,
+                          const AttnItem* work, float sl2e) {
   if (cross)
     hipLaunchKernelGGL((k_attn_cross<T, DH>), grid, dim3(256), 0, st, Q, ldq, K, V, ldkv, O, ldo,
-                       q_off, kv_off, work, sl2e);
+                       work, sl2e);
   else
     hipLaunchKernelGGL((k_attn_self<T, DH>), grid, dim3(256), 0, st, Q, ldq, K, V, ldkv, O, ldo,
-                       q_off, kv_off, work, sl2e);
+                       work, sl2e);
   return hipGetLastError();
 }
 
-int64_t build_attention_work(const int64_t* ids, const int64_t* lens, int64_t n, int qt,
-                             int2* items, AttnBins* bins) {
+int64_t build_attention_work(const int64_t* q_off, const int64_t* kv_off, const int64_t* ids,
+                             int64_t n, int qt, AttnItem* items, AttnBins* bins) {
   // longest-processing-time assignment of whole events to bins; cost = query tiles x keys
+  auto nq = [&](int64_t k) { return q_off[ids[k] + 1] - q_off[ids[k]]; };
+  auto nk = [&](int64_t k) { return kv_off[ids[k] + 1] - kv_off[ids[k]]; };
   std::vector<int64_t> order;
   order.reserve((size_t)n);
-  for (int64_t k = 0; k < n; ++k)
-    if (lens[k] > 0) order.push_back(k);
-  auto cost = [&](int64_t k) { return ((lens[k] + qt - 1) / qt) * lens[k]; };
+  for (int64_t k = 0; k < n; ++k) {
+    if (nq(k) <= 0) continue;
+    if (q_off[ids[k] + 1] > INT32_MAX || kv_off[ids[k] + 1] > INT32_MAX) return -1;
+    order.push_back(k);
+  }
+  auto tiles = [&](int64_t k) { return (nq(k) + qt - 1) / qt; };
+  auto cost = [&](int64_t k) { return tiles(k) * nk(k); };
   std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return cost(a) > cost(b); });
-  std::vector<int64_t> bin_of(order.size());
+  std::vector<int> bin_of(order.size());
   int64_t load[kAttnBins] = {0};
   int64_t cnt[kAttnBins] = {0};
   for (size_t i = 0; i < order.size(); ++i) {
@@ -434,7 +434,7 @@ int64_t build_attention_work(const int64_t* ids, const int64_t* lens, int64_t n,
       if (load[b] < load[best]) best = b;
     bin_of[i] = best;
     load[best] += cost(order[i]);
-    cnt[best] += (lens[order[i]] + qt - 1) / qt;
+    cnt[best] += tiles(order[i]);
   }
   int64_t pos = 0;
   bins->max_len = 0;
@@ -444,9 +444,11 @@ int64_t build_attention_work(const int64_t* ids, const int64_t* lens, int64_t n,
     bins->max_len = std::max<int32_t>(bins->max_len, (int32_t)cnt[b]);
     for (size_t i = 0; i < order.size(); ++i) {
       if (bin_of[i] != b) continue;
-      const int64_t k = order[i];
-      for (int64_t q = 0; q < (lens[k] + qt - 1) / qt; ++q)
-        items[pos++] = make_int2((int)ids[k], (int)q);
+      const int64_t k = order[i], e = ids[k];
+      for (int64_t q = 0; q < tiles(k); ++q)
+        items[pos++] = AttnItem{(int32_t)(q_off[e] + q * qt),
+                                (int32_t)std::min<int64_t>(qt, nq(k) - q * qt),
+                                (int32_t)kv_off[e], (int32_t)nk(k)};
     }
   }
   return pos;
@@ -461,9 +463,9 @@ int attention_query_tile(bool bf16, int dh, int n_heads) {
 
 template <typename T>
 hipError_t launch_attention(hipStream_t st, bool cross, int dh, int n_heads, int64_t n_items,
-                            const AttnBins& bins, const int2* work, const T* Q, int ldq,
+                            const AttnBins& bins, const AttnItem* work, const T* Q, int ldq,
                             int64_t hsq, const T* K, const T* V, int ldkv, int64_t hskv, T* O,
-                            int ldo, const int64_t* q_off, const int64_t* kv_off) {
+                            int ldo) {
   if (n_items <= 0) return hipSuccess;
   if (n_items > 0x7fffffff) return hipErrorInvalidValue;
   const float sl2e = 1.4426950408889634f / sqrtf((float)dh);
@@ -477,10 +479,10 @@ hipError_t launch_attention(hipStream_t st, bool cross, int dh, int n_heads, int
       if (blocks == 0) return hipSuccess;
       if (cross)
         hipLaunchKernelGGL(k_attn32_cross, dim3((unsigned)blocks), dim3(256), 0, st, Q, ldq, hsq,
-                           K, V, ldkv, hskv, O, ldo, q_off, kv_off, work, bins, n_heads, sl2e);
+                           K, V, ldkv, hskv, O, ldo, work, bins, n_heads, sl2e);
       else
         hipLaunchKernelGGL(k_attn32_self, dim3((unsigned)blocks), dim3(256), 0, st, Q, ldq, hsq,
-                           K, V, ldkv, hskv, O, ldo, q_off, kv_off, work, bins, n_heads, sl2e);
+                           K, V, ldkv, hskv, O, ldo, work, bins, n_heads, sl2e);
       return hipGetLastError();
     }
   }
@@ -488,20 +490,20 @@ hipError_t launch_attention(hipStream_t st, bool cross, int dh, int n_heads, int
   if (hsq != dh || hskv != dh) return hipErrorInvalidValue;
   const dim3 grid((unsigned)n_items, n_heads);
   switch (dh) {
-    case 16: return go_attn<T, 16>(cross, grid, st, Q, ldq, K, V, ldkv, O, ldo, q_off, kv_off, work, sl2e);
-    case 32: return go_attn<T, 32>(cross, grid, st, Q, ldq, K, V, ldkv, O, ldo, q_off, kv_off, work, sl2e);
-    case 64: return go_attn<T, 64>(cross, grid, st, Q, ldq, K, V, ldkv, O, ldo, q_off, kv_off, work, sl2e);
+    case 16: return go_attn<T, 16>(cross, grid, st, Q, ldq, K, V, ldkv, O, ldo, work, sl2e);
+    case 32: return go_attn<T, 32>(cross, grid, st, Q, ldq, K, V, ldkv, O, ldo, work, sl2e);
+    case 64: return go_attn<T, 64>(cross, grid, st, Q, ldq, K, V, ldkv, O, ldo, work, sl2e);
     default: return hipErrorInvalidValue;
   }
 }
 
 template hipError_t launch_attention<float>(hipStream_t, bool, int, int, int64_t,
-                                            const AttnBins&, const int2*, const float*, int,
+                                            const AttnBins&, const AttnItem*, const float*, int,
                                             int64_t, const float*, const float*, int, int64_t,
-                                            float*, int, const int64_t*, const int64_t*);
+                                            float*, int);
 template hipError_t launch_attention<bf16>(hipStream_t, bool, int, int, int64_t,
-                                           const AttnBins&, const int2*, const bf16*, int,
+                                           const AttnBins&, const AttnItem*, const bf16*, int,
                                            int64_t, const bf16*, const bf16*, int, int64_t,
-                                           bf16*, int, const int64_t*, const int64_t*);
+                                           bf16*, int);
 
 }  // namespace fmd

@@ -164,12 +164,12 @@ int ensure_ws_alloc(fmd_model* m, int64_t T, int64_t E, int64_t items, bool* gre
   }
   if (items > w.cap_items) {
     const int64_t cap = std::max(items, w.cap_items + w.cap_items / 4);
-    FMD_TRY(grow(w.work, (size_t)cap * sizeof(int2)));
+    FMD_TRY(grow(w.work, (size_t)cap * sizeof(AttnItem)));
     w.cap_items = cap;
     *grew = true;
   }
   if (items > w.h_cap_items) {
-    FMD_TRY(grow_host(w.h_work, (size_t)std::max<int64_t>(items, 1) * sizeof(int2)));
+    FMD_TRY(grow_host(w.h_work, (size_t)std::max<int64_t>(items, 1) * sizeof(AttnItem)));
     w.h_cap_items = items;
   }
   return FMD_OK;
@@ -249,13 +249,12 @@ int stage_events(fmd_model* m, const fmd_events_in* ev, Call& c) {
   // work items: (event, query tile), in bins of whole events balanced by attention work
   const int qt = attention_query_tile(m->cfg.precision == FMD_BF16, m->cfg.d_model / std::max(m->cfg.n_heads, 1),
                                       m->cfg.n_heads);
-  std::vector<int64_t> ids((size_t)E), lens((size_t)E);
+  std::vector<int64_t> ids((size_t)E);
   int64_t items = 0;
   double s2 = 0;
   for (int64_t e = 0; e < E; ++e) {
     const int64_t n = ev->offsets[e + 1] - ev->offsets[e];
     ids[e] = e;
-    lens[e] = n;
     items += (n + qt - 1) / qt;
     s2 += (double)n * (double)n;
   }
@@ -265,9 +264,10 @@ int stage_events(fmd_model* m, const fmd_events_in* ev, Call& c) {
   // The pinned staging buffers may still feed the previous call's copies.
   HIP_TRY(hipStreamSynchronize(c.st));
   std::memcpy(w.h_off, ev->offsets, (size_t)(E + 1) * 8);
-  build_attention_work(ids.data(), lens.data(), E, qt, w.h_work, &c.bins);
+  if (build_attention_work(w.h_off, w.h_off, ids.data(), E, qt, w.h_work, &c.bins) != items)
+    return fail(FMD_E_INVALID, "token rows beyond 2^31");
   HIP_TRY(hipMemcpyAsync(w.off, w.h_off, (size_t)(E + 1) * 8, hipMemcpyHostToDevice, c.st));
-  if (items) HIP_TRY(hipMemcpyAsync(w.work, w.h_work, (size_t)items * sizeof(int2), hipMemcpyHostToDevice, c.st));
+  if (items) HIP_TRY(hipMemcpyAsync(w.work, w.h_work, (size_t)items * sizeof(AttnItem), hipMemcpyHostToDevice, c.st));
   FMD_TRY(timed(m, c.st, FMD_K_OTHER, 0, [&] { return launch_token_map(c.st, w.off, E, c.T, w.tok_event); }));
   if (ev->on_device) {
     c.u = ev->feat;
@@ -452,12 +452,11 @@ int net_forward(fmd_model* m, Call& c, const float* t_ev) {
         const int64_t pl = c.Tp * dh;
         return launch_attention<T>(c.st, false, dh, Hh, c.items, c.bins, w.work, (const T*)qkv, dh,
                                    pl, (const T*)(qkv + Hh * pl * es),
-                                   (const T*)(qkv + 2 * Hh * pl * es), dh, pl, (T*)w.att, d,
-                                   w.off, w.off);
+                                   (const T*)(qkv + 2 * Hh * pl * es), dh, pl, (T*)w.att, d);
       }
       return launch_attention<T>(c.st, false, dh, Hh, c.items, c.bins, w.work, (const T*)qkv, 3 * d,
                                  dh, (const T*)(qkv + d * es), (const T*)(qkv + 2 * d * es), 3 * d,
-                                 dh, (T*)w.att, d, w.off, w.off);
+                                 dh, (T*)w.att, d);
     }));
     if (fz & FMD_FUSED_OQC) {
       FMD_TRY(timed(m, c.st, FMD_K_FUSED_OQC, 2.0 * Td * dd * dd * 2,
@@ -483,8 +482,7 @@ int net_forward(fmd_model* m, Call& c, const float* t_ev) {
       const bool hm = (fz & FMD_FUSED_OQC) != 0;
       return launch_attention<T>(c.st, true, dh, Hh, c.items, c.bins, w.work, (const T*)w.qc,
                                  hm ? dh : d, hm ? c.Tp * dh : dh, (const T*)(kv + o),
-                                 (const T*)(kv + o + d * es), 2 * d * L, dh, (T*)w.att, d, w.off,
-                                 w.off);
+                                 (const T*)(kv + o + d * es), 2 * d * L, dh, (T*)w.att, d);
     }));
     if (fz & FMD_FUSED_MLP) {
       FMD_TRY(timed(m, c.st, FMD_K_FUSED_MLP, 2.0 * Td * dd * dd * 9,
@@ -1165,54 +1163,52 @@ int fmd_debug_attention(int32_t precision, int64_t n_events, const int64_t* q_of
   if (n_heads < 1 || n_events < 0 || !q_offsets || !kv_offsets) return fail(FMD_E_INVALID, "bad arguments");
   if (q_offsets[0] != 0 || kv_offsets[0] != 0) return fail(FMD_E_INVALID, "offsets must start at 0");
   const int qt = attention_query_tile(precision == FMD_BF16, dh, n_heads);
-  std::vector<int64_t> ids((size_t)n_events), lens((size_t)n_events);
+  std::vector<int64_t> ids((size_t)n_events);
   int64_t n_items = 0;
   for (int64_t e = 0; e < n_events; ++e) {
     const int64_t nq = q_offsets[e + 1] - q_offsets[e], nk = kv_offsets[e + 1] - kv_offsets[e];
     if (nq < 0 || nk < 0) return fail(FMD_E_INVALID, "offsets decrease");
     if (nq > 0 && nk == 0) return fail(FMD_E_INVALID, "event %lld has queries but no keys", (long long)e);
     ids[e] = e;
-    lens[e] = nq;
     n_items += (nq + qt - 1) / qt;
   }
-  std::vector<int2> work((size_t)n_items);
+  std::vector<AttnItem> work((size_t)n_items);
   AttnBins bins{};
-  build_attention_work(ids.data(), lens.data(), n_events, qt, work.data(), &bins);
+  if (build_attention_work(q_offsets, kv_offsets, ids.data(), n_events, qt, work.data(), &bins) !=
+      n_items)
+    return fail(FMD_E_INVALID, "rows beyond 2^31");
   const int64_t Tq = q_offsets[n_events], Tk = kv_offsets[n_events];
   if (work.empty()) return FMD_OK;
   if (!Q || !K || !V || !O) return fail(FMD_E_INVALID, "null operand");
   hipStream_t st = (hipStream_t)hip_stream;
   const int ld = n_heads * dh;
   const size_t es = precision == FMD_BF16 ? 2 : 4;
-  int64_t *qo = nullptr, *ko = nullptr;
-  int2* wk = nullptr;
+  AttnItem* wk = nullptr;
   void *Qp = nullptr, *Kp = nullptr, *Vp = nullptr, *Op = nullptr;
   int status = FMD_OK;
-  if (grow(qo, (n_events + 1) * 8) || grow(ko, (n_events + 1) * 8) || grow(wk, work.size() * sizeof(int2)) ||
+  if (grow(wk, work.size() * sizeof(AttnItem)) ||
       grow(Qp, (size_t)Tq * ld * es) || grow(Kp, (size_t)Tk * ld * es) || grow(Vp, (size_t)Tk * ld * es) ||
       grow(Op, (size_t)Tq * ld * es)) {
     status = FMD_E_NOMEM;
   } else {
-    hipError_t e = hipMemcpy(qo, q_offsets, (n_events + 1) * 8, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(ko, kv_offsets, (n_events + 1) * 8, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(wk, work.data(), work.size() * sizeof(int2), hipMemcpyHostToDevice);
+    hipError_t e = hipMemcpy(wk, work.data(), work.size() * sizeof(AttnItem), hipMemcpyHostToDevice);
     if (precision == FMD_BF16) {
       if (e == hipSuccess) e = launch_convert<bf16>(st, Q, Tq * ld, (bf16*)Qp);
       if (e == hipSuccess) e = launch_convert<bf16>(st, K, Tk * ld, (bf16*)Kp);
       if (e == hipSuccess) e = launch_convert<bf16>(st, V, Tk * ld, (bf16*)Vp);
       if (e == hipSuccess)
         e = launch_attention<bf16>(st, false, dh, n_heads, (int64_t)work.size(), bins, wk, (const bf16*)Qp, ld,
-                                   dh, (const bf16*)Kp, (const bf16*)Vp, ld, dh, (bf16*)Op, ld, qo, ko);
+                                   dh, (const bf16*)Kp, (const bf16*)Vp, ld, dh, (bf16*)Op, ld);
       if (e == hipSuccess) e = launch_to_f32<bf16>(st, (const bf16*)Op, Tq * ld, O);
     } else {
       if (e == hipSuccess)
         e = launch_attention<float>(st, false, dh, n_heads, (int64_t)work.size(), bins, wk, Q, ld, dh, K, V, ld,
-                                    dh, O, ld, qo, ko);
+                                    dh, O, ld);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) status = fail(FMD_E_DEVICE, "debug attention: %s", hipGetErrorString(e));
   }
-  void* bufs[] = {qo, ko, wk, Qp, Kp, Vp, Op};
+  void* bufs[] = {wk, Qp, Kp, Vp, Op};
   for (void* p : bufs)
     if (p) (void)hipFree(p);
   return status;

@@ -40,11 +40,11 @@ struct Workspace {
   float2* stats = nullptr;         // [Tp] LayerNorm (mean, rstd) of the rows of H
   int32_t* tok_event = nullptr;    // [Tp]
   int64_t* off = nullptr;          // [E + 1]
-  int2* work = nullptr;            // attention work list
+  AttnItem* work = nullptr;        // attention work list
   StageDesc* desc = nullptr;       // [stages] stage table of the call
   int32_t* ctr = nullptr;          // current stage index (device)
   int64_t* h_off = nullptr;        // pinned staging
-  int2* h_work = nullptr;
+  AttnItem* h_work = nullptr;
   StageDesc* h_desc = nullptr;
   int64_t h_cap_ev = 0, h_cap_items = 0;
   int cap_desc = 0;

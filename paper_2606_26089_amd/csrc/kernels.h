@@ -91,22 +91,27 @@ struct AttnBins {
   int32_t start[kAttnBins], len[kAttnBins];
   int32_t max_len;
 };
-// Fills `items` (capacity >= sum over events of ceil(n / qt)) from per-event lengths:
-// events longest first within each bin, bins balanced by attention work (longest-processing-
-// time assignment). ids[k], lens[k]: event id and length; returns the item count.
-int64_t build_attention_work(const int64_t* ids, const int64_t* lens, int64_t n, int qt,
-                             int2* items, AttnBins* bins);
+// One attention work item: a query tile of one event, with its rows: queries
+// [q0, q0 + nq) (nq <= the query tile) against the event's keys [k0, k0 + nk).
+struct AttnItem {
+  int32_t q0, nq, k0, nk;
+};
+// Fills `items` (capacity >= sum over the events of ceil(n_q / qt)) for the events ids[0..n)
+// of the CSR offsets q_off / kv_off (host arrays): events with the most work first within
+// each bin, bins balanced by attention work (longest-processing-time assignment); events
+// without queries get no item. Returns the item count, or -1 if a row index exceeds 2^31-1.
+int64_t build_attention_work(const int64_t* q_off, const int64_t* kv_off, const int64_t* ids,
+                             int64_t n, int qt, AttnItem* items, AttnBins* bins);
 
-// Masked multi-head attention over CSR events. work: int2 (event, 64-query tile) items.
+// Masked multi-head attention over ragged events, one work item per (event, query tile).
 // Element (row, head, dim) of Q sits at Q[row * ldq + head * hsq + dim], of K / V at
 // [row * ldkv + head * hskv + dim]: hs = dh for row-major [rows, heads x dh] operands,
 // ld = dh and hs = plane size for head-major ones (BF16 with dh 32 only). O is row-major.
 template <typename T>
 hipError_t launch_attention(hipStream_t st, bool cross, int dh, int n_heads, int64_t n_items,
                             const AttnBins& bins,
-                            const int2* work, const T* Q, int ldq, int64_t hsq, const T* K,
-                            const T* V, int ldkv, int64_t hskv, T* O, int ldo,
-                            const int64_t* q_off, const int64_t* kv_off);
+                            const AttnItem* work, const T* Q, int ldq, int64_t hsq, const T* K,
+                            const T* V, int ldkv, int64_t hskv, T* O, int ldo);
 
 hipError_t launch_token_map(hipStream_t st, const int64_t* off, int64_t E, int64_t T,
                             int32_t* tok_event);

@@ -215,9 +215,11 @@ int iterate(fmd_server* S, std::vector<Req*>& finished) {
   std::memcpy(w.h_off, off.data(), (size_t)(E + 1) * 8);
   AttnBins bins{};
   {
-    std::vector<int64_t> ids(real.size()), lens(real.size());
-    for (size_t i = 0; i < real.size(); ++i) ids[i] = real[i].first, lens[i] = real[i].second;
-    build_attention_work(ids.data(), lens.data(), (int64_t)real.size(), qt, w.h_work, &bins);
+    std::vector<int64_t> ids(real.size());
+    for (size_t i = 0; i < real.size(); ++i) ids[i] = real[i].first;
+    if (build_attention_work(off.data(), off.data(), ids.data(), (int64_t)real.size(), qt, w.h_work,
+                             &bins) != items)
+      return fail(FMD_E_INVALID, "token rows beyond 2^31");
   }
   if (E > w.cap_desc) {
     FMD_TRY(grow(w.desc, (size_t)E * sizeof(StageDesc)));
@@ -227,7 +229,7 @@ int iterate(fmd_server* S, std::vector<Req*>& finished) {
   }
   std::memcpy(w.h_desc, desc.data(), (size_t)E * sizeof(StageDesc));
   HIP_TRY(hipMemcpyAsync(w.off, w.h_off, (size_t)(E + 1) * 8, hipMemcpyHostToDevice, S->st));
-  HIP_TRY(hipMemcpyAsync(w.work, w.h_work, (size_t)items * sizeof(int2), hipMemcpyHostToDevice, S->st));
+  HIP_TRY(hipMemcpyAsync(w.work, w.h_work, (size_t)items * sizeof(AttnItem), hipMemcpyHostToDevice, S->st));
   HIP_TRY(hipMemcpyAsync(w.desc, w.h_desc, (size_t)E * sizeof(StageDesc), hipMemcpyHostToDevice, S->st));
   HIP_TRY(hipMemcpyAsync(w.tev, tev.data(), (size_t)E * 4, hipMemcpyHostToDevice, S->st));
 
