@@ -2,14 +2,16 @@
 // pre-LayerNorm block: self-attention, cross-attention to the truth encoding, 4x GELU MLP),
 // written for model width d = 256 on gfx950.
 //
-// Every kernel works on 128 token rows with 8 waves. The rows' FP32 residual values live in
-// registers for the whole kernel, as a full-width accumulator: wave w holds columns
-// [32w, 32w + 32) of all 128 rows, in the 32x32 MFMA output layout (lane l, register r of
-// fragment mi: row 32 mi + 8 (r/4) + 4 (l/32) + r%4, column l%32). The A operands of the
-// products (an attention output tile, the LayerNorm of the residual rows, an MLP hidden
-// chunk) sit in LDS; the weights stream from L2 as pre-packed MFMA B fragments, 8 in flight
-// per wave, with no LDS staging and no barriers. LayerNorm statistics are computed inside
-// the kernel from the full rows (two passes: mean, then squared deviations).
+// The rows' FP32 residual values live in registers for the whole kernel, as a full-width
+// accumulator in the 32x32 MFMA output layout (lane l, register r of fragment mi: row
+// 32 mi + 8 (r/4) + 4 (l/32) + r%4, column l%32). k_fused_qkv and k_fused_oqc take 64 rows
+// with 8 waves, wave w holding columns [32w, 32w + 32); k_fused_mlp takes 64 rows with 4
+// waves, wave w holding columns [64w, 64w + 64), so that two of its workgroups share a CU
+// and overlap each other's barriers and memory phases. The A operands of the products (an
+// attention output tile, the LayerNorm of the residual rows, an MLP hidden chunk) sit in
+// LDS; the weights stream from L2 as pre-packed MFMA B fragments, 8 in flight per wave, with
+// no LDS staging. LayerNorm statistics are computed inside the kernel from the full rows
+// (two passes: mean, then squared deviations).
 //
 //   k_fused_qkv  LN1(H) -> [Q|K|V]
 //   k_fused_oqc  H += att W_o + b_o;  qc = LN2(H) W_qc + b_qc
@@ -128,21 +130,21 @@ __device__ __forceinline__ void zero(f32x16 (&acc)[TM], const float* __restrict_
 }
 
 // ROWS x 256 BF16 tile of S (pitch lds_) at rows m0.. into LDS (pitch kLdA).
-template <int ROWS>
+template <int ROWS, int NT = kThreads>
 __device__ __forceinline__ void tile_to_lds(bf16* __restrict__ A, const bf16* __restrict__ S,
                                             int lds_, int64_t m0, int tid) {
   constexpr int kChunks = ROWS * kD / 8;                // 16-byte chunks
-  constexpr int kPer = kChunks / kThreads;
+  constexpr int kPer = kChunks / NT;
   u32x4 v[kPer];
 #pragma unroll
   for (int i = 0; i < kPer; ++i) {
-    const int idx = tid + i * kThreads;
+    const int idx = tid + i * NT;
     v[i] = *(const u32x4*)((const char*)(S + m0 * lds_) +
                            (uint32_t)(((idx / (kD / 8)) * lds_ + (idx % (kD / 8)) * 8) * 2));
   }
 #pragma unroll
   for (int i = 0; i < kPer; ++i) {
-    const int idx = tid + i * kThreads;
+    const int idx = tid + i * NT;
     *(u32x4*)(A + (idx / (kD / 8)) * kLdA + (idx % (kD / 8)) * 8) = v[i];
   }
 }
@@ -318,20 +320,70 @@ __device__ __forceinline__ float gelu_as(float z) {
   return fmaf(hz, copysignf(erf_abs, x), hz);
 }
 
-// One up-projection chunk of the MLP (if UP): h2n = A[row0 + .., :] x W_up chunk (16
-// fragments from the ring; cur = the chunk's first fragment, next = the phase after it),
-// software-pipelined with the GELU of the previous chunk's products h2 (two values per
-// k step, + bias bv, BF16 into the LDS hidden tile hb). The MFMAs of one chunk and the
-// vector work of the other are independent, so they overlap in the SIMD.
-template <bool UP, int TA>
-__device__ __forceinline__ void up_and_gelu(f32x16 (&h2n)[TA], const f32x16 (&h2)[TA],
-                                            const bf16* __restrict__ A, int row0,
-                                            u32x4 (&ring)[kRing],
-                                            const u32x4* __restrict__ cur,
-                                            const u32x4* __restrict__ next, float bv,
-                                            bf16* __restrict__ hb, int hcol, int lane) {
+// ---- helpers of the 64-row MLP kernel: four waves, wave w owning output column blocks
+// 2w and 2w + 1 (64 columns) of all rows and hidden column block w of every chunk.
+constexpr int kWaves4 = 4;
+constexpr int kThreads4 = 64 * kWaves4;
+
+// Fragment t of a weight stream over NC column blocks taken together: K step t / NC of
+// column block t % NC (blocks cstride fragments-of-64-lanes apart).
+template <int NC>
+__device__ __forceinline__ const u32x4* frag_at(const u32x4* p, int cstride, int t) {
+  return p + (t % NC) * cstride + (t / NC) * 64;
+}
+
+template <int NC>
+__device__ __forceinline__ void ring_fill_nc(u32x4 (&ring)[kRing], const u32x4* __restrict__ p,
+                                             int cstride, int lane) {
+#pragma unroll
+  for (int t = 0; t < kRing; ++t) ring[t] = frag_at<NC>(p, cstride, t)[lane];
+}
+
+// acc[mi][nj] += A[row0 + 32 mi + .., K] x B[K, column block nj] over NK K steps (A in LDS,
+// pitch ld). Fragment t = NC k + nj sits in ring slot t % kRing; on use the slot is refilled
+// with fragment t + kRing of this stream or, past its end, of the next phase's stream
+// (NCN column blocks, stride nstride), unless kNext is false.
+template <int TM, int NC, int NK, int NCN, bool kNext>
+__device__ __forceinline__ void mfma_phase_nc(f32x16 (&acc)[TM][NC], const bf16* __restrict__ lds,
+                                              int ld, int row0, u32x4 (&ring)[kRing],
+                                              const u32x4* __restrict__ cur, int cstride,
+                                              const u32x4* __restrict__ next, int nstride,
+                                              int lane) {
   asm volatile("" ::: "memory");
-  const bf16* arow = A + (row0 + (lane & 31)) * kLdA + (lane >> 5) * 8;
+  constexpr int F = NC * NK;
+  const bf16* arow = lds + (row0 + (lane & 31)) * ld + (lane >> 5) * 8;
+#pragma unroll
+  for (int k = 0; k < NK; ++k) {
+    bf16x8 a[TM];
+#pragma unroll
+    for (int mi = 0; mi < TM; ++mi) a[mi] = *(const bf16x8*)(arow + mi * 32 * ld + k * 16);
+#pragma unroll
+    for (int nj = 0; nj < NC; ++nj) {
+      const int t = k * NC + nj;
+      const bf16x8 b = as_bf16x8(ring[t % kRing]);
+      if (t + kRing < F)
+        ring[t % kRing] = frag_at<NC>(cur, cstride, t + kRing)[lane];
+      else if (kNext)
+        ring[t % kRing] = frag_at<NCN>(next, nstride, t + kRing - F)[lane];
+#pragma unroll
+      for (int mi = 0; mi < TM; ++mi)
+        acc[mi][nj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[mi], b, acc[mi][nj], 0, 0, 0);
+    }
+  }
+}
+
+// Up-projection of one hidden chunk for all rows (if UP: h2n += LN tile x W_up chunk, one
+// column block, 16 K steps) software-pipelined with the GELU of the previous chunk's
+// products h2 (two values per K step, + bias bv, BF16 into the hidden tile hb at column
+// hcol); the prefetch past the end reads the next phase's stream (NCN blocks).
+template <bool UP, int TA, int NCN>
+__device__ __forceinline__ void up_gelu_nc(f32x16 (&h2n)[TA][1], const f32x16 (&h2)[TA][1],
+                                           const bf16* __restrict__ A, u32x4 (&ring)[kRing],
+                                           const u32x4* __restrict__ cur,
+                                           const u32x4* __restrict__ next, int nstride, float bv,
+                                           bf16* __restrict__ hb, int hcol, int lane) {
+  asm volatile("" ::: "memory");
+  const bf16* arow = A + (lane & 31) * kLdA + (lane >> 5) * 8;
 #pragma unroll
   for (int ks = 0; ks < kKs; ++ks) {
     if constexpr (UP) {
@@ -339,17 +391,83 @@ __device__ __forceinline__ void up_and_gelu(f32x16 (&h2n)[TA], const f32x16 (&h2
 #pragma unroll
       for (int mi = 0; mi < TA; ++mi) a[mi] = *(const bf16x8*)(arow + mi * 32 * kLdA + ks * 16);
       const bf16x8 b = as_bf16x8(ring[ks % kRing]);
-      const u32x4* src = ks + kRing < kKs ? cur + (ks + kRing) * 64 : next + (ks + kRing - kKs) * 64;
-      ring[ks % kRing] = src[lane];
+      ring[ks % kRing] = ks + kRing < kKs ? cur[(ks + kRing) * 64 + lane]
+                                          : frag_at<NCN>(next, nstride, ks + kRing - kKs)[lane];
 #pragma unroll
       for (int mi = 0; mi < TA; ++mi)
-        h2n[mi] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[mi], b, h2n[mi], 0, 0, 0);
+        h2n[mi][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[mi], b, h2n[mi][0], 0, 0, 0);
     }
 #pragma unroll
-    for (int q = 0; q < TA; ++q) {     // 16 TA values of h2 over the 16 k steps
+    for (int q = 0; q < TA; ++q) {     // 16 TA values of h2 over the 16 K steps
       const int v = TA * ks + q, mi = v >> 4, r = v & 15;
-      hb[(row0 + acc_row(mi, r, lane)) * kLdH + hcol] = (bf16)gelu_as(h2[mi][r] + bv);
+      hb[acc_row(mi, r, lane) * kLdH + hcol] = (bf16)gelu_as(h2[mi][0][r] + bv);
     }
+  }
+}
+
+struct SharedLn4 {
+  float red[2][64 * kWaves4];
+  float mu[kWaves4][64];
+  float rs[kWaves4][64];
+};
+
+// LayerNorm statistics of the 32 TM rows held as acc[TM][2] (this wave: column blocks
+// nj = 0, 1): the two columns a lane holds of a row are added first, then the
+// transpose-reduction over the 32 lanes, then the kWaves4 wave partials in wave order.
+// Means / inverse deviations land in this wave's sl.mu[w] / sl.rs[w]. Two barriers.
+template <int TM>
+__device__ __forceinline__ void row_stats_nc(const f32x16 (&acc)[TM][2], SharedLn4& sl,
+                                             float2* __restrict__ stats_out, int64_t m0,
+                                             int lane, int w) {
+#pragma clang fp contract(off)
+  static_assert(TM % 2 == 0, "row statistics take 32-value groups of two fragments");
+  constexpr int G = TM / 2;
+  float* mu = sl.mu[w];
+  float* rs = sl.rs[w];
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    float v[32];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) v[h * 16 + r] = acc[2 * g + h][0][r] + acc[2 * g + h][1][r];
+    transpose_reduce32(v, lane);
+    sl.red[0][own_row(g, lane) * kWaves4 + w] = v[0];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    const float* p = &sl.red[0][own_row(g, lane) * kWaves4];
+    float t = 0.f;
+#pragma unroll
+    for (int q = 0; q < kWaves4; ++q) t += p[q];
+    mu[own_row(g, lane)] = t * (1.0f / kD);
+  }
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    float v[32];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const float m = mu[acc_row(2 * g + h, r, lane)];
+        const float d0 = acc[2 * g + h][0][r] - m, d1 = acc[2 * g + h][1][r] - m;
+        v[h * 16 + r] = d0 * d0 + d1 * d1;
+      }
+    transpose_reduce32(v, lane);
+    sl.red[1][own_row(g, lane) * kWaves4 + w] = v[0];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    const int row = own_row(g, lane);
+    const float* p = &sl.red[1][row * kWaves4];
+    float t = 0.f;
+#pragma unroll
+    for (int q = 0; q < kWaves4; ++q) t += p[q];
+    const float r = rsqrtf(t * (1.0f / kD) + kLnEps);
+    rs[row] = r;
+    if (stats_out && w == 0) stats_out[m0 + row] = make_float2(mu[row], r);
   }
 }
 
@@ -423,82 +541,120 @@ __global__ __launch_bounds__(kThreads) void k_fused_oqc(
   store_rows_bf16<kDh>(acc, qc + (int64_t)w * plane, m0, lane & 31, lane);   // head-major
 }
 
+// MLP block on 64-row tiles with four waves: two workgroups share a CU, one wave of each per
+// SIMD, so one workgroup's barriers, LDS traffic and loads overlap the other's matrix work.
 template <int TM>
-__global__ __launch_bounds__(kThreads) void k_fused_mlp(
+__global__ __launch_bounds__(kThreads4) __attribute__((amdgpu_waves_per_eu(2))) void k_fused_mlp(
     const bf16* __restrict__ att, const u32x4* __restrict__ Wf_oc, const float* __restrict__ b_oc,
     float* __restrict__ H, const float* __restrict__ g, const float* __restrict__ s,
     const u32x4* __restrict__ Wf_up, const float* __restrict__ b_up,
     const u32x4* __restrict__ Wf_dn, const float* __restrict__ b_dn,
     float2* __restrict__ stats_out) {
-  constexpr int ROWS = 32 * TM, TA = TM / 2;   // hidden-chunk products: 2 x 4 waves
+  constexpr int ROWS = 32 * TM;
+  static_assert(ROWS == 64, "statistics scratch sized for 64 rows");
   __shared__ __attribute__((aligned(16))) bf16 A[ROWS * kLdA];
   __shared__ __attribute__((aligned(16))) bf16 Hc[2][ROWS * kLdH];
-  __shared__ SharedLn sl;
+  __shared__ SharedLn4 sl;
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int wm = w >> 2, wn = w & 3;        // of ROWS/2 x 32
   const int64_t m0 = (int64_t)blockIdx.x * ROWS;
-  const int col = w * 32 + (lane & 31);
+  const int col0 = 64 * w + (lane & 31);     // column of block nj: col0 + 32 nj
   constexpr int kChunks = 4 * kD / kBH;      // 8
-  constexpr int kUpKs = kKs;                 // 16 fragments per up-projection chunk
-  constexpr int kDnKs = kBH / 16;            // 8 fragments per down-projection chunk
-  const u32x4* woc = Wf_oc + w * kKs * 64;
-  // chunk c: up-projection fragments of column block 4c + wn, down-projection fragments
-  // c * kDnKs .. of column block w (K = 4d)
-  const u32x4* wup = Wf_up + wn * kKs * 64;          // + c * 4 * kKs * 64
-  const u32x4* wdn = Wf_dn + w * (4 * kD / 16) * 64; // + c * kDnKs * 64
+  constexpr int kDnKs = kBH / 16;            // 8 K steps per down-projection chunk
+  constexpr int kOcStride = kKs * 64;        // column-block stride, K = d
+  constexpr int kDnStride = (4 * kD / 16) * 64;   // column-block stride, K = 4d
+  const u32x4* woc = Wf_oc + 2 * w * kOcStride;
+  auto up_c = [&](int c) { return Wf_up + (4 * c + w) * kKs * 64; };
+  auto dn_c = [&](int c) { return Wf_dn + 2 * w * kDnStride + c * kDnKs * 64; };
   u32x4 ring[kRing];
-  ring_fill(ring, woc, lane);
-  tile_to_lds<ROWS>(A, att, kD, m0, tid);
-  f32x16 acc[TM];
-  load_rows(acc, H, m0, col, b_oc, lane);
+  ring_fill_nc<2>(ring, woc, kOcStride, lane);
+  tile_to_lds<ROWS, kThreads4>(A, att, kD, m0, tid);
+  f32x16 acc[TM][2];
+#pragma unroll
+  for (int nj = 0; nj < 2; ++nj) {
+    const float bv = b_oc[col0 + 32 * nj];
+    const RowIo<float, kD> io(H, m0, col0 + 32 * nj, lane);
+#pragma unroll
+    for (int mi = 0; mi < TM; ++mi)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[mi][nj][r] = *io.at(mi, r) + bv;
+  }
   __syncthreads();
-  mfma_phase<TM, false>(acc, A, kLdA, 0, kKs, ring, woc, woc, lane);
-  row_stats(acc, sl, nullptr, m0, lane, w);   // barrier: A reads done
-  ring_fill(ring, wup, lane);
-  ln_to_lds(acc, sl.mu[w], sl.rs[w], g, s, A, col, lane);
-  __syncthreads();
-  const int hcol = wn * 32 + (lane & 31);
-  auto up_c = [&](int c) { return wup + c * (kBH / 32) * kKs * 64; };
-  auto dn_c = [&](int c) { return wdn + c * kDnKs * 64; };
-  // chunk c: [up-projection of chunk c+1 | GELU of chunk c] -> barrier -> down-projection of
-  // chunk c. Weight stream order: up 0, up 1, down 0, up 2, down 1, ..., up 7, down 6, down 7.
-  f32x16 h2[2][TA];
+  mfma_phase_nc<TM, 2, kKs, 1, false>(acc, A, kLdA, 0, ring, woc, kOcStride, woc, 0, lane);
+  row_stats_nc(acc, sl, nullptr, m0, lane, w);   // barriers: A reads done
+  ring_fill_nc<1>(ring, up_c(0), 0, lane);
+  {
+    const float* mu = sl.mu[w];
+    const float* rs = sl.rs[w];
 #pragma unroll
-  for (int mi = 0; mi < TA; ++mi)
+    for (int nj = 0; nj < 2; ++nj) {
+      const int col = col0 + 32 * nj;
+      const float gv = g[col], sv = s[col];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) h2[0][mi][r] = 0.f;
-  mfma_phase<TA>(h2[0], A, kLdA, wm * 16 * TM, kUpKs, ring, up_c(0), up_c(1), lane);
-#pragma unroll 1
-  for (int c = 0; c < kChunks; c += 2) {
+      for (int mi = 0; mi < TM; ++mi)
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {     // chunk c + u; h2[u] holds its products
-      const int cc = c + u;
-      bf16* hb = Hc[u];
-      const float bv = b_up[cc * kBH + hcol];
-      if (cc + 1 < kChunks) {
-#pragma unroll
-        for (int mi = 0; mi < TA; ++mi)
-#pragma unroll
-          for (int r = 0; r < 16; ++r) h2[u ^ 1][mi][r] = 0.f;
-        up_and_gelu<true>(h2[u ^ 1], h2[u], A, wm * 16 * TM, ring, up_c(cc + 1), dn_c(cc), bv,
-                          hb, hcol, lane);
-      } else {
-        up_and_gelu<false>(h2[u ^ 1], h2[u], A, wm * 16 * TM, ring, dn_c(cc), dn_c(cc), bv, hb,
-                           hcol, lane);
-      }
-      __syncthreads();
-      const u32x4* nxt = cc + 2 < kChunks ? up_c(cc + 2) : dn_c(cc + 1 < kChunks ? cc + 1 : cc);
-      mfma_phase<TM>(acc, hb, kLdH, 0, kDnKs, ring, dn_c(cc), nxt, lane);
+        for (int r = 0; r < 16; ++r) {
+          const int row = acc_row(mi, r, lane);
+          A[row * kLdA + col] = (bf16)((acc[mi][nj][r] - mu[row]) * rs[row] * gv + sv);
+        }
     }
   }
-  const float bv = b_dn[col];
+  __syncthreads();
+  const int hcol = 32 * w + (lane & 31);
+  f32x16 h2[2][TM][1];
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int mi = 0; mi < TM; ++mi)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) h2[u][mi][0][r] = 0.f;
+  mfma_phase_nc<TM, 1, kKs, 1, true>(h2[0], A, kLdA, 0, ring, up_c(0), 0, up_c(1), 0, lane);
+  // chunk cc: [up-projection cc+1 | GELU cc] -> barrier -> down-projection cc. Weight stream
+  // order: up 0, up 1, down 0, up 2, down 1, ..., up 7, down 6, down 7.
+#pragma unroll 1
+  for (int c = 0; c < kChunks - 2; c += 2) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int cc = c + u;
+#pragma unroll
+      for (int mi = 0; mi < TM; ++mi)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) h2[u ^ 1][mi][0][r] = 0.f;
+      up_gelu_nc<true, TM, 2>(h2[u ^ 1], h2[u], A, ring, up_c(cc + 1), dn_c(cc), kDnStride,
+                              b_up[cc * kBH + hcol], Hc[u], hcol, lane);
+      __syncthreads();
+      mfma_phase_nc<TM, 2, kDnKs, 1, true>(acc, Hc[u], kLdH, 0, ring, dn_c(cc), kDnStride,
+                                           up_c(cc + 2), 0, lane);
+    }
+  }
+  // chunks 6 and 7
 #pragma unroll
   for (int mi = 0; mi < TM; ++mi)
 #pragma unroll
-    for (int r = 0; r < 16; ++r) acc[mi][r] += bv;
-  store_rows_f32(acc, H, m0, col, lane);
-  row_stats(acc, sl, stats_out, m0, lane, w);
+    for (int r = 0; r < 16; ++r) h2[1][mi][0][r] = 0.f;
+  up_gelu_nc<true, TM, 2>(h2[1], h2[0], A, ring, up_c(7), dn_c(6), kDnStride,
+                          b_up[6 * kBH + hcol], Hc[0], hcol, lane);
+  __syncthreads();
+  mfma_phase_nc<TM, 2, kDnKs, 2, true>(acc, Hc[0], kLdH, 0, ring, dn_c(6), kDnStride, dn_c(7),
+                                       kDnStride, lane);
+  up_gelu_nc<false, TM, 2>(h2[0], h2[1], A, ring, up_c(7), dn_c(7), kDnStride,
+                           b_up[7 * kBH + hcol], Hc[1], hcol, lane);
+  __syncthreads();
+  mfma_phase_nc<TM, 2, kDnKs, 2, false>(acc, Hc[1], kLdH, 0, ring, dn_c(7), kDnStride, dn_c(7),
+                                        kDnStride, lane);
+#pragma unroll
+  for (int nj = 0; nj < 2; ++nj) {
+    const float bv = b_dn[col0 + 32 * nj];
+    const RowIo<float, kD> io(H, m0, col0 + 32 * nj, lane);
+#pragma unroll
+    for (int mi = 0; mi < TM; ++mi)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        acc[mi][nj][r] += bv;
+        *io.at(mi, r) = acc[mi][nj][r];
+      }
+  }
+  row_stats_nc(acc, sl, stats_out, m0, lane, w);
 }
 
 __global__ void k_pack_frag(const float* __restrict__ W, int K, int N, u32x4* __restrict__ Wf) {
@@ -530,9 +686,6 @@ hipError_t launch_pack_frag(hipStream_t st, const float* W, int K, int N, void* 
 // 64-row tiles for the two HBM-bound kernels: half the accumulator, so two workgroups share a
 // CU and one's loads overlap the other's products
 constexpr int kTmIo = 2;
-// The MLP kernel stays on 128-row tiles: at 64 rows it needs ~180 registers (one workgroup
-// per CU either way) and reads the weights twice as often; measured 15% slower.
-constexpr int kTmMlp = 4;
 
 hipError_t launch_fused_qkv(hipStream_t st, int64_t Mp, const float* H, const float* g,
                             const float* s, const void* Wf, const float* bias, void* qkv) {
@@ -558,9 +711,9 @@ hipError_t launch_fused_mlp(hipStream_t st, int64_t Mp, const void* att, const v
                             const float* b_oc, float* H, const float* g, const float* s,
                             const void* Wf_up, const float* b_up, const void* Wf_dn,
                             const float* b_dn, float2* stats_out) {
-  if (Mp % (32 * kTmMlp)) return hipErrorInvalidValue;
+  if (Mp % 64) return hipErrorInvalidValue;
   if (Mp == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fused_mlp<kTmMlp>, dim3((unsigned)(Mp / (32 * kTmMlp))), dim3(kThreads), 0, st,
+  hipLaunchKernelGGL(k_fused_mlp<2>, dim3((unsigned)(Mp / 64)), dim3(kThreads4), 0, st,
                      (const bf16*)att, (const u32x4*)Wf_oc, b_oc, H, g, s,
                      (const u32x4*)Wf_up, b_up, (const u32x4*)Wf_dn, b_dn, stats_out);
   return hipGetLastError();
