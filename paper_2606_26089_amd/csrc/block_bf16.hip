@@ -308,16 +308,20 @@ __device__ __forceinline__ void store_rows_bf16(const f32x16 (&acc)[TM], bf16* _
 // GELU(z) = z/2 (1 + erf(z / sqrt 2)) with erf by Abramowitz & Stegun 7.1.25:
 // erf(x) = 1 - t (a1 + t (a2 + t a3)) exp(-x^2), t = 1 / (1 + p |x|), absolute error at most
 // 2.5e-5, far below the BF16 rounding of the result. Branch-free (a library erf branches on
-// |x|), with the hardware reciprocal and exp2: 13 vector instructions per value.
-__device__ __forceinline__ float gelu_as(float z) {
-  const float x = z * 0.70710678118654752f;
-  const float t = __builtin_amdgcn_rcpf(fmaf(0.47047f, fabsf(x), 1.0f));
-  const float poly = t * fmaf(t, fmaf(t, 0.7478556f, -0.0958798f), 0.3480242f);
-  // exp(-x^2) = exp2(-z^2 log2(e) / 2)
-  const float ex = __builtin_amdgcn_exp2f(z * z * -0.72134752044448170f);
-  const float erf_abs = fmaf(-poly, ex, 1.0f);
-  const float hz = 0.5f * z;
-  return fmaf(hz, copysignf(erf_abs, x), hz);
+// |x|), with the hardware reciprocal and exp2, in a scaled variable u = z / sqrt(2 ln 2) so
+// that exp(-x^2) = exp2(-u^2); with h = sqrt(ln 2 / 2), GELU = h (u + |u| erf(|x|)).
+// a = pre-activation product, bu = bias * kGeluU; 11 vector instructions per value.
+constexpr float kGeluU = 0.84932180028801904f;   // 1 / sqrt(2 ln 2)
+__device__ __forceinline__ float gelu_as(float a, float bu) {
+  constexpr float kT = 0.47047f * 0.83255461115769775f;   // p sqrt(ln 2): t from |u|
+  constexpr float h = 0.5f / kGeluU;
+  const float u = fmaf(a, kGeluU, bu);
+  const float t = __builtin_amdgcn_rcpf(fmaf(kT, fabsf(u), 1.0f));
+  const float ex = __builtin_amdgcn_exp2f(-(u * u));
+  const float p1 = fmaf(t, h * 0.7478556f, h * -0.0958798f);
+  const float p2 = fmaf(t, p1, h * 0.3480242f);
+  const float he = fmaf(-(t * ex), p2, h);          // h erf(|x|)
+  return fmaf(fabsf(u), he, u * h);
 }
 
 // ---- helpers of the 64-row MLP kernel: four waves, wave w owning output column blocks
@@ -374,8 +378,8 @@ __device__ __forceinline__ void mfma_phase_nc(f32x16 (&acc)[TM][NC], const bf16*
 
 // Up-projection of one hidden chunk for all rows (if UP: h2n += LN tile x W_up chunk, one
 // column block, 16 K steps) software-pipelined with the GELU of the previous chunk's
-// products h2 (two values per K step, + bias bv, BF16 into the hidden tile hb at column
-// hcol); the prefetch past the end reads the next phase's stream (NCN blocks).
+// products h2 (two values per K step, bias term bv = bias x kGeluU, BF16 into the hidden
+// tile hb at column hcol); the prefetch past the end reads the next phase's stream (NCN blocks).
 template <bool UP, int TA, int NCN>
 __device__ __forceinline__ void up_gelu_nc(f32x16 (&h2n)[TA][1], const f32x16 (&h2)[TA][1],
                                            const bf16* __restrict__ A, u32x4 (&ring)[kRing],
@@ -400,7 +404,7 @@ __device__ __forceinline__ void up_gelu_nc(f32x16 (&h2n)[TA][1], const f32x16 (&
 #pragma unroll
     for (int q = 0; q < TA; ++q) {     // 16 TA values of h2 over the 16 K steps
       const int v = TA * ks + q, mi = v >> 4, r = v & 15;
-      hb[acc_row(mi, r, lane) * kLdH + hcol] = (bf16)gelu_as(h2[mi][0][r] + bv);
+      hb[acc_row(mi, r, lane) * kLdH + hcol] = (bf16)gelu_as(h2[mi][0][r], bv);
     }
   }
 }
@@ -621,7 +625,7 @@ __global__ __launch_bounds__(kThreads4) __attribute__((amdgpu_waves_per_eu(2))) 
 #pragma unroll
         for (int r = 0; r < 16; ++r) h2[u ^ 1][mi][0][r] = 0.f;
       up_gelu_nc<true, TM, 2>(h2[u ^ 1], h2[u], A, ring, up_c(cc + 1), dn_c(cc), kDnStride,
-                              b_up[cc * kBH + hcol], Hc[u], hcol, lane);
+                              kGeluU * b_up[cc * kBH + hcol], Hc[u], hcol, lane);
       __syncthreads();
       mfma_phase_nc<TM, 2, kDnKs, 1, true>(acc, Hc[u], kLdH, 0, ring, dn_c(cc), kDnStride,
                                            up_c(cc + 2), 0, lane);
@@ -633,12 +637,12 @@ __global__ __launch_bounds__(kThreads4) __attribute__((amdgpu_waves_per_eu(2))) 
 #pragma unroll
     for (int r = 0; r < 16; ++r) h2[1][mi][0][r] = 0.f;
   up_gelu_nc<true, TM, 2>(h2[1], h2[0], A, ring, up_c(7), dn_c(6), kDnStride,
-                          b_up[6 * kBH + hcol], Hc[0], hcol, lane);
+                          kGeluU * b_up[6 * kBH + hcol], Hc[0], hcol, lane);
   __syncthreads();
   mfma_phase_nc<TM, 2, kDnKs, 2, true>(acc, Hc[0], kLdH, 0, ring, dn_c(6), kDnStride, dn_c(7),
                                        kDnStride, lane);
   up_gelu_nc<false, TM, 2>(h2[0], h2[1], A, ring, up_c(7), dn_c(7), kDnStride,
-                           b_up[7 * kBH + hcol], Hc[1], hcol, lane);
+                           kGeluU * b_up[7 * kBH + hcol], Hc[1], hcol, lane);
   __syncthreads();
   mfma_phase_nc<TM, 2, kDnKs, 2, false>(acc, Hc[1], kLdH, 0, ring, dn_c(7), kDnStride, dn_c(7),
                                         kDnStride, lane);
