@@ -547,13 +547,23 @@ __global__ __launch_bounds__(kThreads) void k_fused_oqc(
 
 // MLP block on 64-row tiles with four waves: two workgroups share a CU, one wave of each per
 // SIMD, so one workgroup's barriers, LDS traffic and loads overlap the other's matrix work.
-template <int TM>
+// With QKV, the kernel goes on to the next block's LN1 + [Q|K|V] projection from the final
+// rows still in registers (as k_fused_qkv does from H), writing head-major planes.
+struct NextQkv {
+  const float* g;        // LN1 gain and shift of the next block
+  const float* s;
+  const u32x4* Wf;       // its W_qkv fragments
+  const float* bias;
+  bf16* qkv;             // [3][8 heads][Mp][32]
+};
+
+template <int TM, bool QKV>
 __global__ __launch_bounds__(kThreads4) __attribute__((amdgpu_waves_per_eu(2))) void k_fused_mlp(
     const bf16* __restrict__ att, const u32x4* __restrict__ Wf_oc, const float* __restrict__ b_oc,
     float* __restrict__ H, const float* __restrict__ g, const float* __restrict__ s,
     const u32x4* __restrict__ Wf_up, const float* __restrict__ b_up,
     const u32x4* __restrict__ Wf_dn, const float* __restrict__ b_dn,
-    float2* __restrict__ stats_out) {
+    float2* __restrict__ stats_out, NextQkv nq) {
   constexpr int ROWS = 32 * TM;
   static_assert(ROWS == 64, "statistics scratch sized for 64 rows");
   __shared__ __attribute__((aligned(16))) bf16 A[ROWS * kLdA];
@@ -658,7 +668,55 @@ __global__ __launch_bounds__(kThreads4) __attribute__((amdgpu_waves_per_eu(2))) 
         *io.at(mi, r) = acc[mi][nj][r];
       }
   }
-  row_stats_nc(acc, sl, stats_out, m0, lane, w);
+  if constexpr (!QKV) {
+    row_stats_nc(acc, sl, stats_out, m0, lane, w);
+  } else {
+    // slab sl of the next block's W_qkv: column blocks 8 sl + 2w, 8 sl + 2w + 1
+    auto qkv_c = [&](int slab) { return nq.Wf + (8 * slab + 2 * w) * kOcStride; };
+    ring_fill_nc<2>(ring, qkv_c(0), kOcStride, lane);
+    row_stats_nc(acc, sl, stats_out, m0, lane, w);   // barriers: every wave is past its
+    {                                                // last read of the LN3 tile A
+      const float* mu = sl.mu[w];
+      const float* rs = sl.rs[w];
+#pragma unroll
+      for (int nj = 0; nj < 2; ++nj) {
+        const int col = col0 + 32 * nj;
+        const float gv = nq.g[col], sv = nq.s[col];
+#pragma unroll
+        for (int mi = 0; mi < TM; ++mi)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const int row = acc_row(mi, r, lane);
+            A[row * kLdA + col] = (bf16)((acc[mi][nj][r] - mu[row]) * rs[row] * gv + sv);
+          }
+      }
+    }
+    __syncthreads();
+    const int64_t plane = (int64_t)gridDim.x * ROWS * kDh;
+#pragma unroll 1
+    for (int slab = 0; slab < 3; ++slab) {
+#pragma unroll
+      for (int nj = 0; nj < 2; ++nj) {
+        const float bv = nq.bias[slab * kD + col0 + 32 * nj];
+#pragma unroll
+        for (int mi = 0; mi < TM; ++mi)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) acc[mi][nj][r] = bv;
+      }
+      mfma_phase_nc<TM, 2, kKs, 2, true>(acc, A, kLdA, 0, ring, qkv_c(slab), kOcStride,
+                                         qkv_c(slab < 2 ? slab + 1 : slab), kOcStride, lane);
+      // head-major: column block nj of this wave is head 2w + nj
+#pragma unroll
+      for (int nj = 0; nj < 2; ++nj) {
+        const RowIo<bf16, kDh> io(nq.qkv + (int64_t)(slab * (kD / kDh) + 2 * w + nj) * plane, m0,
+                                  lane & 31, lane);
+#pragma unroll
+        for (int mi = 0; mi < TM; ++mi)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) *io.at(mi, r) = (bf16)acc[mi][nj][r];
+      }
+    }
+  }
 }
 
 __global__ void k_pack_frag(const float* __restrict__ W, int K, int N, u32x4* __restrict__ Wf) {
@@ -714,12 +772,23 @@ hipError_t launch_fused_oqc(hipStream_t st, int64_t Mp, const void* att, const v
 hipError_t launch_fused_mlp(hipStream_t st, int64_t Mp, const void* att, const void* Wf_oc,
                             const float* b_oc, float* H, const float* g, const float* s,
                             const void* Wf_up, const float* b_up, const void* Wf_dn,
-                            const float* b_dn, float2* stats_out) {
+                            const float* b_dn, float2* stats_out, const float* g1n,
+                            const float* s1n, const void* Wf_qkv_n, const float* b_qkv_n,
+                            void* qkv) {
   if (Mp % 64) return hipErrorInvalidValue;
   if (Mp == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fused_mlp<2>, dim3((unsigned)(Mp / 64)), dim3(kThreads4), 0, st,
-                     (const bf16*)att, (const u32x4*)Wf_oc, b_oc, H, g, s,
-                     (const u32x4*)Wf_up, b_up, (const u32x4*)Wf_dn, b_dn, stats_out);
+  const dim3 grid((unsigned)(Mp / 64));
+  if (qkv) {
+    if (!g1n || !s1n || !Wf_qkv_n || !b_qkv_n) return hipErrorInvalidValue;
+    const NextQkv nq{g1n, s1n, (const u32x4*)Wf_qkv_n, b_qkv_n, (bf16*)qkv};
+    hipLaunchKernelGGL((k_fused_mlp<2, true>), grid, dim3(kThreads4), 0, st, (const bf16*)att,
+                       (const u32x4*)Wf_oc, b_oc, H, g, s, (const u32x4*)Wf_up, b_up,
+                       (const u32x4*)Wf_dn, b_dn, stats_out, nq);
+  } else {
+    hipLaunchKernelGGL((k_fused_mlp<2, false>), grid, dim3(kThreads4), 0, st, (const bf16*)att,
+                       (const u32x4*)Wf_oc, b_oc, H, g, s, (const u32x4*)Wf_up, b_up,
+                       (const u32x4*)Wf_dn, b_dn, stats_out, NextQkv{});
+  }
   return hipGetLastError();
 }
 

@@ -432,13 +432,15 @@ int net_forward(fmd_model* m, Call& c, const float* t_ev) {
   // cross query; bit 4: W_oc + residual + LN3 + MLP + residual); the GEMM kernels otherwise
   const int fz = std::is_same<T, bf16>::value ? m->fused : 0;
   const double dd = (double)d;
+  bool qkv_ready = false;   // the previous block's MLP kernel formed this block's [Q|K|V]
   for (int l = 0; l < L; ++l) {
     const DevBlock& B = m->blk[l];
     if (fz & FMD_FUSED_QKV) {
-      FMD_TRY(timed(m, c.st, FMD_K_GEMM_QKV, 2.0 * Td * dd * 3 * dd,
-                    Td * dd * 4 + (Td + dd) * 3 * dd * es, [&] {
-        return launch_fused_qkv(c.st, c.Tp, w.H, B.g1, B.s1, B.Fqkv, B.bqkv, w.qkv);
-      }));
+      if (!qkv_ready)
+        FMD_TRY(timed(m, c.st, FMD_K_GEMM_QKV, 2.0 * Td * dd * 3 * dd,
+                      Td * dd * 4 + (Td + dd) * 3 * dd * es, [&] {
+          return launch_fused_qkv(c.st, c.Tp, w.H, B.g1, B.s1, B.Fqkv, B.bqkv, w.qkv);
+        }));
     } else {
       if (l > 0) FMD_TRY(row_stats(m, c));
       FMD_TRY(timed(m, c.st, FMD_K_GEMM_QKV, 2.0 * Td * d * 3 * d, ln_in + (Td + d) * 3 * d * es, [&] {
@@ -485,11 +487,18 @@ int net_forward(fmd_model* m, Call& c, const float* t_ev) {
                                  (const T*)(kv + o + d * es), 2 * d * L, dh, (T*)w.att, d);
     }));
     if (fz & FMD_FUSED_MLP) {
-      FMD_TRY(timed(m, c.st, FMD_K_FUSED_MLP, 2.0 * Td * dd * dd * 9,
-                    Td * (dd * (es + 8) + 8) + 9 * dd * dd * es, [&] {
+      // chained with the next block's LN1 + QKV when that segment is fused too
+      const bool chain = (fz & FMD_FUSED_QKV) && l + 1 < L;
+      const DevBlock* N = chain ? &m->blk[l + 1] : nullptr;
+      FMD_TRY(timed(m, c.st, FMD_K_FUSED_MLP, 2.0 * Td * dd * dd * (chain ? 15 : 9),
+                    Td * (dd * (es + 8) + 8) + 9 * dd * dd * es +
+                        (chain ? Td * 3 * dd * es + 3 * dd * dd * es : 0.0), [&] {
         return launch_fused_mlp(c.st, c.Tp, w.att, B.Foc, B.boc, w.H, B.g3, B.s3, B.Fup, B.bup,
-                                B.Fdn, B.bdn, w.stats);
+                                B.Fdn, B.bdn, w.stats, chain ? N->g1 : nullptr,
+                                chain ? N->s1 : nullptr, chain ? N->Fqkv : nullptr,
+                                chain ? N->bqkv : nullptr, chain ? w.qkv : nullptr);
       }));
+      qkv_ready = chain;
     } else {
       FMD_TRY(timed(m, c.st, FMD_K_GEMM_PROJ, 2.0 * Td * d * d, (Td + d) * d * es + resid, [&] {
         return launch_gemm<T>(c.st, FMD_K_GEMM_PROJ, false, resid_epi(m), c.Tp, d, d, w.att, d,
