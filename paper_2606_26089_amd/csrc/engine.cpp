@@ -287,6 +287,25 @@ int truth_cache(fmd_model* m, Call& c) {
     return launch_truth_encode<T>(c.st, c.u, 9, 9, c.T, m->W_tin, m->b_tin, m->g_t, m->s_t, d,
                                   (T*)w.c, d);
   }));
+  if (m->kv_hm) {
+    // per block: [K | V] rows into a scratch buffer (the MLP hidden buffer, free here), then
+    // into the head-major planes the attention kernel reads with contiguous rows
+    const int dh = d / cf.n_heads;
+    const int64_t plane = w.cap_tok;
+    for (int l = 0; l < L; ++l) {
+      FMD_TRY(timed(m, c.st, FMD_K_OTHER, 2.0 * c.T * d * 2 * d, [&] {
+        return launch_gemm<T>(c.st, FMD_K_OTHER, false, EPI_STORE, c.Tp, 2 * d, d, w.c, d,
+                              (const T*)m->Wkv + (size_t)l * 2 * d * d, m->bkv + l * 2 * d,
+                              nullptr, nullptr, nullptr, w.hid, 2 * d);
+      }));
+      FMD_TRY(timed(m, c.st, FMD_K_OTHER, 0, [&] {
+        return launch_kv_headmajor(c.st, w.hid, c.T, d, dh, cf.n_heads,
+                                   (char*)w.kv + (size_t)l * 2 * cf.n_heads * plane * dh * sizeof(T),
+                                   plane, 0);
+      }));
+    }
+    return FMD_OK;
+  }
   FMD_TRY(timed(m, c.st, FMD_K_OTHER, 2.0 * c.T * d * 2 * d * L, [&] {
     return launch_gemm<T>(c.st, FMD_K_OTHER, false, EPI_STORE, c.Tp, 2 * d * L, d, w.c, d,
                           (const T*)m->Wkv, m->bkv, nullptr, nullptr, nullptr, w.kv, 2 * d * L);
@@ -482,6 +501,13 @@ int net_forward(fmd_model* m, Call& c, const float* t_ev) {
       const size_t o = (size_t)l * 2 * d * es;
       // the cross query is head-major [heads][Tp][dh] when the fused kernel formed it
       const bool hm = (fz & FMD_FUSED_OQC) != 0;
+      if (m->kv_hm) {   // cache planes [L][K, V][heads][cap rows][dh]
+        const int64_t pl = w.cap_tok * dh;
+        const char* kb = kv + (size_t)l * 2 * Hh * pl * es;
+        return launch_attention<T>(c.st, true, dh, Hh, c.items, c.bins, w.work, (const T*)w.qc,
+                                   hm ? dh : d, hm ? c.Tp * dh : dh, (const T*)kb,
+                                   (const T*)(kb + Hh * pl * es), dh, pl, (T*)w.att, d);
+      }
       return launch_attention<T>(c.st, true, dh, Hh, c.items, c.bins, w.work, (const T*)w.qc,
                                  hm ? dh : d, hm ? c.Tp * dh : dh, (const T*)(kv + o),
                                  (const T*)(kv + o + d * es), 2 * d * L, dh, (T*)w.att, d);
@@ -772,6 +798,7 @@ int fmd_model_create(const fmd_model_config* cfg, const float* params, size_t n_
   if (grow(m->Wout_pk, (size_t)64 * d * 4) != FMD_OK) return bail(FMD_E_NOMEM);
   if (grow(m->bout_pk, (size_t)64 * 4) != FMD_OK) return bail(FMD_E_NOMEM);
   m->fused_ok = cfg->precision == FMD_BF16 && fused_supported(cfg->d_model, cfg->mlp_ratio);
+  m->kv_hm = cfg->precision == FMD_BF16 && cfg->d_model == 32 * cfg->n_heads;
   m->fused = m->fused_ok ? FMD_FUSED_ALL : 0;
   if (m->fused_ok && grow(m->frag, (size_t)(L * blk_elems) * 2) != FMD_OK) return bail(FMD_E_NOMEM);
   m->blk.assign(L, DevBlock{});

@@ -86,6 +86,7 @@ struct fmd_model {
   void* packed = nullptr;          // packed matrices in the compute type
   void* frag = nullptr;            // fragment-layout BF16 matrices of the fused kernels
   bool fused_ok = false;           // the fused block kernels exist for this configuration
+  bool kv_hm = false;              // cross K/V cache head-major [L][2][heads][cap][dh]
   int fused = 0;                   // segments that use them (FMD_FUSED_* bits)
   float* bkv = nullptr;            // [L * 2d] cross K/V biases
   float* Wout_pk = nullptr;        // [64][d] output head, transposed, rows >= f_reco zero (FP32)

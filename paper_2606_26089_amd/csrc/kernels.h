@@ -151,6 +151,10 @@ hipError_t launch_embed(hipStream_t st, const float* xs, int ldx, int f, int64_t
 // taken from desc[*ctr].
 // Output head for d_model 256 and 9 features: ode-update(LN(H; stats, g, s) Wt^T + b) over
 // the ode.m_valid valid rows, Wt float [>= 9, 256] (row c: weights of output c).
+// One block's BF16 cross K/V rows [rows][2d] into the head-major cache planes (plane rows
+// each; this block's first plane at dst): rows land at [row0, row0 + rows).
+hipError_t launch_kv_headmajor(hipStream_t st, const void* src, int64_t rows, int d, int dh,
+                               int n_heads, void* dst, int64_t plane, int64_t row0);
 bool head256_supported(int d, int nf);
 hipError_t launch_head256(hipStream_t st, const float* H, const float2* stats, const float* g,
                           const float* s, const float* Wt, const float* b, const OdeArgs& ode);

@@ -617,4 +617,30 @@ hipError_t launch_head256(hipStream_t st, const float* H, const float2* stats, c
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------------------
+// One block's cross K/V rows [rows][2d] (K | V, row-major, pitch 2d) into head-major planes:
+// element (row, s, head, i) -> dst[((s * n_heads + head) * plane + row0 + row) * dh + i],
+// s = 0 for K, 1 for V. 16-byte copies.
+__global__ void k_kv_headmajor(const bf16* __restrict__ src, int64_t rows, int d, int dh,
+                               int n_heads, bf16* __restrict__ dst, int64_t plane, int64_t row0) {
+  const int per_row = 2 * d / 8;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= rows * per_row) return;
+  const int64_t row = t / per_row;
+  const int col = (int)(t % per_row) * 8;
+  const int sel = col / d, head = (col % d) / dh, i = col % dh;
+  *(u32x4*)(dst + ((int64_t)(sel * n_heads + head) * plane + row0 + row) * dh + i) =
+      *(const u32x4*)(src + row * 2 * d + col);
+}
+
+hipError_t launch_kv_headmajor(hipStream_t st, const void* src, int64_t rows, int d, int dh,
+                               int n_heads, void* dst, int64_t plane, int64_t row0) {
+  if (rows <= 0) return hipSuccess;
+  if (dh % 8 || d % dh || row0 + rows > plane) return hipErrorInvalidValue;
+  const int64_t n = rows * (2 * d / 8);
+  hipLaunchKernelGGL(k_kv_headmajor, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+                     (const bf16*)src, rows, d, dh, n_heads, (bf16*)dst, plane, row0);
+  return hipGetLastError();
+}
+
 }  // namespace fmd

@@ -159,6 +159,18 @@ int admit_device(fmd_server* S, Req* r) {
                                  d, cb, d));
   // K/V cache of the request's rows; padded rows past its end recompute identical values
   // for neighbours (a pure function of their own truth encoding) or fill unused rows.
+  if (m->kv_hm) {   // per block into scratch rows, then the request's rows of the planes
+    const int H = m->cfg.n_heads, dh = d / H;
+    for (int l = 0; l < L; ++l) {
+      HIP_TRY(launch_gemm<T>(S->st, FMD_K_OTHER, false, EPI_STORE, round_up(nT, kGemmBM), 2 * d,
+                             d, cb, d, (const T*)m->Wkv + (size_t)l * 2 * d * d,
+                             m->bkv + l * 2 * d, nullptr, nullptr, nullptr, w.hid, 2 * d));
+      HIP_TRY(launch_kv_headmajor(S->st, w.hid, nT, d, dh, H,
+                                  (char*)w.kv + (size_t)l * 2 * H * w.cap_tok * dh * es,
+                                  w.cap_tok, b));
+    }
+    return FMD_OK;
+  }
   HIP_TRY(launch_gemm<T>(S->st, FMD_K_OTHER, false, EPI_STORE, round_up(nT, kGemmBM), 2 * d * L, d,
                          cb, d, (const T*)m->Wkv, m->bkv, nullptr, nullptr, nullptr,
                          (char*)w.kv + (size_t)b * 2 * d * L * es, 2 * d * L));

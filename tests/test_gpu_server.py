@@ -56,6 +56,27 @@ def test_mix_equals_alone_bitwise(env, precision):
     m.close()
 
 
+@pytest.mark.parametrize("cfg", [configs.ModelCfg(d_model=64, n_blocks=2, n_heads=2, n_max=64),
+                                 configs.BASE_MODEL],
+                         ids=["d64-heads32", "base-fused"])
+def test_mix_equals_alone_bitwise_heads_of_32(env, cfg):
+    # BF16 with heads of 32 keeps the cross K/V cache head-major: the server writes each
+    # admitted request's rows into the planes at its pool offset
+    torch, fmd = env
+    cfg = cfg.with_precision(configs.BF16)
+    flat = params.draw(cfg, 9, perturbed=True)
+    reqs = _requests(6, seed=3)
+    m = fmd.Model(cfg, flat)
+    alone = [m.simulate(off, feat, seed, sched) for off, feat, seed, sched in reqs]
+    srv = fmd.Server(m, hbm_budget_bytes=512 << 20)
+    ids = [srv.submit(off, feat, seed, sched) for off, feat, seed, sched in reqs]
+    for rid, ref in zip(ids, alone):
+        out, _ = srv.wait(rid)
+        assert np.array_equal(out, ref)
+    srv.close()
+    m.close()
+
+
 def test_staggered_arrivals_overlap_and_match(env):
     torch, fmd = env
     flat = params.draw(CFG, 3)
