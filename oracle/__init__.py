@@ -18,6 +18,7 @@ Modules:
   net        unpacking of the flat parameters; LayerNorm, GELU, Linear, attention;
              truth encoder; time embedding; the velocity field
   ode        explicit Euler and classic RK4 on a uniform grid
+  observables  H_T, MET and lepton isolation of reconstructed events (Sec. 2.4)
   sample     per-event sampling driver and output decoding
 
 Pins (tests marked "not gpu"): Philox against the generator of NumPy and the published
