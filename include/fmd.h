@@ -153,6 +153,24 @@ int fmd_velocity(fmd_model* m, const fmd_events_in* truth, const float* x,
 int fmd_noise(uint64_t seed, const int64_t* offsets, int64_t n_events, int32_t n_feat,
               float* x0_device, void* hip_stream);
 
+/* Event observables of reconstructed events (Sec. 2.4, event post-processing, and its
+ * isolation equation): per event the scalar sum H_T of the particles' pT and MET, the
+ * magnitude of their vector pT sum; per particle the isolation of an electron or muon,
+ * R_iso = (sum of the pT of the event's other particles with Delta R = sqrt(Delta eta^2 +
+ * Delta phi^2) < 0.4) / its own pT, and NaN for the other classes.
+ * reco: n_events, offsets (HOST array [n_events + 1], offsets[0] = 0, nondecreasing) and feat
+ * [offsets[n_events], 9] FP32 in the particle state layout of fmd_simulate's output; the
+ * kinematics are pT = 10 GeV exp(x0), eta = x1, phi = x2 and the class is the first
+ * maximum of x3..x7 (charged hadron, electron, muon, neutral hadron, photon).
+ * ht, met [n_events] and iso [offsets[n_events]] FP32 are written in the memory reco->feat
+ * lives in (reco->on_device). Delta phi is wrapped by multiples of 2 pi; the cone test and
+ * the class maximum are taken in FP32, pT and all sums in FP64. The final-state-radiation
+ * photon exclusion is not applied (the paper does not define it). The call returns after
+ * the results are complete. Errors: FMD_E_INVALID (bad offsets, null pointers),
+ * FMD_E_NOMEM, FMD_E_DEVICE. */
+int fmd_event_observables(const fmd_events_in* reco, float* ht, float* met, float* iso,
+                          void* hip_stream);
+
 /* Ragged packing. `padded` is [n_events, n_max, f] FP32 (device), lengths is int32
  * [n_events] (device); lengths are clamped to [0, n_max]. The call writes offsets_out
  * int64[n_events + 1] (device, exclusive prefix sum of the lengths) and feat_out

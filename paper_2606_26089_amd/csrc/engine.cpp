@@ -12,6 +12,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1010,6 +1011,60 @@ int fmd_noise(uint64_t seed, const int64_t* offsets, int64_t n_events, int32_t n
   (void)hipFree(off);
   (void)hipFree(tok);
   return status;
+}
+
+int fmd_event_observables(const fmd_events_in* reco, float* ht, float* met, float* iso,
+                          void* hip_stream) {
+  if (!reco || !reco->offsets || reco->n_events < 0) return fail(FMD_E_INVALID, "bad events");
+  const int64_t E = reco->n_events;
+  fmd_events_in ev = *reco;
+  int64_t T = 0;
+  FMD_TRY(check_events(nullptr, &ev, &T, nullptr));
+  if (E == 0) return FMD_OK;
+  if (!ht || !met || (T > 0 && (!iso || !reco->feat))) return fail(FMD_E_INVALID, "null output");
+  hipStream_t st = (hipStream_t)hip_stream;
+  // device offsets (and, for host data, device copies) in a grow-only buffer kept between
+  // calls; the lock covers the whole call, which ends with the stream synchronized
+  static std::mutex mu;
+  static void* buf = nullptr;
+  static size_t cap = 0;
+  std::lock_guard<std::mutex> lock(mu);
+  const bool dev = reco->on_device != 0;
+  const size_t b_off = (size_t)(E + 1) * 8, b_feat = dev ? 0 : (size_t)T * 9 * 4,
+               b_out = dev ? 0 : (size_t)(2 * E + T) * 4;
+  const size_t need = ((b_off + 255) & ~(size_t)255) + ((b_feat + 255) & ~(size_t)255) + b_out;
+  if (need > cap) {
+    if (buf) (void)hipFree(buf);
+    buf = nullptr;
+    cap = 0;
+    if (hipMalloc(&buf, need) != hipSuccess) return fail(FMD_E_NOMEM, "allocation failed");
+    cap = need;
+  }
+  char* p = (char*)buf;
+  int64_t* d_off = (int64_t*)p;
+  p += (b_off + 255) & ~(size_t)255;
+  const float* d_feat = reco->feat;
+  float *d_ht = ht, *d_met = met, *d_iso = iso;
+  if (!dev) {
+    d_feat = (const float*)p;
+    p += (b_feat + 255) & ~(size_t)255;
+    d_ht = (float*)p;
+    d_met = d_ht + E;
+    d_iso = d_met + E;
+  }
+  hipError_t e = hipMemcpyAsync(d_off, reco->offsets, b_off, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess && !dev && T > 0)
+    e = hipMemcpyAsync((void*)d_feat, reco->feat, b_feat, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = launch_event_observables(st, d_feat, 9, d_off, E, d_ht, d_met, d_iso);
+  if (e == hipSuccess && !dev) {
+    e = hipMemcpyAsync(ht, d_ht, (size_t)E * 4, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(met, d_met, (size_t)E * 4, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess && T > 0)
+      e = hipMemcpyAsync(iso, d_iso, (size_t)T * 4, hipMemcpyDeviceToHost, st);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return fail(FMD_E_DEVICE, "event observables: %s", hipGetErrorString(e));
+  return FMD_OK;
 }
 
 int fmd_debug_philox(uint64_t key0, uint64_t key1, const uint64_t* counters, int64_t n,

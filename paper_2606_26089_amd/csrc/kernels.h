@@ -155,6 +155,11 @@ hipError_t launch_embed(hipStream_t st, const float* xs, int ldx, int f, int64_t
 // each; this block's first plane at dst): rows land at [row0, row0 + rows).
 hipError_t launch_kv_headmajor(hipStream_t st, const void* src, int64_t rows, int d, int dh,
                                int n_heads, void* dst, int64_t plane, int64_t row0);
+// Event observables (H_T, MET per event; lepton isolation per particle, NaN otherwise) of
+// reconstructed particles feat [rows, ldf] FP32 with device CSR offsets.
+hipError_t launch_event_observables(hipStream_t st, const float* feat, int ldf,
+                                    const int64_t* off_device, int64_t n_events, float* ht,
+                                    float* met, float* iso);
 bool head256_supported(int d, int nf);
 hipError_t launch_head256(hipStream_t st, const float* H, const float2* stats, const float* g,
                           const float* s, const float* Wt, const float* b, const OdeArgs& ode);

@@ -643,4 +643,117 @@ hipError_t launch_kv_headmajor(hipStream_t st, const void* src, int64_t rows, in
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------------------
+// Event observables of reconstructed events (Sec. 2.4, event post-processing): H_T and MET
+// per event, and the isolation of every electron and muon: the pT sum of the event's other
+// particles inside Delta R < 0.4, over the lepton's pT. One workgroup per event. pT, the
+// trigonometric terms and every sum are FP64; the class maximum and the cone test are taken
+// in FP32 with separate multiplies and adds (integer decisions in the input's precision).
+// The event's particles stream through LDS in tiles of kObsTile; each thread takes
+// particles i = tid, tid + 256, ... and sums its cone members in order of j.
+namespace {
+constexpr int kObsTile = 1024;
+constexpr float kObsTwoPi = (float)(2.0 * 3.14159265358979323846);
+constexpr float kObsInvTwoPi = (float)(1.0 / (2.0 * 3.14159265358979323846));
+
+__device__ __forceinline__ int obs_class(const float* f) {
+  int c = 0;
+  float best = f[3];
+#pragma unroll
+  for (int k = 1; k < 5; ++k)
+    if (f[3 + k] > best) best = f[3 + k], c = k;    // first maximum
+  return c;
+}
+
+__device__ __forceinline__ bool obs_in_cone(float eta_i, float phi_i, float eta_j, float phi_j) {
+#pragma clang fp contract(off)
+  const float deta = eta_i - eta_j;
+  const float d = phi_i - phi_j;
+  const float dphi = d - kObsTwoPi * rintf(d * kObsInvTwoPi);
+  return deta * deta + dphi * dphi < 0.16f;
+}
+
+__device__ __forceinline__ double obs_block_sum(double v, double* red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) t += red[q];       // the same order in every thread
+  return t;
+}
+}  // namespace
+
+__global__ __launch_bounds__(256) void k_event_observables(const float* __restrict__ feat,
+                                                           int ldf,
+                                                           const int64_t* __restrict__ off,
+                                                           float* __restrict__ ht,
+                                                           float* __restrict__ met,
+                                                           float* __restrict__ iso) {
+  __shared__ double s_pt[kObsTile];
+  __shared__ float s_eta[kObsTile], s_phi[kObsTile];
+  __shared__ double red[4];
+  const int e = blockIdx.x, tid = threadIdx.x;
+  const int64_t a = off[e], n = off[e + 1] - a;
+  double h = 0.0, px = 0.0, py = 0.0;
+  for (int64_t i = tid; i < n; i += 256) {
+    const float* f = feat + (a + i) * ldf;
+    const double pt = 10.0 * exp((double)f[0]);
+    const double phi = (double)f[2];
+    h += pt;
+    px += pt * cos(phi);
+    py += pt * sin(phi);
+  }
+  h = obs_block_sum(h, red);
+  px = obs_block_sum(px, red);
+  py = obs_block_sum(py, red);
+  if (tid == 0) {
+    ht[e] = (float)h;
+    met[e] = (float)sqrt(px * px + py * py);
+  }
+  for (int64_t i0 = 0; i0 < n; i0 += 256) {
+    const int64_t i = i0 + tid;
+    bool lep = false;
+    double pt_i = 0.0;
+    float eta_i = 0.f, phi_i = 0.f;
+    if (i < n) {
+      const float* f = feat + (a + i) * ldf;
+      const int c = obs_class(f);
+      lep = c == 1 || c == 2;                      // electron, muon
+      pt_i = 10.0 * exp((double)f[0]);
+      eta_i = f[1];
+      phi_i = f[2];
+    }
+    double sum = 0.0;
+    for (int64_t j0 = 0; j0 < n; j0 += kObsTile) {
+      const int nt = (int)min<int64_t>(kObsTile, n - j0);
+      __syncthreads();
+      for (int j = tid; j < nt; j += 256) {
+        const float* f = feat + (a + j0 + j) * ldf;
+        s_pt[j] = 10.0 * exp((double)f[0]);
+        s_eta[j] = f[1];
+        s_phi[j] = f[2];
+      }
+      __syncthreads();
+      if (lep)
+        for (int j = 0; j < nt; ++j)
+          if (j0 + j != i && obs_in_cone(eta_i, phi_i, s_eta[j], s_phi[j])) sum += s_pt[j];
+    }
+    if (i < n) iso[a + i] = lep ? (float)(sum / pt_i) : __builtin_nanf("");
+  }
+}
+
+hipError_t launch_event_observables(hipStream_t st, const float* feat, int ldf,
+                                    const int64_t* off_device, int64_t n_events, float* ht,
+                                    float* met, float* iso) {
+  if (n_events <= 0) return hipSuccess;
+  if (n_events > 0x7fffffff || ldf < 8) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_event_observables, dim3((unsigned)n_events), dim3(256), 0, st, feat, ldf,
+                     off_device, ht, met, iso);
+  return hipGetLastError();
+}
+
 }  // namespace fmd

@@ -97,6 +97,8 @@ def lib():
         "fmd_velocity": (c_int32, [c_void_p, ctypes.POINTER(EventsIn), c_void_p, c_void_p,
                                    c_void_p, c_void_p]),
         "fmd_noise": (c_int32, [ctypes.c_uint64, P_int64, c_int64, c_int32, c_void_p, c_void_p]),
+        "fmd_event_observables": (c_int32, [ctypes.POINTER(EventsIn), c_void_p, c_void_p, c_void_p,
+                                            c_void_p]),
         "fmd_debug_philox": (c_int32, [ctypes.c_uint64, ctypes.c_uint64, c_void_p, c_int64,
                                        c_void_p, c_void_p]),
         "fmd_pack_padded": (c_int32, [c_void_p, c_void_p, c_int64, c_int32, c_int32, c_void_p,
@@ -373,6 +375,25 @@ def noise(seed, offsets, n_feat, out, stream=None):
         raise ValueError("noise writes device memory: pass a device tensor")
     _check(lib().fmd_noise(ctypes.c_uint64(seed), p, len(off) - 1, int(n_feat), op, _stream(stream)))
     return out
+
+
+def event_observables(offsets, feat, stream=None):
+    """(ht [E], met [E], iso [T]) of reconstructed events feat [T, 9] (Sec. 2.4): H_T, MET and
+    lepton isolation (NaN for other classes). Outputs live where feat lives (NumPy on the
+    host, torch tensors on its device)."""
+    ev, off = _events(offsets, feat)
+    E, T = len(off) - 1, int(off[-1])
+    if _is_torch(feat):
+        import torch
+        ht = torch.empty(E, dtype=torch.float32, device=feat.device)
+        met = torch.empty(E, dtype=torch.float32, device=feat.device)
+        iso = torch.empty(T, dtype=torch.float32, device=feat.device)
+        ptrs = [c_void_p(t.data_ptr()) for t in (ht, met, iso)]
+    else:
+        ht, met, iso = np.empty(E, np.float32), np.empty(E, np.float32), np.empty(T, np.float32)
+        ptrs = [c_void_p(a.ctypes.data) for a in (ht, met, iso)]
+    _check(lib().fmd_event_observables(ctypes.byref(ev), *ptrs, _stream(stream)))
+    return ht, met, iso
 
 
 def pack_padded(padded, lengths, offsets_out, feat_out, stream=None):

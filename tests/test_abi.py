@@ -113,6 +113,14 @@ def test_null_model_and_errors_are_reported(fmd):
     assert st == fmd.E_INVALID
     assert b"null model" in L.fmd_last_error()
     assert L.fmd_noise(0, None, 1, 9, None, None) == fmd.E_INVALID
+    assert L.fmd_event_observables(None, None, None, None, None) == fmd.E_INVALID
+    bad = np.array([0, 3, 1], dtype=np.int64)
+    ev2 = fmd.EventsIn(2, bad.ctypes.data_as(fmd.P_int64), None, 0)
+    assert L.fmd_event_observables(ctypes.byref(ev2), None, None, None, None) == fmd.E_INVALID
+    assert b"offsets decrease" in L.fmd_last_error()
+    zero = np.zeros(1, dtype=np.int64)
+    ev0 = fmd.EventsIn(0, zero.ctypes.data_as(fmd.P_int64), None, 0)
+    assert L.fmd_event_observables(ctypes.byref(ev0), None, None, None, None) == fmd.OK
     assert L.fmd_pack_padded(None, None, 1, 4, 9, None, None, None) == fmd.E_INVALID
     assert L.fmd_debug_gemm(0, 4, 60, 32, None, None, None, 0, None, None, 0, None, -1, None) == fmd.E_INVALID
     assert L.fmd_model_destroy(None) == fmd.OK
