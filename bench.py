@@ -81,6 +81,30 @@ def time_path(fmd, torch, cfg, flat, off, feat_d, w, steps, warmup, timing):
     return dt, out.cpu().numpy(), kern
 
 
+def observables_leg(fmd, torch, off, reco, reps):
+    """Event observables (Sec. 2.4: H_T, MET, lepton isolation in a Delta R < 0.4 cone) of the
+    BF16 sampler's output, resident on the device: wall time per call over `reps` calls
+    (each uploads the offsets and ends synchronized), and the cone tests per second counted
+    algorithmically (one per lepton and other particle of its event)."""
+    reco_d = torch.from_numpy(reco).cuda()
+    fmd.event_observables(off, reco_d)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fmd.event_observables(off, reco_d)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    cls = np.argmax(reco[:, 3:8], axis=1)
+    lep = (cls == 1) | (cls == 2)
+    n = np.diff(off)
+    E = len(off) - 1
+    n_lep = np.bincount(np.repeat(np.arange(E), n)[lep], minlength=E)
+    tests = float((n_lep * np.maximum(n - 1, 0)).sum())
+    return {"kernel": "k_event_observables", "ms_per_call": round(dt * 1e3, 4),
+            "events_per_s": round(E / dt, 1), "cone_tests_per_s": round(tests / dt, 1),
+            "cone_tests_per_call": tests, "calls": reps}
+
+
 def bound_of(k, dtype):
     """The resource that bounds a kernel class at its algorithmic FLOPs and bytes: the one
     whose peak takes longer to serve them."""
@@ -240,6 +264,10 @@ def main():
     log(f"dominant kernel {rl['kernel']}: {rl['achieved']} {rl['unit']} ({rl['frac']:.3f} of peak), "
         f"HBM traffic {rl['traffic']} bytes/launch (algorithmic {rl['bytes_per_launch']:.0f})")
 
+    obs = observables_leg(fmd, torch, off, out16, 20)
+    log(f"event observables: {obs['ms_per_call']:.3f} ms per call, {obs['events_per_s']:.0f} "
+        f"events/s, {obs['cone_tests_per_s'] / 1e9:.2f} G cone tests/s")
+
     fp32 = None
     out32 = None
     if not a.no_fp32:
@@ -285,7 +313,7 @@ def main():
                    "precision": "bf16 operands, fp32 accumulation and state",
                    "tiles": kern16["_tiles"]},
         "fp32": fp32, "error": err,
-        "latency": serve,
+        "latency": serve, "observables": obs,
         "roofline": rl, "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
