@@ -20,6 +20,7 @@ Modules:
   ode        explicit Euler and classic RK4 on a uniform grid
   observables  H_T, MET and lepton isolation of reconstructed events (Sec. 2.4)
   sample     per-event sampling driver and output decoding
+  select     truth preprocessing: model pT cut and particle limit
 
 Pins (tests marked "not gpu"): Philox against the generator of NumPy and the published
 known-answer vector; Box-Muller moments; LayerNorm, GELU and softmax textbook
