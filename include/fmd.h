@@ -171,6 +171,22 @@ int fmd_noise(uint64_t seed, const int64_t* offsets, int64_t n_events, int32_t n
 int fmd_event_observables(const fmd_events_in* reco, float* ht, float* met, float* iso,
                           void* hip_stream);
 
+/* Truth preprocessing before sampling: the model's selection of truth particles (the neural
+ * backend's pT cut and particle limit come with the released model: 0.25 GeV and 400
+ * particles for the CMS model, 0.5 GeV and 128 for the ALEPH one; Sec. 2.2 and the
+ * configuration reference appendix). A particle survives when pT > pt_cut_gev, decided as
+ * x0 > (float)ln(pt_cut_gev / 10) on the state value x0 = ln(pT / 10 GeV); an event with
+ * more than max_particles survivors keeps the max_particles of largest x0 (equal x0: the
+ * earlier one). Kept particles stay in input order; the event count is unchanged (events may
+ * become empty).
+ * truth: offsets on the HOST, feat [offsets[n], 9] FP32 in device or host memory
+ * (on_device). offsets_out: HOST int64 [n_events + 1], written. feat_out: same memory kind
+ * as truth->feat, capacity offsets[n_events] rows; rows [0, offsets_out[n_events]) written.
+ * Returns after the results are complete. Errors: FMD_E_INVALID (bad offsets, null
+ * pointers, pt_cut_gev <= 0, max_particles < 0), FMD_E_NOMEM, FMD_E_DEVICE. */
+int fmd_truth_select(const fmd_events_in* truth, double pt_cut_gev, int32_t max_particles,
+                     int64_t* offsets_out, float* feat_out, void* hip_stream);
+
 /* Ragged packing. `padded` is [n_events, n_max, f] FP32 (device), lengths is int32
  * [n_events] (device); lengths are clamped to [0, n_max]. The call writes offsets_out
  * int64[n_events + 1] (device, exclusive prefix sum of the lengths) and feat_out

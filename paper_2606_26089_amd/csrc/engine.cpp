@@ -1067,6 +1067,65 @@ int fmd_event_observables(const fmd_events_in* reco, float* ht, float* met, floa
   return FMD_OK;
 }
 
+int fmd_truth_select(const fmd_events_in* truth, double pt_cut_gev, int32_t max_particles,
+                     int64_t* offsets_out, float* feat_out, void* hip_stream) {
+  if (!truth || !offsets_out) return fail(FMD_E_INVALID, "null argument");
+  if (!(pt_cut_gev > 0.0) || max_particles < 0) return fail(FMD_E_INVALID, "bad cut or limit");
+  fmd_events_in ev = *truth;
+  int64_t T = 0;
+  FMD_TRY(check_events(nullptr, &ev, &T, nullptr));
+  const int64_t E = truth->n_events;
+  offsets_out[0] = 0;
+  if (E == 0) return FMD_OK;
+  if (T > 0 && !feat_out) return fail(FMD_E_INVALID, "null output");
+  hipStream_t st = (hipStream_t)hip_stream;
+  static std::mutex mu;
+  static void* buf = nullptr;
+  static size_t cap = 0;
+  std::lock_guard<std::mutex> lock(mu);
+  const bool dev = truth->on_device != 0;
+  auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const size_t b_off = al((size_t)(E + 1) * 8), b_cnt = al((size_t)E * 4), b_keep = al((size_t)T),
+               b_feat = dev ? 0 : al((size_t)T * 9 * 4);
+  const size_t need = 2 * b_off + b_cnt + b_keep + 2 * b_feat;
+  if (need > cap) {
+    if (buf) (void)hipFree(buf);
+    buf = nullptr;
+    cap = 0;
+    if (hipMalloc(&buf, need) != hipSuccess) return fail(FMD_E_NOMEM, "allocation failed");
+    cap = need;
+  }
+  char* p = (char*)buf;
+  int64_t* d_off = (int64_t*)p;
+  int64_t* d_off2 = (int64_t*)(p + b_off);
+  int32_t* d_cnt = (int32_t*)(p + 2 * b_off);
+  uint8_t* d_keep = (uint8_t*)(p + 2 * b_off + b_cnt);
+  const float* d_in = truth->feat;
+  float* d_out = feat_out;
+  if (!dev) {
+    d_in = (const float*)(p + 2 * b_off + b_cnt + b_keep);
+    d_out = (float*)(p + 2 * b_off + b_cnt + b_keep + b_feat);
+  }
+  const float c0 = (float)std::log(pt_cut_gev / 10.0);
+  std::vector<int32_t> cnt((size_t)E);
+  hipError_t e = hipMemcpyAsync(d_off, truth->offsets, (size_t)(E + 1) * 8, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess && !dev && T > 0)
+    e = hipMemcpyAsync((void*)d_in, truth->feat, (size_t)T * 9 * 4, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = launch_select_count(st, d_in, 9, d_off, E, c0, max_particles, d_keep, d_cnt);
+  if (e == hipSuccess) e = hipMemcpyAsync(cnt.data(), d_cnt, (size_t)E * 4, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e == hipSuccess) {
+    for (int64_t i = 0; i < E; ++i) offsets_out[i + 1] = offsets_out[i] + cnt[(size_t)i];
+    e = hipMemcpyAsync(d_off2, offsets_out, (size_t)(E + 1) * 8, hipMemcpyHostToDevice, st);
+  }
+  if (e == hipSuccess) e = launch_select_write(st, d_in, 9, d_off, d_off2, E, d_keep, d_out);
+  if (e == hipSuccess && !dev && offsets_out[E] > 0)
+    e = hipMemcpyAsync(feat_out, d_out, (size_t)offsets_out[E] * 9 * 4, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return fail(FMD_E_DEVICE, "truth selection: %s", hipGetErrorString(e));
+  return FMD_OK;
+}
+
 int fmd_debug_philox(uint64_t key0, uint64_t key1, const uint64_t* counters, int64_t n,
                      uint64_t* out, void* hip_stream) {
   if (n < 0 || (n > 0 && (!counters || !out))) return fail(FMD_E_INVALID, "bad arguments");

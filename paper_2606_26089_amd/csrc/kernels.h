@@ -160,6 +160,14 @@ hipError_t launch_kv_headmajor(hipStream_t st, const void* src, int64_t rows, in
 hipError_t launch_event_observables(hipStream_t st, const float* feat, int ldf,
                                     const int64_t* off_device, int64_t n_events, float* ht,
                                     float* met, float* iso);
+// Truth preprocessing: per-event keep flags and counts (pass 1), then the kept rows in input
+// order at off_out (pass 2); see fmd_truth_select.
+hipError_t launch_select_count(hipStream_t st, const float* feat, int ldf, const int64_t* off,
+                               int64_t n_events, float c0, int limit, uint8_t* keep,
+                               int32_t* cnt);
+hipError_t launch_select_write(hipStream_t st, const float* feat, int ldf, const int64_t* off,
+                               const int64_t* off_out, int64_t n_events, const uint8_t* keep,
+                               float* out);
 bool head256_supported(int d, int nf);
 hipError_t launch_head256(hipStream_t st, const float* H, const float2* stats, const float* g,
                           const float* s, const float* Wt, const float* b, const OdeArgs& ode);

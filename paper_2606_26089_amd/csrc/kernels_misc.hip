@@ -756,4 +756,104 @@ hipError_t launch_event_observables(hipStream_t st, const float* feat, int ldf,
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------------------
+// Truth preprocessing before the sampler: the model's pT cut and particle limit (stream
+// compaction per event). Pass 1, one workgroup per event: a particle survives when
+// x0 > c0 (x0 = ln(pT / 10 GeV), c0 = ln(cut / 10 GeV) in float32); if more than `limit`
+// survive, a survivor is kept when fewer than `limit` survivors rank before it (larger x0,
+// or equal x0 and an earlier position). Writes keep[row] and the event's count. Pass 2
+// writes the kept rows in input order at the event's output offset (a block-wide prefix
+// sum of the keep flags).
+namespace {
+constexpr int kSelTile = 1024;
+}  // namespace
+
+__global__ __launch_bounds__(256) void k_select_count(const float* __restrict__ feat, int ldf,
+                                                      const int64_t* __restrict__ off, float c0,
+                                                      int limit, uint8_t* __restrict__ keep,
+                                                      int32_t* __restrict__ cnt) {
+  __shared__ float s_x[kSelTile];
+  __shared__ int s_n;
+  const int e = blockIdx.x, tid = threadIdx.x;
+  const int64_t a = off[e], n = off[e + 1] - a;
+  if (tid == 0) s_n = 0;
+  __syncthreads();
+  int mine = 0;
+  for (int64_t i = tid; i < n; i += 256) mine += feat[(a + i) * ldf] > c0;
+  atomicAdd(&s_n, mine);                 // LDS atomic: an integer count, order-free
+  __syncthreads();
+  const int surv = s_n;
+  const bool all = surv <= limit;
+  for (int64_t i0 = 0; i0 < n; i0 += 256) {
+    const int64_t i = i0 + tid;
+    const float xi = i < n ? feat[(a + i) * ldf] : 0.f;
+    const bool si = i < n && xi > c0;
+    int rank = 0;
+    if (!all) {
+      for (int64_t j0 = 0; j0 < n; j0 += kSelTile) {
+        const int nt = (int)min<int64_t>(kSelTile, n - j0);
+        __syncthreads();
+        for (int j = tid; j < nt; j += 256) s_x[j] = feat[(a + j0 + j) * ldf];
+        __syncthreads();
+        if (si)
+          for (int j = 0; j < nt; ++j) {
+            const float xj = s_x[j];
+            rank += xj > c0 && (xj > xi || (xj == xi && j0 + j < i));
+          }
+      }
+    }
+    if (i < n) keep[a + i] = si && (all || rank < limit);
+  }
+  if (tid == 0) cnt[e] = all ? surv : limit;
+}
+
+__global__ __launch_bounds__(256) void k_select_write(const float* __restrict__ feat, int ldf,
+                                                      const int64_t* __restrict__ off,
+                                                      const int64_t* __restrict__ off_out,
+                                                      const uint8_t* __restrict__ keep,
+                                                      float* __restrict__ out) {
+  __shared__ int s_tot[4];
+  const int e = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t a = off[e], n = off[e + 1] - a;
+  int64_t base = off_out[e];
+  for (int64_t i0 = 0; i0 < n; i0 += 256) {
+    const int64_t i = i0 + tid;
+    const bool k = i < n && keep[a + i];
+    // block prefix of the flags: ballot within the wave, wave totals through LDS
+    const uint64_t bal = __ballot(k);
+    const int before_w = __popcll(bal & ((lane ? (~0ull >> (64 - lane)) : 0ull)));
+    __syncthreads();
+    if (lane == 0) s_tot[wave] = __popcll(bal);
+    __syncthreads();
+    int before = before_w;
+    for (int q = 0; q < wave; ++q) before += s_tot[q];
+    if (k) {
+      const float* src = feat + (a + i) * ldf;
+      float* dst = out + (base + before) * ldf;
+      for (int f = 0; f < ldf; ++f) dst[f] = src[f];
+    }
+    base += s_tot[0] + s_tot[1] + s_tot[2] + s_tot[3];
+  }
+}
+
+hipError_t launch_select_count(hipStream_t st, const float* feat, int ldf, const int64_t* off,
+                               int64_t n_events, float c0, int limit, uint8_t* keep,
+                               int32_t* cnt) {
+  if (n_events <= 0) return hipSuccess;
+  if (n_events > 0x7fffffff || limit < 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_select_count, dim3((unsigned)n_events), dim3(256), 0, st, feat, ldf, off,
+                     c0, limit, keep, cnt);
+  return hipGetLastError();
+}
+
+hipError_t launch_select_write(hipStream_t st, const float* feat, int ldf, const int64_t* off,
+                               const int64_t* off_out, int64_t n_events, const uint8_t* keep,
+                               float* out) {
+  if (n_events <= 0) return hipSuccess;
+  if (n_events > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_select_write, dim3((unsigned)n_events), dim3(256), 0, st, feat, ldf, off,
+                     off_out, keep, out);
+  return hipGetLastError();
+}
+
 }  // namespace fmd

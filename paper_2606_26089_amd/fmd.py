@@ -99,6 +99,8 @@ def lib():
         "fmd_noise": (c_int32, [ctypes.c_uint64, P_int64, c_int64, c_int32, c_void_p, c_void_p]),
         "fmd_event_observables": (c_int32, [ctypes.POINTER(EventsIn), c_void_p, c_void_p, c_void_p,
                                             c_void_p]),
+        "fmd_truth_select": (c_int32, [ctypes.POINTER(EventsIn), ctypes.c_double, c_int32, P_int64,
+                                       c_void_p, c_void_p]),
         "fmd_debug_philox": (c_int32, [ctypes.c_uint64, ctypes.c_uint64, c_void_p, c_int64,
                                        c_void_p, c_void_p]),
         "fmd_pack_padded": (c_int32, [c_void_p, c_void_p, c_int64, c_int32, c_int32, c_void_p,
@@ -394,6 +396,25 @@ def event_observables(offsets, feat, stream=None):
         ptrs = [c_void_p(a.ctypes.data) for a in (ht, met, iso)]
     _check(lib().fmd_event_observables(ctypes.byref(ev), *ptrs, _stream(stream)))
     return ht, met, iso
+
+
+def truth_select(offsets, feat, pt_cut_gev, max_particles, stream=None):
+    """(offsets_out [E+1] int64 NumPy, feat_out [offsets_out[-1], 9]) after the model's truth
+    selection: pT > pt_cut_gev, at most max_particles per event (the hardest), input order.
+    feat_out lives where feat lives."""
+    ev, off = _events(offsets, feat)
+    T = int(off[-1])
+    out_off = np.zeros(len(off), dtype=np.int64)
+    if _is_torch(feat):
+        import torch
+        out = torch.empty((T, 9), dtype=torch.float32, device=feat.device)
+        op = c_void_p(out.data_ptr())
+    else:
+        out = np.empty((T, 9), dtype=np.float32)
+        op = c_void_p(out.ctypes.data)
+    _check(lib().fmd_truth_select(ctypes.byref(ev), float(pt_cut_gev), int(max_particles),
+                                  out_off.ctypes.data_as(P_int64), op, _stream(stream)))
+    return out_off, out[: int(out_off[-1])]
 
 
 def pack_padded(padded, lengths, offsets_out, feat_out, stream=None):

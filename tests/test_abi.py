@@ -121,6 +121,14 @@ def test_null_model_and_errors_are_reported(fmd):
     zero = np.zeros(1, dtype=np.int64)
     ev0 = fmd.EventsIn(0, zero.ctypes.data_as(fmd.P_int64), None, 0)
     assert L.fmd_event_observables(ctypes.byref(ev0), None, None, None, None) == fmd.OK
+    oo = np.zeros(3, dtype=np.int64)
+    assert L.fmd_truth_select(None, 0.5, 128, oo.ctypes.data_as(fmd.P_int64), None, None) == fmd.E_INVALID
+    assert L.fmd_truth_select(ctypes.byref(ev0), 0.0, 128, oo.ctypes.data_as(fmd.P_int64), None,
+                              None) == fmd.E_INVALID
+    assert L.fmd_truth_select(ctypes.byref(ev0), 0.5, -1, oo.ctypes.data_as(fmd.P_int64), None,
+                              None) == fmd.E_INVALID
+    assert L.fmd_truth_select(ctypes.byref(ev0), 0.5, 128, oo.ctypes.data_as(fmd.P_int64), None,
+                              None) == fmd.OK
     assert L.fmd_pack_padded(None, None, 1, 4, 9, None, None, None) == fmd.E_INVALID
     assert L.fmd_debug_gemm(0, 4, 60, 32, None, None, None, 0, None, None, 0, None, -1, None) == fmd.E_INVALID
     assert L.fmd_model_destroy(None) == fmd.OK
