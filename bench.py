@@ -105,6 +105,23 @@ def observables_leg(fmd, torch, off, reco, reps):
             "cone_tests_per_call": tests, "calls": reps}
 
 
+def select_leg(fmd, torch, off, feat_d, cut, limit, reps):
+    """Truth preprocessing (model pT cut and particle limit) on the workload's truth, resident
+    on the device: wall time per call over `reps` calls (each ends synchronized)."""
+    o2, _ = fmd.truth_select(off, feat_d, cut, limit)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fmd.truth_select(off, feat_d, cut, limit)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    E = len(off) - 1
+    return {"kernels": ["k_select_count", "k_select_write"], "pt_cut_gev": cut,
+            "max_particles": limit, "ms_per_call": round(dt * 1e3, 4),
+            "events_per_s": round(E / dt, 1), "particles_in": int(off[-1]),
+            "particles_out": int(o2[-1]), "calls": reps}
+
+
 def bound_of(k, dtype):
     """The resource that bounds a kernel class at its algorithmic FLOPs and bytes: the one
     whose peak takes longer to serve them."""
@@ -264,6 +281,9 @@ def main():
     log(f"dominant kernel {rl['kernel']}: {rl['achieved']} {rl['unit']} ({rl['frac']:.3f} of peak), "
         f"HBM traffic {rl['traffic']} bytes/launch (algorithmic {rl['bytes_per_launch']:.0f})")
 
+    selection = select_leg(fmd, torch, off, feat_d, 0.5, 128, 20)
+    log(f"truth selection (0.5 GeV, 128 particles): {selection['ms_per_call']:.3f} ms per call, "
+        f"{selection['particles_in']} -> {selection['particles_out']} particles")
     obs = observables_leg(fmd, torch, off, out16, 20)
     log(f"event observables: {obs['ms_per_call']:.3f} ms per call, {obs['events_per_s']:.0f} "
         f"events/s, {obs['cone_tests_per_s'] / 1e9:.2f} G cone tests/s")
@@ -313,7 +333,7 @@ def main():
                    "precision": "bf16 operands, fp32 accumulation and state",
                    "tiles": kern16["_tiles"]},
         "fp32": fp32, "error": err,
-        "latency": serve, "observables": obs,
+        "latency": serve, "truth_selection": selection, "observables": obs,
         "roofline": rl, "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
