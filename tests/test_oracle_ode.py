@@ -38,13 +38,26 @@ def _rk4_product(alpha, beta, K, t0=0.0, t1=1.0):
     return g
 
 
-@pytest.mark.parametrize("scheme", [ode.EULER, ode.RK4])
+def _midpoint_product(alpha, beta, K, t0=0.0, t1=1.0):
+    """Growth factor of the explicit midpoint rule on x' = (alpha + beta t) x: one step
+    multiplies x by 1 + h m (1 + h a / 2), a = lam(t_k), m = lam(t_k + h/2)."""
+    h = (t1 - t0) / K
+    g = 1.0
+    for k in range(K):
+        t = t0 + k * h
+        a, m = alpha + beta * t, alpha + beta * (t + h / 2)
+        g *= 1 + h * m * (1 + h * a / 2)
+    return g
+
+
+@pytest.mark.parametrize("scheme", [ode.EULER, ode.RK4, ode.MIDPOINT])
 @pytest.mark.parametrize("K", [1, 3, 16, 50])
 def test_linear_field_exact_product(scheme, K):
     alpha, beta = -0.7, 1.9
     x0 = np.array([[1.0, -2.0, 0.5]])
     x = ode.integrate(lambda x, t: (alpha + beta * t) * x, x0, scheme, K)
-    g = _euler_product(alpha, beta, K) if scheme == ode.EULER else _rk4_product(alpha, beta, K)
+    g = {ode.EULER: _euler_product, ode.RK4: _rk4_product,
+         ode.MIDPOINT: _midpoint_product}[scheme](alpha, beta, K)
     np.testing.assert_allclose(x, g * x0, rtol=1e-13)
 
 
@@ -53,11 +66,13 @@ def test_linear_field_converges_to_exponential_at_the_right_order():
     exact = math.exp(alpha + beta / 2)          # x(1) = x0 exp(int_0^1 alpha + beta t dt)
     x0 = np.ones((1, 1))
     errs = {}
-    for scheme in (ode.EULER, ode.RK4):
+    for scheme in (ode.EULER, ode.RK4, ode.MIDPOINT):
         errs[scheme] = [abs(ode.integrate(lambda x, t: (alpha + beta * t) * x, x0, scheme, K)[0, 0]
                             - exact) for K in (8, 16, 32, 64)]
     for a, b in zip(errs[ode.EULER], errs[ode.EULER][1:]):
         assert 0.85 < math.log2(a / b) < 1.15
+    for a, b in zip(errs[ode.MIDPOINT], errs[ode.MIDPOINT][1:]):
+        assert 1.85 < math.log2(a / b) < 2.15
     for a, b in zip(errs[ode.RK4], errs[ode.RK4][1:]):
         assert 3.7 < math.log2(a / b) < 4.3
 
@@ -65,6 +80,7 @@ def test_linear_field_converges_to_exponential_at_the_right_order():
 def test_stage_times():
     assert ode.stage_times(ode.EULER, 4) == [0.0, 0.25, 0.5, 0.75]
     assert ode.stage_times(ode.RK4, 2) == [0.0, 0.25, 0.25, 0.5, 0.5, 0.75, 0.75, 1.0]
+    assert ode.stage_times(ode.MIDPOINT, 2) == [0.0, 0.25, 0.5, 0.75]
     with pytest.raises(ValueError):
         ode.integrate(lambda x, t: x, np.ones(1), ode.EULER, 0)
 
@@ -76,6 +92,9 @@ def test_time_dependence_enters_at_stage_times():
     assert math.isclose(x[0], 0.25, rel_tol=1e-14)
     xe = ode.integrate(lambda x, t: np.full_like(x, t ** 3), np.zeros(1), ode.EULER, K)
     assert math.isclose(xe[0], sum((k / K) ** 3 for k in range(K)) / K, rel_tol=1e-14)
+    # midpoint: the midpoint quadrature sum of t^3
+    xm = ode.integrate(lambda x, t: np.full_like(x, t ** 3), np.zeros(1), ode.MIDPOINT, K)
+    assert math.isclose(xm[0], sum(((k + 0.5) / K) ** 3 for k in range(K)) / K, rel_tol=1e-14)
 
 
 def _tiny_problem():

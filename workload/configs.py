@@ -11,7 +11,7 @@ F_FEAT = 9          # [ln(pT/10 GeV), eta, phi, onehot5(class), charge]
 T_EMBED = 32        # sinusoidal time-embedding width
 MLP_RATIO = 4
 
-EULER, RK4 = 0, 1
+EULER, RK4, MIDPOINT = 0, 1, 2
 FP32, BF16 = 0, 1
 
 
@@ -44,7 +44,7 @@ class Schedule:
 
     @property
     def stages(self) -> int:
-        return 1 if self.scheme == EULER else 4
+        return {EULER: 1, MIDPOINT: 2}.get(self.scheme, 4)
 
     @property
     def evals(self) -> int:
