@@ -54,7 +54,9 @@ typedef enum {
 typedef struct fmd_model fmd_model;     /* opaque */
 
 enum { FMD_FP32 = 0, FMD_BF16 = 1 };   /* precision of GEMM / attention operands */
-enum { FMD_EULER = 0, FMD_RK4 = 1 };   /* integration scheme */
+/* integration scheme: Euler (one evaluation per step, the paper's), classic RK4 (four),
+ * explicit midpoint (two: x <- x + h v(x + h/2 v(x, t), t + h/2)) */
+enum { FMD_EULER = 0, FMD_RK4 = 1, FMD_MIDPOINT = 2 };
 
 /* Network shape. Supported: d_model = n_heads * dh with dh in {16, 32, 64}; d_model a
  * multiple of 64; mlp_ratio = 4; t_embed_dim = 32; f_truth = f_reco = 9; 1 <= n_max <= 4096.

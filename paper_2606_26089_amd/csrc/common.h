@@ -68,7 +68,8 @@ __device__ __forceinline__ float gelu_erf(float z) {
 
 // ODE state update of one feature, v being the velocity evaluated at xs. Modes:
 // 0 Euler x += h v; 1..4 the four RK4 stages (acc collects k1 + 2 k2 + 2 k3, xs receives
-// the next stage input); 5 velocity only (v written to out); anything else: no effect.
+// the next stage input); 5 velocity only (v written to out); 7, 8 the two explicit midpoint
+// stages (xs <- x + h/2 v, then x <- x + h v); anything else: no effect.
 __device__ __forceinline__ void ode_update(int mode, float h, float v, float* x, float* acc,
                                            float* xs, float* out) {
   switch (mode) {
@@ -97,6 +98,14 @@ __device__ __forceinline__ void ode_update(int mode, float h, float v, float* x,
     case 5:
       if (out) *out = v;
       break;
+    case 7:
+      *xs = fmaf(0.5f * h, v, *x);
+      break;
+    case 8: {
+      const float xn = fmaf(h, v, *x);
+      *x = xn; *xs = xn;
+      if (out) *out = xn;
+    } break;
     default:
       break;
   }

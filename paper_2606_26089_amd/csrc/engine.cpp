@@ -203,7 +203,7 @@ int check_events(const fmd_model* m, const fmd_events_in* ev, int64_t* T_out, in
 
 int check_schedule(const fmd_schedule* s) {
   if (!s) return fail(FMD_E_INVALID, "null schedule");
-  if (s->scheme != FMD_EULER && s->scheme != FMD_RK4)
+  if (s->scheme != FMD_EULER && s->scheme != FMD_RK4 && s->scheme != FMD_MIDPOINT)
     return fail(FMD_E_INVALID, "unknown scheme %d", s->scheme);
   if (s->n_steps < 1) return fail(FMD_E_INVALID, "n_steps must be >= 1");
   if (!std::isfinite(s->t0) || !std::isfinite(s->t1) || s->t0 == s->t1)
@@ -569,10 +569,35 @@ int head(fmd_model* m, Call& c, bool direct, int mode, float* out, int ldo) {
   });
 }
 
+int stages_per_step(int scheme) {
+  return scheme == FMD_EULER ? 1 : scheme == FMD_MIDPOINT ? 2 : 4;
+}
+
+// Stage i of a schedule (step i / S, stage i % S): evaluation time, step and update mode.
+StageDesc stage_desc(const fmd_schedule& s, int i) {
+  static const double c_rk4[4] = {0.0, 0.5, 0.5, 1.0};
+  const int S = stages_per_step(s.scheme), k = i / S, st = i % S;
+  const double h = (s.t1 - s.t0) / s.n_steps;
+  StageDesc d;
+  if (s.scheme == FMD_EULER) {
+    d.t = (float)(s.t0 + k * h);
+    d.mode = UPD_EULER;
+  } else if (s.scheme == FMD_MIDPOINT) {
+    d.t = (float)(s.t0 + (k + 0.5 * st) * h);
+    d.mode = st == 0 ? UPD_MID_0 : UPD_MID_1;
+  } else {
+    d.t = (float)(s.t0 + (k + c_rk4[st]) * h);
+    d.mode = UPD_RK4_0 + st;
+  }
+  d.h = (float)h;
+  d.write_out = i == s.n_steps * S - 1;
+  return d;
+}
+
 // Uploads the stage table of a schedule: stage i = (t, h, update mode, write output).
 int upload_stages(fmd_model* m, Call& c, const fmd_schedule* s, int* n_stages) {
   Workspace& w = m->ws;
-  const int K = s->n_steps, S = s->scheme == FMD_EULER ? 1 : 4;
+  const int K = s->n_steps, S = stages_per_step(s->scheme);
   const int n = K * S;
   if (n > w.cap_desc) {
     FMD_TRY(grow(w.desc, (size_t)n * sizeof(StageDesc)));
@@ -581,16 +606,7 @@ int upload_stages(fmd_model* m, Call& c, const fmd_schedule* s, int* n_stages) {
     w.cap_desc = n;
     w.generation++;
   }
-  const double h = (s->t1 - s->t0) / K;
-  static const double c_rk4[4] = {0.0, 0.5, 0.5, 1.0};
-  for (int k = 0; k < K; ++k)
-    for (int st = 0; st < S; ++st) {
-      StageDesc& d = w.h_desc[k * S + st];
-      d.t = (float)(s->t0 + (k + (S == 1 ? 0.0 : c_rk4[st])) * h);
-      d.h = (float)h;
-      d.mode = S == 1 ? UPD_EULER : UPD_RK4_0 + st;
-      d.write_out = k == K - 1 && st == S - 1;
-    }
+  for (int i = 0; i < n; ++i) w.h_desc[i] = stage_desc(*s, i);
   HIP_TRY(hipMemcpyAsync(w.desc, w.h_desc, (size_t)n * sizeof(StageDesc), hipMemcpyHostToDevice, c.st));
   FMD_TRY(timed(m, c.st, FMD_K_OTHER, 0, [&] { return launch_set_counter(c.st, w.ctr, 0); }));
   *n_stages = n;

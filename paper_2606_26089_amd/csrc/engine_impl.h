@@ -109,6 +109,8 @@ struct Call {
 int ensure_ws(fmd_model* m, int64_t T, int64_t E, int64_t items);
 int check_events(const fmd_model* m, const fmd_events_in* ev, int64_t* T_out, int64_t* max_n);
 int check_schedule(const fmd_schedule* s);
+int stages_per_step(int scheme);
+StageDesc stage_desc(const fmd_schedule& s, int i);
 int row_stats(fmd_model* m, Call& c);
 int enter_stream(fmd_model* m, hipStream_t caller, Call& c);
 int leave_stream(fmd_model* m, hipStream_t caller);

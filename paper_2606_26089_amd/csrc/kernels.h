@@ -21,7 +21,9 @@ enum UpdMode {
   UPD_RK4_2 = 3,      // acc <- acc + 2v ; xs <- x + h v
   UPD_RK4_3 = 4,      // x <- x + h/6 (acc + v) ; xs <- x
   UPD_VELOCITY = 5,   // v only, written to `out`
-  UPD_NONE = 6        // no update (rows that belong to no event)
+  UPD_NONE = 6,       // no update (rows that belong to no event)
+  UPD_MID_0 = 7,      // xs <- x + h/2 v  (explicit midpoint, first stage)
+  UPD_MID_1 = 8       // x <- x + h v ; xs <- x
 };
 
 constexpr int kStateLd = 16;       // row stride (floats) of the device ODE state arrays

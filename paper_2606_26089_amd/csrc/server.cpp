@@ -193,7 +193,6 @@ int iterate(fmd_server* S, std::vector<Req*>& finished) {
   std::vector<std::pair<int64_t, int64_t>> real;   // (segment index, length)
   double sum_n2 = 0;
   int64_t pos = 0, items = 0;
-  static const double c_rk4[4] = {0.0, 0.5, 0.5, 1.0};
   for (Req* r : res) {
     if (r->base > pos) {
       off.push_back(r->base);
@@ -201,14 +200,7 @@ int iterate(fmd_server* S, std::vector<Req*>& finished) {
       tev.push_back(0.f);
       pos = r->base;
     }
-    const int Sn = r->sched.scheme == FMD_EULER ? 1 : 4;
-    const int k = r->stage / Sn, st = r->stage % Sn;
-    const double h = (r->sched.t1 - r->sched.t0) / r->sched.n_steps;
-    StageDesc sd;
-    sd.t = (float)(r->sched.t0 + (k + (Sn == 1 ? 0.0 : c_rk4[st])) * h);
-    sd.h = (float)h;
-    sd.mode = Sn == 1 ? UPD_EULER : UPD_RK4_0 + st;
-    sd.write_out = r->stage == r->n_stages - 1;
+    const StageDesc sd = stage_desc(r->sched, r->stage);
     for (int64_t e = 0; e < r->n_events; ++e) {
       const int64_t n = r->off[e + 1] - r->off[e];
       if (n == 0) continue;
@@ -413,7 +405,7 @@ int fmd_server_submit(fmd_server* S, const fmd_events_in* truth, uint64_t seed,
   r->sched = *sched;
   r->T = T;
   r->n_events = truth->n_events;
-  r->n_stages = sched->n_steps * (sched->scheme == FMD_EULER ? 1 : 4);
+  r->n_stages = sched->n_steps * stages_per_step(sched->scheme);
   r->out.assign((size_t)T * 9, 0.f);
   r->stats.t_submit_ns = now_ns();
   std::lock_guard<std::mutex> lk(S->mu);

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libfmdet.so")
 OK, PENDING = 0, 1
 E_INVALID, E_NOMEM, E_BUDGET, E_UNSUPPORTED, E_DEVICE, E_STATE = -1, -2, -3, -4, -5, -6
 FP32, BF16 = 0, 1
-EULER, RK4 = 0, 1
+EULER, RK4, MIDPOINT = 0, 1, 2
 (K_GEMM_QKV, K_GEMM_PROJ, K_GEMM_QC, K_GEMM_UP, K_GEMM_DOWN, K_FUSED_OQC, K_FUSED_MLP,
  K_ATTN_SELF, K_ATTN_CROSS, K_OTHER) = range(10)
 FUSED_QKV, FUSED_OQC, FUSED_MLP, FUSED_ALL = 1, 2, 4, 7

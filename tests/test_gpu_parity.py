@@ -33,7 +33,8 @@ def dev(torch, a):
 # integrator and state update against the closed form of a linear field
 
 @pytest.mark.parametrize("scheme,K", [(configs.EULER, 1), (configs.EULER, 20), (configs.RK4, 1),
-                                      (configs.RK4, 16)])
+                                      (configs.RK4, 16), (configs.MIDPOINT, 1),
+                                      (configs.MIDPOINT, 32)])
 def test_linear_field_closed_form(env, scheme, K):
     torch, fmd = env
     alpha, beta = -0.7, 1.9
@@ -48,6 +49,8 @@ def test_linear_field_closed_form(env, scheme, K):
         t = k * h
         if scheme == configs.EULER:
             g *= 1 + h * (alpha + beta * t)
+        elif scheme == configs.MIDPOINT:
+            g *= 1 + h * (alpha + beta * (t + h / 2)) * (1 + h * (alpha + beta * t) / 2)
         else:
             a, mid, e = alpha + beta * t, alpha + beta * (t + h / 2), alpha + beta * (t + h)
             k2 = mid * (1 + h * a / 2)
@@ -110,6 +113,20 @@ def test_small_workload_perturbed_params_rk4(env):
     m.close()
     ref = sample.simulate(flat, cfg, off, feat, sched, seed=3)
     assert errors.normwise_rel_err(out, ref).max() < 1e-4
+
+
+@pytest.mark.parametrize("cfg,tol", [(configs.SMALL_MODEL, 1e-4),
+                                     (configs.BASE_MODEL.with_precision(configs.BF16), 2e-2)])
+def test_midpoint_integration_matches_oracle(env, cfg, tol):
+    torch, fmd = env
+    off, feat = events.truth_events(8, ("uniform", 1, 48), seed=22)
+    flat = params.draw(cfg, seed=6, perturbed=True)
+    sched = configs.Schedule(configs.MIDPOINT, 6)
+    m = fmd.Model(cfg, flat)
+    out = m.simulate(off, dev(torch, feat), 4, sched).cpu().numpy()
+    m.close()
+    ref = sample.simulate(flat, cfg, off, feat, sched, seed=4)
+    assert errors.normwise_rel_err(out, ref).max() < tol
 
 
 def _golden():

@@ -25,7 +25,8 @@ def _requests(n, seed=0):
     out = []
     for i in range(n):
         off, feat = events.truth_events(int(rng.integers(1, 9)), ("uniform", 1, 64), seed=100 + i)
-        sched = configs.Schedule(configs.EULER, 3) if i % 2 else configs.Schedule(configs.RK4, 2)
+        sched = (configs.Schedule(configs.RK4, 2), configs.Schedule(configs.EULER, 3),
+                 configs.Schedule(configs.MIDPOINT, 3))[i % 3]
         out.append((off, feat, 1000 + i, sched))
     return out
 
