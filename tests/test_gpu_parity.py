@@ -129,6 +129,30 @@ def test_midpoint_integration_matches_oracle(env, cfg, tol):
     assert errors.normwise_rel_err(out, ref).max() < tol
 
 
+def test_integrators_at_equal_evaluation_budget(env, capsys):
+    """Euler 64 steps, midpoint 32, RK4 16 (64 evaluations each) on the FP32 path against a
+    fine oracle integration (RK4, 64 steps): the step count and scheme trade speed for
+    quality; at equal cost the higher order wins by orders of magnitude."""
+    torch, fmd = env
+    cfg = configs.BASE_MODEL
+    off, feat = events.truth_events(4, ("uniform", 20, 60), seed=23)
+    flat = params.draw(cfg, seed=0)
+    ref = sample.simulate(flat, cfg, off, feat, configs.Schedule(configs.RK4, 64), seed=7)
+    m = fmd.Model(cfg, flat)
+    errs = {}
+    for name, sched in (("euler", configs.Schedule(configs.EULER, 64)),
+                        ("midpoint", configs.Schedule(configs.MIDPOINT, 32)),
+                        ("rk4", configs.Schedule(configs.RK4, 16))):
+        assert sched.evals == 64
+        out = m.simulate(off, dev(torch, feat), 7, sched).cpu().numpy()
+        errs[name] = float(errors.normwise_rel_err(out, ref).max())
+    m.close()
+    with capsys.disabled():
+        print(f"\nerror vs fine oracle at 64 evaluations: {errs}")
+    assert errs["rk4"] < errs["midpoint"] < errs["euler"]
+    assert errs["rk4"] < 1e-3
+
+
 def _golden():
     if not os.path.exists(GOLDEN):
         pytest.skip("golden oracle outputs missing (tests/golden/make_oracle_outputs.py)")
