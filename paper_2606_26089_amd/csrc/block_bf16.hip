@@ -475,6 +475,20 @@ __device__ __forceinline__ void row_stats_nc(const f32x16 (&acc)[TM][2], SharedL
   }
 }
 
+// Head partials of the 32 TM rows: lane l ends with the sum over this wave's 64 columns of
+// y * w for its own row own_row(0, l) (the lane's two columns by one fused multiply-add,
+// then the transpose-reduction).
+__device__ __forceinline__ float head_partial(const f32x16 (&y)[2][2], float w0, float w1,
+                                              int lane) {
+  float v[32];
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[h * 16 + r] = fmaf(y[h][1][r], w1, y[h][0][r] * w0);
+  transpose_reduce32(v, lane);
+  return v[0];
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------------------
@@ -557,13 +571,28 @@ struct NextQkv {
   bf16* qkv;             // [3][8 heads][Mp][32]
 };
 
-template <int TM, bool QKV>
+// With HEAD (the last block), the kernel applies the output head to the final rows instead:
+// LN_f, the 9-wide projection (FP32, per-wave partial sums over the wave's 64 columns by the
+// transpose-reduction, then the 4 wave partials in wave order) and the ODE update of the
+// state, as the separate head kernel does; the residual rows are then not stored.
+struct NextHead {
+  const float* g;        // LN_f gain and shift
+  const float* s;
+  const float* Wt;       // W_out transposed: row c = weights of output c (c < 9), 256 wide
+  const float* b;
+  OdeArgs ode;
+};
+
+enum MlpTail { kTailStats = 0, kTailQkv = 1, kTailHead = 2 };
+
+template <int TM, int TAIL>
 __global__ __launch_bounds__(kThreads4) __attribute__((amdgpu_waves_per_eu(2))) void k_fused_mlp(
     const bf16* __restrict__ att, const u32x4* __restrict__ Wf_oc, const float* __restrict__ b_oc,
     float* __restrict__ H, const float* __restrict__ g, const float* __restrict__ s,
     const u32x4* __restrict__ Wf_up, const float* __restrict__ b_up,
     const u32x4* __restrict__ Wf_dn, const float* __restrict__ b_dn,
-    float2* __restrict__ stats_out, NextQkv nq) {
+    float2* __restrict__ stats_out, NextQkv nq, NextHead nh) {
+  constexpr bool QKV = TAIL == kTailQkv;
   constexpr int ROWS = 32 * TM;
   static_assert(ROWS == 64, "statistics scratch sized for 64 rows");
   __shared__ __attribute__((aligned(16))) bf16 A[ROWS * kLdA];
@@ -665,11 +694,61 @@ __global__ __launch_bounds__(kThreads4) __attribute__((amdgpu_waves_per_eu(2))) 
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         acc[mi][nj][r] += bv;
-        *io.at(mi, r) = acc[mi][nj][r];
+        if constexpr (TAIL != kTailHead) *io.at(mi, r) = acc[mi][nj][r];
       }
   }
-  if constexpr (!QKV) {
+  if constexpr (TAIL == kTailStats) {
     row_stats_nc(acc, sl, stats_out, m0, lane, w);
+  } else if constexpr (TAIL == kTailHead) {
+    static_assert(TM == 2, "one 32-value group per lane");
+    constexpr int kF = 9;
+    row_stats_nc(acc, sl, nullptr, m0, lane, w);   // barriers: the hidden buffers are free
+    const float* mu = sl.mu[w];
+    const float* rs = sl.rs[w];
+#pragma unroll
+    for (int nj = 0; nj < 2; ++nj) {
+      const int col = col0 + 32 * nj;
+      const float gv = nh.g[col], sv = nh.s[col];
+#pragma unroll
+      for (int mi = 0; mi < TM; ++mi)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int row = acc_row(mi, r, lane);
+          acc[mi][nj][r] = fmaf((acc[mi][nj][r] - mu[row]) * rs[row], gv, sv);
+        }
+    }
+    float* part = reinterpret_cast<float*>(Hc[0]);    // [ROWS][kF][kWaves4]
+#pragma unroll 1
+    for (int c = 0; c < kF; ++c) {
+      part[(own_row(0, lane) * kF + c) * kWaves4 + w] =
+          head_partial(acc, nh.Wt[c * kD + col0], nh.Wt[c * kD + col0 + 32], lane);
+    }
+    __syncthreads();
+    const OdeArgs& od = nh.ode;
+    int mode = od.mode;
+    float hs = od.h;
+    float* out = od.out;
+    if (od.desc && !od.tok_event) {
+      const StageDesc sd = od.desc[*od.ctr];
+      mode = sd.mode;
+      hs = sd.h;
+      if (!sd.write_out) out = nullptr;
+    }
+    for (int t = tid; t < ROWS * kF; t += kThreads4) {
+      const int row = t / kF, f = t % kF;
+      const int64_t r = m0 + row;
+      if (r >= od.m_valid) continue;
+      const float* p = &part[t * kWaves4];
+      const float v = ((p[0] + p[1]) + p[2]) + p[3] + nh.b[f];
+      const int64_t o = r * od.ldx + f;
+      if (od.tok_event) {
+        const StageDesc sd = od.desc[od.tok_event[r]];
+        ode_update(sd.mode, sd.h, v, od.x + o, od.acc + o, od.xs + o,
+                   out && sd.write_out ? out + r * od.ldo + f : nullptr);
+      } else {
+        ode_update(mode, hs, v, od.x + o, od.acc + o, od.xs + o, out ? out + r * od.ldo + f : nullptr);
+      }
+    }
   } else {
     // slab sl of the next block's W_qkv: column blocks 8 sl + 2w, 8 sl + 2w + 1
     auto qkv_c = [&](int slab) { return nq.Wf + (8 * slab + 2 * w) * kOcStride; };
@@ -774,20 +853,31 @@ hipError_t launch_fused_mlp(hipStream_t st, int64_t Mp, const void* att, const v
                             const void* Wf_up, const float* b_up, const void* Wf_dn,
                             const float* b_dn, float2* stats_out, const float* g1n,
                             const float* s1n, const void* Wf_qkv_n, const float* b_qkv_n,
-                            void* qkv) {
+                            void* qkv, const float* gf, const float* sf, const float* Wt_out,
+                            const float* b_out, const OdeArgs* head) {
   if (Mp % 64) return hipErrorInvalidValue;
   if (Mp == 0) return hipSuccess;
+  if (qkv && head) return hipErrorInvalidValue;
   const dim3 grid((unsigned)(Mp / 64));
   if (qkv) {
     if (!g1n || !s1n || !Wf_qkv_n || !b_qkv_n) return hipErrorInvalidValue;
     const NextQkv nq{g1n, s1n, (const u32x4*)Wf_qkv_n, b_qkv_n, (bf16*)qkv};
-    hipLaunchKernelGGL((k_fused_mlp<2, true>), grid, dim3(kThreads4), 0, st, (const bf16*)att,
-                       (const u32x4*)Wf_oc, b_oc, H, g, s, (const u32x4*)Wf_up, b_up,
-                       (const u32x4*)Wf_dn, b_dn, stats_out, nq);
+    hipLaunchKernelGGL((k_fused_mlp<2, kTailQkv>), grid, dim3(kThreads4), 0, st,
+                       (const bf16*)att, (const u32x4*)Wf_oc, b_oc, H, g, s,
+                       (const u32x4*)Wf_up, b_up, (const u32x4*)Wf_dn, b_dn, stats_out, nq,
+                       NextHead{});
+  } else if (head) {
+    if (!gf || !sf || !Wt_out || !b_out || head->nf != 9) return hipErrorInvalidValue;
+    const NextHead nh{gf, sf, Wt_out, b_out, *head};
+    hipLaunchKernelGGL((k_fused_mlp<2, kTailHead>), grid, dim3(kThreads4), 0, st,
+                       (const bf16*)att, (const u32x4*)Wf_oc, b_oc, H, g, s,
+                       (const u32x4*)Wf_up, b_up, (const u32x4*)Wf_dn, b_dn, stats_out,
+                       NextQkv{}, nh);
   } else {
-    hipLaunchKernelGGL((k_fused_mlp<2, false>), grid, dim3(kThreads4), 0, st, (const bf16*)att,
-                       (const u32x4*)Wf_oc, b_oc, H, g, s, (const u32x4*)Wf_up, b_up,
-                       (const u32x4*)Wf_dn, b_dn, stats_out, NextQkv{});
+    hipLaunchKernelGGL((k_fused_mlp<2, kTailStats>), grid, dim3(kThreads4), 0, st,
+                       (const bf16*)att, (const u32x4*)Wf_oc, b_oc, H, g, s,
+                       (const u32x4*)Wf_up, b_up, (const u32x4*)Wf_dn, b_dn, stats_out,
+                       NextQkv{}, NextHead{});
   }
   return hipGetLastError();
 }

@@ -517,15 +517,24 @@ int net_forward(fmd_model* m, Call& c, const float* t_ev) {
       // chained with the next block's LN1 + QKV when that segment is fused too
       const bool chain = (fz & FMD_FUSED_QKV) && l + 1 < L;
       const DevBlock* N = chain ? &m->blk[l + 1] : nullptr;
-      FMD_TRY(timed(m, c.st, FMD_K_FUSED_MLP, 2.0 * Td * dd * dd * (chain ? 15 : 9),
-                    Td * (dd * (es + 8) + 8) + 9 * dd * dd * es +
-                        (chain ? Td * 3 * dd * es + 3 * dd * dd * es : 0.0), [&] {
+      // the last block applies the output head and the state update instead of storing H
+      const bool fold = l + 1 == L && c.head && c.head->nf == 9;
+      const double Tv = (double)c.T;
+      FMD_TRY(timed(m, c.st, FMD_K_FUSED_MLP,
+                    2.0 * Td * dd * dd * (chain ? 15 : 9) + (fold ? 2.0 * Tv * dd * 9 : 0.0),
+                    Td * (dd * (es + (fold ? 4 : 8)) + (fold ? 0 : 8)) + 9 * dd * dd * es +
+                        (chain ? Td * 3 * dd * es + 3 * dd * dd * es : 0.0) +
+                        (fold ? Tv * 9 * 4 * 5 : 0.0), [&] {
         return launch_fused_mlp(c.st, c.Tp, w.att, B.Foc, B.boc, w.H, B.g3, B.s3, B.Fup, B.bup,
                                 B.Fdn, B.bdn, w.stats, chain ? N->g1 : nullptr,
                                 chain ? N->s1 : nullptr, chain ? N->Fqkv : nullptr,
-                                chain ? N->bqkv : nullptr, chain ? w.qkv : nullptr);
+                                chain ? N->bqkv : nullptr, chain ? w.qkv : nullptr,
+                                fold ? m->g_f : nullptr, fold ? m->s_f : nullptr,
+                                fold ? m->Wout_pk : nullptr, fold ? m->bout_pk : nullptr,
+                                fold ? c.head : nullptr);
       }));
       qkv_ready = chain;
+      c.head_done = fold;
     } else {
       FMD_TRY(timed(m, c.st, FMD_K_GEMM_PROJ, 2.0 * Td * d * d, (Td + d) * d * es + resid, [&] {
         return launch_gemm<T>(c.st, FMD_K_GEMM_PROJ, false, resid_epi(m), c.Tp, d, d, w.att, d,
@@ -550,6 +559,12 @@ int net_forward(fmd_model* m, Call& c, const float* t_ev) {
 
 // Output head with the fused state update. With `direct` the update mode is `mode` (the
 // velocity-only hook); otherwise mode, step and output write follow the stage table.
+OdeArgs head_args(fmd_model* m, Call& c, bool direct, int mode, float* out, int ldo) {
+  Workspace& w = m->ws;
+  return OdeArgs{w.x, w.acc, w.xs, out, c.T, kStateLd, ldo, 9, mode, 0.f,
+                 direct ? nullptr : w.desc, w.ctr, nullptr};
+}
+
 int head(fmd_model* m, Call& c, bool direct, int mode, float* out, int ldo) {
   Workspace& w = m->ws;
   if (m->kind == 1)
@@ -559,8 +574,7 @@ int head(fmd_model* m, Call& c, bool direct, int mode, float* out, int ldo) {
     });
   FMD_TRY(row_stats(m, c));
   const int d = m->cfg.d_model;
-  const OdeArgs ode{w.x, w.acc, w.xs, out, c.T, kStateLd, ldo, 9, mode, 0.f,
-                    direct ? nullptr : w.desc, w.ctr, nullptr};
+  const OdeArgs ode = head_args(m, c, direct, mode, out, ldo);
   return timed(m, c.st, FMD_K_OTHER, 2.0 * c.T * d * 9, [&] {
     if (head256_supported(d, 9))
       return launch_head256(c.st, w.H, w.stats, m->g_f, m->s_f, m->Wout_pk, m->bout_pk, ode);
@@ -616,8 +630,13 @@ int upload_stages(fmd_model* m, Call& c, const fmd_schedule* s, int* n_stages) {
 // One ODE stage: velocity at the current stage input, fused update, counter advance.
 template <typename T>
 int run_stage(fmd_model* m, Call& c, float* out, int ldo) {
-  if (m->kind == 0) FMD_TRY(net_forward<T>(m, c, nullptr));
-  FMD_TRY(head(m, c, false, 0, out, ldo));
+  const OdeArgs ode = head_args(m, c, false, 0, out, ldo);
+  c.head = &ode;
+  c.head_done = false;
+  const int rc = m->kind == 0 ? net_forward<T>(m, c, nullptr) : FMD_OK;
+  c.head = nullptr;
+  FMD_TRY(rc);
+  if (!c.head_done) FMD_TRY(head(m, c, false, 0, out, ldo));
   return timed(m, c.st, FMD_K_OTHER, 0, [&] { return launch_stage_advance(c.st, m->ws.ctr); });
 }
 

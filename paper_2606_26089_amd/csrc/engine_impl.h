@@ -103,6 +103,10 @@ struct Call {
   double sum_n2;        // sum over events of N_e^2 (attention work)
   const float* u;       // truth features on device [T, 9]
   OdeArgs sargs;        // epilogue arguments of the residual GEMMs (statistics output)
+  // Output head to fold into the last block's fused MLP kernel (9 features, BF16 fused
+  // path); net_forward sets head_done when it did, and the caller then skips its head.
+  const OdeArgs* head = nullptr;
+  bool head_done = false;
 };
 
 

@@ -196,13 +196,18 @@ hipError_t launch_fused_oqc(hipStream_t st, int64_t Mp, const void* att, const v
                             const void* Wf_qc, const float* b_qc, void* qc);
 // H += att Woc + b_oc;  H += GELU(LN(H; g, s) Wup + b_up) Wdn + b_dn;  stats_out = LN stats of
 // H. With qkv set, also the next block's [Q | K | V] = LN(H; g1n, s1n) Wqkv_n + b_qkv_n into
-// qkv, head-major like launch_fused_qkv (the next block then skips its QKV kernel).
+// qkv, head-major like launch_fused_qkv (the next block then skips its QKV kernel). With head
+// set instead (the last block, 9 features), the output head LN_f(H; gf, sf) Wt_out^T + b_out
+// and the ODE update of *head, as launch_head256 does; H is then not written.
 hipError_t launch_fused_mlp(hipStream_t st, int64_t Mp, const void* att, const void* Wf_oc,
                             const float* b_oc, float* H, const float* g, const float* s,
                             const void* Wf_up, const float* b_up, const void* Wf_dn,
                             const float* b_dn, float2* stats_out, const float* g1n = nullptr,
                             const float* s1n = nullptr, const void* Wf_qkv_n = nullptr,
-                            const float* b_qkv_n = nullptr, void* qkv = nullptr);
+                            const float* b_qkv_n = nullptr, void* qkv = nullptr,
+                            const float* gf = nullptr, const float* sf = nullptr,
+                            const float* Wt_out = nullptr, const float* b_out = nullptr,
+                            const OdeArgs* head = nullptr);
 
 // dst[i] = T(src[i]).
 template <typename T>

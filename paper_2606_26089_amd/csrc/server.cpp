@@ -248,15 +248,20 @@ int iterate(fmd_server* S, std::vector<Req*>& finished) {
   c.u = w.u;
   HIP_TRY(launch_token_map(S->st, w.off, E, span, w.tok_event));
   FMD_TRY(autotune<T>(m, c));
-  FMD_TRY(net_forward<T>(m, c, w.tev));
-  FMD_TRY(row_stats(m, c));
-  const int d = m->cfg.d_model;
   const OdeArgs ode{w.x, w.acc, w.xs, w.io, span, kStateLd, 9, 9, 0, 0.f, w.desc, nullptr, w.tok_event};
-  if (head256_supported(d, 9))
-    HIP_TRY(launch_head256(S->st, w.H, w.stats, m->g_f, m->s_f, m->Wout_pk, m->bout_pk, ode));
-  else
-    HIP_TRY(launch_gemm<float>(S->st, FMD_K_OTHER, true, EPI_ODE, c.Tp, 64, d, w.H, d,
-                               m->Wout_pk, m->bout_pk, w.stats, m->g_f, m->s_f, nullptr, 0, &ode));
+  c.head = &ode;
+  FMD_TRY(net_forward<T>(m, c, w.tev));
+  c.head = nullptr;
+  const int d = m->cfg.d_model;
+  if (!c.head_done) {   // else the last block's MLP kernel applied the head
+    FMD_TRY(row_stats(m, c));
+    if (head256_supported(d, 9))
+      HIP_TRY(launch_head256(S->st, w.H, w.stats, m->g_f, m->s_f, m->Wout_pk, m->bout_pk, ode));
+    else
+      HIP_TRY(launch_gemm<float>(S->st, FMD_K_OTHER, true, EPI_ODE, c.Tp, 64, d, w.H, d,
+                                 m->Wout_pk, m->bout_pk, w.stats, m->g_f, m->s_f, nullptr, 0,
+                                 &ode));
+  }
   for (Req* r : res)
     if (r->stage == r->n_stages - 1) {
       HIP_TRY(hipMemcpyAsync(r->out.data(), w.io + r->base * 9, (size_t)r->T * 9 * 4,
