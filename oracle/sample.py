@@ -4,9 +4,12 @@ simulate(truth sets, seed, schedule) -> reco sets, the problem the paper states 
 detector backends (Sec. 1, program summary: truth-level particles in, detector-level
 reconstructed particles out) with the neural backend's sampler (Sec. 2.2). Each event is
 handled alone: its noise is drawn from (seed, event index), its own truth encoding is
-formed, and the ODE is integrated over its N reco slots, one per truth particle (the
-reco multiplicity equals the truth multiplicity in every workload here; the paper's
-model can add particles, a mechanism it does not describe).
+formed, and the ODE is integrated over its reco slots: one per truth particle by default,
+or the per-event reco multiplicities the caller gives (``reco_offsets``). The paper's model
+can emit more or fewer reco particles than truth particles but does not describe how the
+count is chosen; the network itself needs no change for it, since self-attention runs over
+the reco slots and cross-attention from them to the event's truth particles (Sec. 2.2).
+A reco slot needs at least one truth particle to attend to.
 
 ``decode`` maps a 9-feature state back to particle quantities for physics checks:
 pT = 10 GeV exp(x0), eta = x1, phi wrapped to [-pi, pi), class = argmax x[3:8],
@@ -44,23 +47,31 @@ def _pool_init():
 
 
 def simulate_events(flat, cfg, offsets, feat, schedule, seed=None, x0=None, event_ids=None,
-                    dtype=np.float64, processes=1, progress=None):
-    """Run events of a CSR batch; returns the list of per-event [N_e, 9] outputs.
+                    dtype=np.float64, processes=1, progress=None, reco_offsets=None):
+    """Run events of a CSR batch; returns the list of per-event [N_reco_e, 9] outputs.
 
     ``event_ids`` selects events (default all); noise uses the event's index in the batch.
-    ``x0`` ([T, 9], same CSR) replaces the seeded noise when given.
+    ``reco_offsets`` ([E + 1], default ``offsets``) gives the reco multiplicities; the noise
+    of an event's reco slot s is the generator's draw for (event, s) whatever the truth count.
+    ``x0`` ([T_reco, 9], CSR by ``reco_offsets``) replaces the seeded noise when given.
     """
     offsets = np.asarray(offsets, dtype=np.int64)
     E = len(offsets) - 1
+    roff = offsets if reco_offsets is None else np.asarray(reco_offsets, dtype=np.int64)
+    if len(roff) != E + 1 or roff[0] != 0 or np.any(np.diff(roff) < 0):
+        raise ValueError("reco_offsets must be non-decreasing from 0, one entry per event + 1")
     ids = range(E) if event_ids is None else event_ids
     jobs = []
     for e in ids:
         a, b = int(offsets[e]), int(offsets[e + 1])
+        ra, rb = int(roff[e]), int(roff[e + 1])
+        if rb > ra and b == a:
+            raise ValueError(f"event {e} has reco slots but no truth particle")
         u = np.asarray(feat[a:b], dtype=np.float64)
         if x0 is not None:
-            xe = np.asarray(x0[a:b], dtype=np.float64)
+            xe = np.asarray(x0[ra:rb], dtype=np.float64)
         else:
-            xe = noise_event(seed, e, b - a, cfg.f_reco)
+            xe = noise_event(seed, e, rb - ra, cfg.f_reco)
         jobs.append((flat, cfg, u, xe, schedule.scheme, schedule.n_steps,
                      schedule.t0, schedule.t1, dtype))
     out = []
@@ -79,9 +90,10 @@ def simulate_events(flat, cfg, offsets, feat, schedule, seed=None, x0=None, even
 
 
 def simulate(flat, cfg, offsets, feat, schedule, seed=None, x0=None, dtype=np.float64,
-             processes=1):
-    """Whole CSR batch -> [T, 9] FP64 reco state (the raw ODE state at t1)."""
-    outs = simulate_events(flat, cfg, offsets, feat, schedule, seed, x0, None, dtype, processes)
+             processes=1, reco_offsets=None):
+    """Whole CSR batch -> [T_reco, 9] FP64 reco state (the raw ODE state at t1)."""
+    outs = simulate_events(flat, cfg, offsets, feat, schedule, seed, x0, None, dtype, processes,
+                           reco_offsets=reco_offsets)
     return np.concatenate(outs) if outs else np.zeros((0, cfg.f_reco))
 
 
