@@ -138,6 +138,21 @@ int fmd_linear_field_create(double alpha, double beta, fmd_model** out);
 int fmd_simulate(fmd_model* m, const fmd_events_in* truth, uint64_t seed,
                  const fmd_schedule* schedule, fmd_events_out* reco, void* hip_stream);
 
+/* As fmd_simulate, with a reco multiplicity per event given by the caller (the model can
+ * emit more or fewer reco particles than truth particles, Sec. 2.2; how the count is chosen
+ * the paper does not describe, so it is an input here). The reco slots of event e are rows
+ * reco_offsets[e] .. reco_offsets[e + 1] - 1 of reco->feat ([reco_offsets[n], f_reco] FP32,
+ * where reco->on_device says); they self-attend and cross-attend to the event's truth
+ * particles. reco_offsets is a host array [n_events + 1], read during the call only; slot i
+ * of event e draws the noise fmd_simulate describes for (e, i), whatever the truth count.
+ * With reco_offsets equal to truth->offsets the result equals fmd_simulate's.
+ * Errors: as fmd_simulate; FMD_E_INVALID also for null or decreasing reco offsets and for
+ * reco slots in an event without truth particles; FMD_E_UNSUPPORTED for more than n_max
+ * reco slots in an event. */
+int fmd_simulate_reco(fmd_model* m, const fmd_events_in* truth, const int64_t* reco_offsets,
+                      uint64_t seed, const fmd_schedule* schedule, fmd_events_out* reco,
+                      void* hip_stream);
+
 /* As fmd_simulate, but starts from a given state x0 [offsets[n], f_reco] FP32. x0 lives
  * where truth->feat lives (on_device). */
 int fmd_simulate_from_state(fmd_model* m, const fmd_events_in* truth, const float* x0,

@@ -243,37 +243,55 @@ void flush_timing(fmd_model* m) {
 // ---------------------------------------------------------------------------------------
 // one call's device state
 
-// Uploads offsets and the attention work list; runs the token map.
-int stage_events(fmd_model* m, const fmd_events_in* ev, Call& c) {
+// Uploads offsets and the attention work lists; runs the token map. With reco_off (host,
+// [E + 1], already checked) the reco slots of event e are reco_off[e] .. reco_off[e + 1]
+// and their cross-attention keys the event's truth particles; otherwise reco = truth.
+int stage_events(fmd_model* m, const fmd_events_in* ev, Call& c, const int64_t* reco_off = nullptr) {
   Workspace& w = m->ws;
   const int64_t E = ev->n_events;
+  const int64_t* roff = reco_off ? reco_off : ev->offsets;
+  const int64_t Tt = ev->offsets[E];
   // work items: (event, query tile), in bins of whole events balanced by attention work
   const int qt = attention_query_tile(m->cfg.precision == FMD_BF16, m->cfg.d_model / std::max(m->cfg.n_heads, 1),
                                       m->cfg.n_heads);
   std::vector<int64_t> ids((size_t)E);
   int64_t items = 0;
-  double s2 = 0;
+  double s2 = 0, sx = 0;
   for (int64_t e = 0; e < E; ++e) {
-    const int64_t n = ev->offsets[e + 1] - ev->offsets[e];
+    const int64_t n = roff[e + 1] - roff[e], nt = ev->offsets[e + 1] - ev->offsets[e];
     ids[e] = e;
     items += (n + qt - 1) / qt;
     s2 += (double)n * (double)n;
+    sx += (double)n * (double)nt;
   }
   c.items = items;
   c.sum_n2 = s2;
-  FMD_TRY(ensure_ws(m, c.T, E, items));
+  const int64_t all_items = reco_off ? 2 * items : items;
+  FMD_TRY(ensure_ws(m, std::max(c.T, Tt), E, all_items));
   // The pinned staging buffers may still feed the previous call's copies.
   HIP_TRY(hipStreamSynchronize(c.st));
-  std::memcpy(w.h_off, ev->offsets, (size_t)(E + 1) * 8);
+  std::memcpy(w.h_off, roff, (size_t)(E + 1) * 8);
   if (build_attention_work(w.h_off, w.h_off, ids.data(), E, qt, w.h_work, &c.bins) != items)
     return fail(FMD_E_INVALID, "token rows beyond 2^31");
+  same_truth(c);
+  if (reco_off) {
+    c.Tt = Tt;
+    c.Ttp = round_up(std::max<int64_t>(Tt, 1), kGemmBM);
+    c.work_x = items;
+    c.sum_nx = sx;
+    if (build_attention_work(w.h_off, ev->offsets, ids.data(), E, qt, w.h_work + items,
+                             &c.bins_x) != items)
+      return fail(FMD_E_INVALID, "token rows beyond 2^31");
+  }
   HIP_TRY(hipMemcpyAsync(w.off, w.h_off, (size_t)(E + 1) * 8, hipMemcpyHostToDevice, c.st));
-  if (items) HIP_TRY(hipMemcpyAsync(w.work, w.h_work, (size_t)items * sizeof(AttnItem), hipMemcpyHostToDevice, c.st));
+  if (all_items)
+    HIP_TRY(hipMemcpyAsync(w.work, w.h_work, (size_t)all_items * sizeof(AttnItem),
+                           hipMemcpyHostToDevice, c.st));
   FMD_TRY(timed(m, c.st, FMD_K_OTHER, 0, [&] { return launch_token_map(c.st, w.off, E, c.T, w.tok_event); }));
   if (ev->on_device) {
     c.u = ev->feat;
   } else {
-    HIP_TRY(hipMemcpyAsync(w.u, ev->feat, (size_t)c.T * 9 * 4, hipMemcpyHostToDevice, c.st));
+    HIP_TRY(hipMemcpyAsync(w.u, ev->feat, (size_t)c.Tt * 9 * 4, hipMemcpyHostToDevice, c.st));
     c.u = w.u;
   }
   return FMD_OK;
@@ -285,7 +303,7 @@ int truth_cache(fmd_model* m, Call& c) {
   const fmd_model_config& cf = m->cfg;
   const int d = cf.d_model, L = cf.n_blocks;
   FMD_TRY(timed(m, c.st, FMD_K_OTHER, 0, [&] {
-    return launch_truth_encode<T>(c.st, c.u, 9, 9, c.T, m->W_tin, m->b_tin, m->g_t, m->s_t, d,
+    return launch_truth_encode<T>(c.st, c.u, 9, 9, c.Tt, m->W_tin, m->b_tin, m->g_t, m->s_t, d,
                                   (T*)w.c, d);
   }));
   if (m->kv_hm) {
@@ -294,21 +312,21 @@ int truth_cache(fmd_model* m, Call& c) {
     const int dh = d / cf.n_heads;
     const int64_t plane = w.cap_tok;
     for (int l = 0; l < L; ++l) {
-      FMD_TRY(timed(m, c.st, FMD_K_OTHER, 2.0 * c.T * d * 2 * d, [&] {
-        return launch_gemm<T>(c.st, FMD_K_OTHER, false, EPI_STORE, c.Tp, 2 * d, d, w.c, d,
+      FMD_TRY(timed(m, c.st, FMD_K_OTHER, 2.0 * c.Tt * d * 2 * d, [&] {
+        return launch_gemm<T>(c.st, FMD_K_OTHER, false, EPI_STORE, c.Ttp, 2 * d, d, w.c, d,
                               (const T*)m->Wkv + (size_t)l * 2 * d * d, m->bkv + l * 2 * d,
                               nullptr, nullptr, nullptr, w.hid, 2 * d);
       }));
       FMD_TRY(timed(m, c.st, FMD_K_OTHER, 0, [&] {
-        return launch_kv_headmajor(c.st, w.hid, c.T, d, dh, cf.n_heads,
+        return launch_kv_headmajor(c.st, w.hid, c.Tt, d, dh, cf.n_heads,
                                    (char*)w.kv + (size_t)l * 2 * cf.n_heads * plane * dh * sizeof(T),
                                    plane, 0);
       }));
     }
     return FMD_OK;
   }
-  FMD_TRY(timed(m, c.st, FMD_K_OTHER, 2.0 * c.T * d * 2 * d * L, [&] {
-    return launch_gemm<T>(c.st, FMD_K_OTHER, false, EPI_STORE, c.Tp, 2 * d * L, d, w.c, d,
+  FMD_TRY(timed(m, c.st, FMD_K_OTHER, 2.0 * c.Tt * d * 2 * d * L, [&] {
+    return launch_gemm<T>(c.st, FMD_K_OTHER, false, EPI_STORE, c.Ttp, 2 * d * L, d, w.c, d,
                           (const T*)m->Wkv, m->bkv, nullptr, nullptr, nullptr, w.kv, 2 * d * L);
   }));
   return FMD_OK;
@@ -498,18 +516,18 @@ int net_forward(fmd_model* m, Call& c, const float* t_ev) {
                               tile_for(m, TS_PROJ_LN, c.Tp, d));
       }));
     }
-    FMD_TRY(timed(m, c.st, FMD_K_ATTN_CROSS, 4.0 * c.sum_n2 * d, Td * 4 * d * es, [&] {
+    FMD_TRY(timed(m, c.st, FMD_K_ATTN_CROSS, 4.0 * c.sum_nx * d, (Td * 2 + c.Tt * 2.0) * d * es, [&] {
       const size_t o = (size_t)l * 2 * d * es;
       // the cross query is head-major [heads][Tp][dh] when the fused kernel formed it
       const bool hm = (fz & FMD_FUSED_OQC) != 0;
       if (m->kv_hm) {   // cache planes [L][K, V][heads][cap rows][dh]
         const int64_t pl = w.cap_tok * dh;
         const char* kb = kv + (size_t)l * 2 * Hh * pl * es;
-        return launch_attention<T>(c.st, true, dh, Hh, c.items, c.bins, w.work, (const T*)w.qc,
+        return launch_attention<T>(c.st, true, dh, Hh, c.items_x, c.bins_x, w.work + c.work_x, (const T*)w.qc,
                                    hm ? dh : d, hm ? c.Tp * dh : dh, (const T*)kb,
                                    (const T*)(kb + Hh * pl * es), dh, pl, (T*)w.att, d);
       }
-      return launch_attention<T>(c.st, true, dh, Hh, c.items, c.bins, w.work, (const T*)w.qc,
+      return launch_attention<T>(c.st, true, dh, Hh, c.items_x, c.bins_x, w.work + c.work_x, (const T*)w.qc,
                                  hm ? dh : d, hm ? c.Tp * dh : dh, (const T*)(kv + o),
                                  (const T*)(kv + o + d * es), 2 * d * L, dh, (T*)w.att, d);
     }));
@@ -650,7 +668,8 @@ int run_stages(fmd_model* m, Call& c, int n_stages, float* out, int ldo) {
     for (int i = 0; i < n_stages; ++i) FMD_TRY(run_stage<T>(m, c, out, ldo));
     return FMD_OK;
   }
-  const GraphKey key{c.Tp, c.T, c.E, c.items, out, ldo, m->ws.generation, m->tune_gen, c.bins};
+  const GraphKey key{c.Tp, c.T, c.E, c.items, out, ldo, m->ws.generation, m->tune_gen, c.bins,
+                     c.items_x, c.bins_x};
   if (!m->gexec || !(key == m->gkey)) {
     if (m->gexec) (void)hipGraphExecDestroy(m->gexec);
     m->gexec = nullptr;
@@ -697,8 +716,9 @@ int leave_stream(fmd_model* m, hipStream_t caller) {
 
 template <typename T>
 int simulate_body(fmd_model* m, const fmd_events_in* truth, const float* x0, uint64_t seed,
-                  const fmd_schedule* sched, fmd_events_out* reco, Call& c) {
-  FMD_TRY(stage_events(m, truth, c));
+                  const fmd_schedule* sched, fmd_events_out* reco, Call& c,
+                  const int64_t* reco_off) {
+  FMD_TRY(stage_events(m, truth, c, reco_off));
   Workspace& w = m->ws;
   int n_stages = 0;
   FMD_TRY(upload_stages(m, c, sched, &n_stages));
@@ -727,12 +747,36 @@ int simulate_body(fmd_model* m, const fmd_events_in* truth, const float* x0, uin
   return FMD_OK;
 }
 
+// Reco multiplicities given by the caller: offsets from 0, non-decreasing, at most n_max
+// slots per event, and no reco slot in an event without truth particles (its
+// cross-attention would have no key). Sets *T_out to the number of reco slots.
+int check_reco_offsets(const fmd_model* m, const fmd_events_in* truth, const int64_t* roff,
+                       int64_t* T_out) {
+  if (!roff) return fail(FMD_E_INVALID, "null reco offsets");
+  if (roff[0] != 0) return fail(FMD_E_INVALID, "reco offsets[0] must be 0");
+  for (int64_t e = 0; e < truth->n_events; ++e) {
+    const int64_t n = roff[e + 1] - roff[e];
+    if (n < 0) return fail(FMD_E_INVALID, "reco offsets decrease at event %lld", (long long)e);
+    if (m->kind == 0 && n > m->cfg.n_max)
+      return fail(FMD_E_UNSUPPORTED, "event %lld has %lld reco slots, above n_max %d",
+                  (long long)e, (long long)n, m->cfg.n_max);
+    if (n > 0 && truth->offsets[e + 1] == truth->offsets[e])
+      return fail(FMD_E_INVALID, "event %lld has reco slots but no truth particle", (long long)e);
+  }
+  const int64_t T = roff[truth->n_events];
+  if (T > ((int64_t)1 << 31) - 4096) return fail(FMD_E_UNSUPPORTED, "too many reco slots in one call");
+  *T_out = T;
+  return FMD_OK;
+}
+
 int simulate_impl(fmd_model* m, const fmd_events_in* truth, const float* x0, uint64_t seed,
-                  const fmd_schedule* sched, fmd_events_out* reco, void* stream) {
+                  const fmd_schedule* sched, fmd_events_out* reco, void* stream,
+                  const int64_t* reco_off = nullptr) {
   if (!m) return fail(FMD_E_INVALID, "null model");
   if (m->server) return fail(FMD_E_STATE, "the model is owned by a server");
   Call c{};
   FMD_TRY(check_events(m, truth, &c.T, nullptr));
+  if (reco_off) FMD_TRY(check_reco_offsets(m, truth, reco_off, &c.T));
   FMD_TRY(check_schedule(sched));
   if (!reco) return fail(FMD_E_INVALID, "null reco output");
   if (c.T > 0 && !reco->feat) return fail(FMD_E_INVALID, "null reco feature array");
@@ -743,8 +787,8 @@ int simulate_impl(fmd_model* m, const fmd_events_in* truth, const float* x0, uin
   const hipStream_t caller = (hipStream_t)stream;
   FMD_TRY(enter_stream(m, caller, c));
   const int st = m->kind == 0 && m->cfg.precision == FMD_BF16
-                     ? simulate_body<bf16>(m, truth, x0, seed, sched, reco, c)
-                     : simulate_body<float>(m, truth, x0, seed, sched, reco, c);
+                     ? simulate_body<bf16>(m, truth, x0, seed, sched, reco, c, reco_off)
+                     : simulate_body<float>(m, truth, x0, seed, sched, reco, c, reco_off);
   const int st2 = leave_stream(m, caller);
   return st != FMD_OK ? st : st2;
 }
@@ -992,6 +1036,13 @@ int fmd_model_destroy(fmd_model* m) {
 int fmd_simulate(fmd_model* m, const fmd_events_in* truth, uint64_t seed,
                  const fmd_schedule* schedule, fmd_events_out* reco, void* hip_stream) {
   return simulate_impl(m, truth, nullptr, seed, schedule, reco, hip_stream);
+}
+
+int fmd_simulate_reco(fmd_model* m, const fmd_events_in* truth, const int64_t* reco_offsets,
+                      uint64_t seed, const fmd_schedule* schedule, fmd_events_out* reco,
+                      void* hip_stream) {
+  if (!reco_offsets) return fail(FMD_E_INVALID, "null reco offsets");
+  return simulate_impl(m, truth, nullptr, seed, schedule, reco, hip_stream, reco_offsets);
 }
 
 int fmd_simulate_from_state(fmd_model* m, const fmd_events_in* truth, const float* x0,

@@ -58,10 +58,13 @@ struct GraphKey {
   int ldo;
   uint64_t ws_gen, tune_gen;
   AttnBins bins;  // kernel arguments and grid size of the attention launches
+  int64_t items_x;
+  AttnBins bins_x;
   bool operator==(const GraphKey& o) const {
     return Tp == o.Tp && T == o.T && E == o.E && items == o.items && out == o.out &&
            ldo == o.ldo && ws_gen == o.ws_gen && tune_gen == o.tune_gen &&
-           std::memcmp(&bins, &o.bins, sizeof(AttnBins)) == 0;
+           std::memcmp(&bins, &o.bins, sizeof(AttnBins)) == 0 && items_x == o.items_x &&
+           std::memcmp(&bins_x, &o.bins_x, sizeof(AttnBins)) == 0;
   }
 };
 

@@ -98,10 +98,16 @@ int timed(fmd_model* m, hipStream_t st, int cls, double work, F&& launch) {
 // One call's (or one server iteration's) shapes and inputs on the device.
 struct Call {
   hipStream_t st;
-  int64_t E, T, Tp, items;
+  int64_t E, T, Tp, items;   // T reco slots (rows of the state and residual stream)
   AttnBins bins;        // bins of the attention work list
   double sum_n2;        // sum over events of N_e^2 (attention work)
-  const float* u;       // truth features on device [T, 9]
+  // Truth side: Tt truth particles (rows of the truth encoding and cross K/V cache) and the
+  // cross-attention work list (items_x entries from w.work + work_x, bins_x). Equal to the
+  // reco side unless the caller gave reco multiplicities (same_truth sets them so).
+  int64_t Tt, Ttp, items_x, work_x;
+  AttnBins bins_x;
+  double sum_nx;        // sum over events of N_reco N_truth
+  const float* u;       // truth features on device [Tt, 9]
   OdeArgs sargs;        // epilogue arguments of the residual GEMMs (statistics output)
   // Output head to fold into the last block's fused MLP kernel (9 features, BF16 fused
   // path); net_forward sets head_done when it did, and the caller then skips its head.
@@ -109,6 +115,16 @@ struct Call {
   bool head_done = false;
 };
 
+
+// The truth side of a call whose reco slots are its truth particles.
+inline void same_truth(Call& c) {
+  c.Tt = c.T;
+  c.Ttp = c.Tp;
+  c.items_x = c.items;
+  c.work_x = 0;
+  c.bins_x = c.bins;
+  c.sum_nx = c.sum_n2;
+}
 
 int ensure_ws(fmd_model* m, int64_t T, int64_t E, int64_t items);
 int check_events(const fmd_model* m, const fmd_events_in* ev, int64_t* T_out, int64_t* max_n);

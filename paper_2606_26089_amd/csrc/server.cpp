@@ -245,6 +245,7 @@ int iterate(fmd_server* S, std::vector<Req*>& finished) {
   c.items = items;
   c.bins = bins;
   c.sum_n2 = sum_n2;
+  same_truth(c);
   c.u = w.u;
   HIP_TRY(launch_token_map(S->st, w.off, E, span, w.tok_event));
   FMD_TRY(autotune<T>(m, c));

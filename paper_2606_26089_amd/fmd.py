@@ -91,6 +91,9 @@ def lib():
         "fmd_linear_field_create": (c_int32, [c_double, c_double, ctypes.POINTER(c_void_p)]),
         "fmd_simulate": (c_int32, [c_void_p, ctypes.POINTER(EventsIn), ctypes.c_uint64,
                                    ctypes.POINTER(Schedule), ctypes.POINTER(EventsOut), c_void_p]),
+        "fmd_simulate_reco": (c_int32, [c_void_p, ctypes.POINTER(EventsIn), P_int64,
+                                        ctypes.c_uint64, ctypes.POINTER(Schedule),
+                                        ctypes.POINTER(EventsOut), c_void_p]),
         "fmd_simulate_from_state": (c_int32, [c_void_p, ctypes.POINTER(EventsIn), c_void_p,
                                               ctypes.POINTER(Schedule), ctypes.POINTER(EventsOut),
                                               c_void_p]),
@@ -240,15 +243,29 @@ class Model:
         except Exception:
             pass
 
-    def simulate(self, offsets, feat, seed, sched, out=None, stream=None):
+    def simulate(self, offsets, feat, seed, sched, out=None, stream=None, reco_offsets=None):
+        """Reco state at t1 [T, 9]; with reco_offsets ([E + 1] host ints) the events get that
+        many reco slots each (fmd_simulate_reco) and the result is [reco_offsets[-1], 9]."""
         ev, off = _events(offsets, feat)
+        roff = None
+        if reco_offsets is not None:
+            roff = np.ascontiguousarray(np.asarray(reco_offsets, dtype=np.int64))
+            if len(roff) != len(off):
+                raise ValueError("reco_offsets needs one entry per event plus one")
+        rows = int(off[-1]) if roff is None else int(roff[-1])
         if out is None:
-            out = _like_out(feat, int(off[-1]), 9)
+            out = _like_out(feat, rows, 9)
         op, odev = _ptr(out)
         o = EventsOut(op, odev)
         s = schedule(sched)
-        _check(lib().fmd_simulate(self._h, ctypes.byref(ev), ctypes.c_uint64(seed), ctypes.byref(s),
-                                  ctypes.byref(o), _stream(stream) if ev.on_device or odev else None))
+        st = _stream(stream) if ev.on_device or odev else None
+        if roff is None:
+            _check(lib().fmd_simulate(self._h, ctypes.byref(ev), ctypes.c_uint64(seed),
+                                      ctypes.byref(s), ctypes.byref(o), st))
+        else:
+            _check(lib().fmd_simulate_reco(self._h, ctypes.byref(ev), roff.ctypes.data_as(P_int64),
+                                           ctypes.c_uint64(seed), ctypes.byref(s),
+                                           ctypes.byref(o), st))
         return out
 
     def simulate_from_state(self, offsets, feat, x0, sched, out=None, stream=None):

@@ -151,3 +151,19 @@ def test_server_argument_checks_without_a_device(fmd, field):
     assert L.fmd_server_destroy(None) == fmd.OK
     rid = ctypes.c_uint64()
     assert L.fmd_server_submit(None, None, 0, None, ctypes.byref(rid)) == fmd.E_INVALID
+
+
+@pytest.mark.parametrize("reco,msg", [([1, 2, 3], r"reco offsets\[0\]"), ([0, 3, 2], "decrease"),
+                                      ([0, 2, 3], "no truth particle")])
+def test_reco_offsets_are_validated_on_the_host(fmd, field, reco, msg):
+    feat = np.zeros((2, 9), dtype=np.float32)
+    with pytest.raises(fmd.FmdError, match=msg):
+        field.simulate([0, 2, 2], feat, 0, _sched(), reco_offsets=reco)
+
+
+def test_reco_offsets_without_slots_need_no_device(fmd, field):
+    feat = np.zeros((5, 9), dtype=np.float32)
+    out = field.simulate([0, 2, 5], feat, 0, _sched(), reco_offsets=[0, 0, 0])
+    assert out.shape == (0, 9)
+    with pytest.raises(ValueError):
+        field.simulate([0, 2, 5], feat, 0, _sched(), reco_offsets=[0, 1])
