@@ -12,6 +12,9 @@ resident in HBM when the timed region starts, and outputs stay in HBM.
   roofline         the kernel class with the largest device time, timed with HIP events
                    on its launch stream during the timed steps
   cpu_baseline     the FP64 oracle on a bounded sample of the same events, host cores
+  reco_multiplicity  the same workload with per-event reco counts differing from the truth
+                   counts (fmd_simulate_reco); truth_selection and observables: the steps
+                   before and after the sampler
 Prints one JSON line on stdout.
 """
 
@@ -120,6 +123,30 @@ def select_leg(fmd, torch, off, feat_d, cut, limit, reps):
             "max_particles": limit, "ms_per_call": round(dt * 1e3, 4),
             "events_per_s": round(E / dt, 1), "particles_in": int(off[-1]),
             "particles_out": int(o2[-1]), "calls": reps}
+
+
+def reco_leg(fmd, torch, cfg, flat, off, feat_d, w, steps):
+    """The sampler with reco multiplicities that differ from the truth multiplicities (each
+    event's count scaled by a seeded factor in [0.8, 1.3]): wall time per step on the same
+    workload, timed like the main path."""
+    n = np.diff(off)
+    f = np.random.default_rng(11).uniform(0.8, 1.3, len(n))
+    r = np.where(n > 0, np.clip(np.rint(n * f), 1, cfg.n_max), 0).astype(np.int64)
+    roff = np.r_[0, np.cumsum(r)].astype(np.int64)
+    m = fmd.Model(cfg, flat)
+    out = torch.empty((int(roff[-1]), 9), dtype=torch.float32, device="cuda")
+    m.simulate(off, feat_d, w.noise_seed, w.schedule, out=out, reco_offsets=roff)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        m.simulate(off, feat_d, w.noise_seed, w.schedule, out=out, reco_offsets=roff)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    m.close()
+    E = len(n)
+    return {"entry": "fmd_simulate_reco", "reco_slots": int(roff[-1]), "truth_particles": int(off[-1]),
+            "ms_per_step": round(dt * 1e3, 2), "events_per_s": round(E / dt, 1),
+            "reco_slots_per_s": round(int(roff[-1]) / dt, 1), "steps": steps}
 
 
 def bound_of(k, dtype):
@@ -288,6 +315,10 @@ def main():
     log(f"event observables: {obs['ms_per_call']:.3f} ms per call, {obs['events_per_s']:.0f} "
         f"events/s, {obs['cone_tests_per_s'] / 1e9:.2f} G cone tests/s")
 
+    reco = reco_leg(fmd, torch, w.model, flat, off, feat_d, w, 1)
+    log(f"reco multiplicities x[0.8, 1.3]: {reco['reco_slots']} slots for {reco['truth_particles']} "
+        f"truth particles, {reco['ms_per_step']:.1f} ms/step, {reco['events_per_s']:.1f} events/s")
+
     fp32 = None
     out32 = None
     if not a.no_fp32:
@@ -334,6 +365,7 @@ def main():
                    "tiles": kern16["_tiles"]},
         "fp32": fp32, "error": err,
         "latency": serve, "truth_selection": selection, "observables": obs,
+        "reco_multiplicity": reco,
         "roofline": rl, "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
