@@ -142,6 +142,7 @@ def test_gemm_every_tiling_matches(env, prec, M, N, K, ln, epi):
 ATTN_CASES = [  # (event sizes, heads, dh)
     ([1], 1, 16), ([2, 31, 32, 33], 4, 16), ([64, 65, 1, 127, 128, 129], 8, 32),
     ([200, 3, 150], 8, 32), ([1000], 2, 32), ([17, 70], 2, 64), ([0, 5, 0, 9], 4, 32),
+    ([95, 96, 97, 160, 161, 225, 255, 256, 257], 8, 32),     # 32-key group edges
 ]
 
 
@@ -168,19 +169,22 @@ def test_attention(env, prec, sizes, H, dh):
     assert normwise(O.cpu().numpy(), ref) < tol
 
 
-def test_cross_attention_with_different_key_sets(env):
+@pytest.mark.parametrize("prec", [0, 1])
+def test_cross_attention_with_different_key_sets(env, prec):
     torch, fmd = env
     rng = np.random.default_rng(5)
-    qo = np.array([0, 3, 50, 51], dtype=np.int64)
-    ko = np.array([0, 70, 71, 200], dtype=np.int64)
+    qo = np.array([0, 3, 50, 51, 251], dtype=np.int64)
+    ko = np.array([0, 70, 71, 200, 233], dtype=np.int64)
     H, dh = 4, 32
     d = H * dh
     Q = rng.standard_normal((qo[-1], d)).astype(np.float32)
     K = rng.standard_normal((ko[-1], d)).astype(np.float32)
     V = rng.standard_normal((ko[-1], d)).astype(np.float32)
     dev = lambda a: torch.from_numpy(a).cuda()  # noqa: E731
-    O = fmd.debug_attention(0, qo, ko, H, dh, dev(Q), dev(K), dev(V)).cpu().numpy()
-    for e in range(3):
+    O = fmd.debug_attention(prec, qo, ko, H, dh, dev(Q), dev(K), dev(V)).cpu().numpy()
+    if prec == 1:
+        Q, K, V = bf16_round(Q), bf16_round(K), bf16_round(V)
+    for e in range(4):
         ref = net.attention(Q[qo[e]:qo[e + 1]].astype(np.float64), K[ko[e]:ko[e + 1]].astype(np.float64),
                             V[ko[e]:ko[e + 1]].astype(np.float64), H)
-        assert normwise(O[qo[e]:qo[e + 1]], ref) < 2e-6
+        assert normwise(O[qo[e]:qo[e + 1]], ref) < (2e-6 if prec == 0 else 1.5e-2)
