@@ -266,10 +266,13 @@ int fmd_graphs_enable(fmd_model* m, int32_t enable);
  * hidden layer never reaches device memory. Results agree with the unfused kernels to BF16
  * rounding, not bitwise (different summation order and LayerNorm statistics computed in
  * the kernel). `mask` selects the segments that use their fused kernel (FMD_FUSED_*; the
- * others run the GEMM kernels); 0 selects the GEMM kernels throughout. A mask outside
+ * others run the GEMM kernels); 0 selects the GEMM kernels throughout. FMD_FUSED_EMBED
+ * (with FMD_FUSED_QKV) forms the input embedding inside block 0's QKV kernel instead of a
+ * kernel of its own; the embedded rows are the same either way. A mask outside
  * [0, FMD_FUSED_ALL] is FMD_E_INVALID; a nonzero mask on a model without the fused kernels
  * is FMD_E_UNSUPPORTED. */
-enum { FMD_FUSED_QKV = 1, FMD_FUSED_OQC = 2, FMD_FUSED_MLP = 4, FMD_FUSED_ALL = 7 };
+enum { FMD_FUSED_QKV = 1, FMD_FUSED_OQC = 2, FMD_FUSED_MLP = 4, FMD_FUSED_EMBED = 8,
+       FMD_FUSED_ALL = 15 };
 int fmd_fused_enable(fmd_model* m, int32_t mask);
 
 /* ---- tile autotuner ------------------------------------------------------------------- */

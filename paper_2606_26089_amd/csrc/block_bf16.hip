@@ -493,13 +493,28 @@ __device__ __forceinline__ float head_partial(const f32x16 (&y)[2][2], float w0,
 
 // ---------------------------------------------------------------------------------------
 
-template <int TM>
-__global__ __launch_bounds__(kThreads) void k_fused_qkv(const float* __restrict__ H,
+// Input embedding of block 0, formed in the QKV kernel instead of read from H, for a stage
+// whose time is the same for every row: row r is temb + sum_k xs[r][k] W_xin[k] over the 9
+// state features, in that order (the order of the embedding kernel, so the rows are the
+// same), and is stored to H. Rows at or past T (padding) are zero. (Per-event times would
+// need a time-embedding row per tile row; those calls keep the embedding kernel.)
+struct EmbedRows {
+  const float* xs;             // state rows, pitch kEmbLd floats, first 9 used
+  int64_t T;
+  const float* temb;           // [256] time embedding of the stage, b_xin included
+  const float* W;              // W_xin [9][256]
+  float* H;                    // [Mp][256] output
+};
+constexpr int kEmbLd = 16;     // pitch of the ODE state rows
+constexpr int kEmbF9 = 9;
+
+template <int TM, bool EMBED>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_fused_qkv(const float* __restrict__ H,
                                                         const float* __restrict__ g,
                                                         const float* __restrict__ s,
                                                         const u32x4* __restrict__ Wf,
                                                         const float* __restrict__ bias,
-                                                        bf16* __restrict__ qkv) {
+                                                        bf16* __restrict__ qkv, EmbedRows em) {
   constexpr int ROWS = 32 * TM;
   __shared__ __attribute__((aligned(16))) bf16 A[ROWS * kLdA];
   __shared__ SharedLn sl;
@@ -510,10 +525,37 @@ __global__ __launch_bounds__(kThreads) void k_fused_qkv(const float* __restrict_
   const int col = w * 32 + (lane & 31);
   const u32x4* wf = Wf + w * kKs * 64;            // slab s: + s * kWaves * kKs * 64
   u32x4 ring[kRing];
-  ring_fill(ring, wf, lane);
+  if constexpr (!EMBED) ring_fill(ring, wf, lane);
   f32x16 acc[TM];
-  load_rows(acc, H, m0, col, nullptr, lane);
-  row_stats(acc, sl, nullptr, m0, lane, w);
+  if constexpr (EMBED) {
+    // the tile's state rows (ROWS x 16 floats), staged in the A buffer
+    static_assert(ROWS * kEmbLd * 4 <= ROWS * kLdA * 2, "staging fits the A tile");
+    float* xt = reinterpret_cast<float*>(A);
+    for (int i = tid; i < ROWS * kEmbLd / 4; i += kThreads)
+      *(float4*)&xt[4 * i] = *(const float4*)&em.xs[m0 * kEmbLd + 4 * i];
+    __syncthreads();
+    float wv[kEmbF9];
+#pragma unroll
+    for (int k = 0; k < kEmbF9; ++k) wv[k] = em.W[k * kD + col];
+    const float t0 = em.temb[col];
+#pragma unroll
+    for (int mi = 0; mi < TM; ++mi)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = acc_row(mi, r, lane);
+        const float* x = &xt[row * kEmbLd];
+        float v = t0;
+#pragma unroll
+        for (int k = 0; k < kEmbF9; ++k) v = fmaf(x[k], wv[k], v);
+        acc[mi][r] = m0 + row < em.T ? v : 0.f;
+        asm volatile("" ::: "memory");   // a row at a time: the LDS reads are not all hoisted
+      }
+    ring_fill(ring, wf, lane);             // after the rows: fewer registers live at once
+    store_rows_f32(acc, em.H, m0, col, lane);
+  } else {
+    load_rows(acc, H, m0, col, nullptr, lane);
+  }
+  row_stats(acc, sl, nullptr, m0, lane, w);   // barriers: the staged rows are consumed
   ln_to_lds(acc, sl.mu[w], sl.rs[w], g, s, A, col, lane);
   __syncthreads();
 #pragma unroll 1
@@ -832,8 +874,22 @@ hipError_t launch_fused_qkv(hipStream_t st, int64_t Mp, const float* H, const fl
                             const float* s, const void* Wf, const float* bias, void* qkv) {
   if (Mp % (32 * kTmIo)) return hipErrorInvalidValue;
   if (Mp == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fused_qkv<kTmIo>, dim3((unsigned)(Mp / (32 * kTmIo))), dim3(kThreads), 0, st, H, g, s,
-                     (const u32x4*)Wf, bias, (bf16*)qkv);
+  hipLaunchKernelGGL((k_fused_qkv<kTmIo, false>), dim3((unsigned)(Mp / (32 * kTmIo))),
+                     dim3(kThreads), 0, st, H, g, s, (const u32x4*)Wf, bias, (bf16*)qkv,
+                     EmbedRows{});
+  return hipGetLastError();
+}
+
+hipError_t launch_fused_embed_qkv(hipStream_t st, int64_t Mp, const float* xs, int ldx, int f,
+                                  int64_t T, const float* temb, const float* W_xin, float* H,
+                                  const float* g, const float* s, const void* Wf,
+                                  const float* bias, void* qkv) {
+  if (Mp % (32 * kTmIo) || ldx != kEmbLd || f != kEmbF9 || T > Mp) return hipErrorInvalidValue;
+  if (Mp == 0) return hipSuccess;
+  const EmbedRows em{xs, T, temb, W_xin, H};
+  hipLaunchKernelGGL((k_fused_qkv<kTmIo, true>), dim3((unsigned)(Mp / (32 * kTmIo))),
+                     dim3(kThreads), 0, st, nullptr, g, s, (const u32x4*)Wf, bias, (bf16*)qkv,
+                     em);
   return hipGetLastError();
 }
 

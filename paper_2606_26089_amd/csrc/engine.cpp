@@ -392,7 +392,9 @@ hipError_t slot_gemm(fmd_model* m, Call& c, int slot, int tile, const DevBlock& 
 // later (the residual stream is rebuilt by the next input embedding).
 template <typename T>
 int autotune(fmd_model* m, Call& c) {
-  if (!m->autotune || m->kind != 0 || m->fused == FMD_FUSED_ALL) return FMD_OK;   // fixed tiling
+  const int blocks_fused = FMD_FUSED_QKV | FMD_FUSED_OQC | FMD_FUSED_MLP;
+  if (!m->autotune || m->kind != 0 || (m->fused & blocks_fused) == blocks_fused)
+    return FMD_OK;   // fixed tiling
   const int b = bucket_of(c.Tp);
   const int d = m->cfg.d_model;
   const int N[TS_COUNT] = {3 * d, d, d, 4 * d, d};
@@ -462,19 +464,29 @@ int net_forward(fmd_model* m, Call& c, const float* t_ev) {
     return launch_time_embed(c.st, t_ev, t_ev ? nullptr : w.desc, w.ctr, 0.f, t_ev ? (int)c.E : 1,
                              m->W_time, m->b_time, m->b_xin, cf.t_embed_dim, d, w.temb);
   }));
-  FMD_TRY(timed(m, c.st, FMD_K_OTHER, 0, [&] {
-    return launch_embed(c.st, w.xs, kStateLd, 9, c.T, t_ev ? w.tok_event : nullptr, w.temb,
-                        m->W_xin, d, w.H, d, w.stats);
-  }));
   // fused BF16 kernels per block segment (bit 1: LN1 + QKV; bit 2: W_o + residual + LN2 +
-  // cross query; bit 4: W_oc + residual + LN3 + MLP + residual); the GEMM kernels otherwise
+  // cross query; bit 4: W_oc + residual + LN3 + MLP + residual; bit 8 with bit 1: the input
+  // embedding formed in block 0's QKV kernel); the GEMM kernels otherwise
   const int fz = std::is_same<T, bf16>::value ? m->fused : 0;
+  // (stage times only: calls with per-event times keep the embedding kernel)
+  const bool embed_in_qkv = (fz & FMD_FUSED_QKV) && (fz & FMD_FUSED_EMBED) && !t_ev;
+  if (!embed_in_qkv)
+    FMD_TRY(timed(m, c.st, FMD_K_OTHER, 0, [&] {
+      return launch_embed(c.st, w.xs, kStateLd, 9, c.T, t_ev ? w.tok_event : nullptr, w.temb,
+                          m->W_xin, d, w.H, d, w.stats);
+    }));
   const double dd = (double)d;
   bool qkv_ready = false;   // the previous block's MLP kernel formed this block's [Q|K|V]
   for (int l = 0; l < L; ++l) {
     const DevBlock& B = m->blk[l];
     if (fz & FMD_FUSED_QKV) {
-      if (!qkv_ready)
+      if (l == 0 && embed_in_qkv)
+        FMD_TRY(timed(m, c.st, FMD_K_GEMM_QKV, 2.0 * Td * dd * 3 * dd + 2.0 * Td * 9 * dd,
+                      Td * (dd * 4 + kStateLd * 4) + (Td + dd) * 3 * dd * es, [&] {
+          return launch_fused_embed_qkv(c.st, c.Tp, w.xs, kStateLd, 9, c.T, w.temb, m->W_xin,
+                                        w.H, B.g1, B.s1, B.Fqkv, B.bqkv, w.qkv);
+        }));
+      else if (!qkv_ready)
         FMD_TRY(timed(m, c.st, FMD_K_GEMM_QKV, 2.0 * Td * dd * 3 * dd,
                       Td * dd * 4 + (Td + dd) * 3 * dd * es, [&] {
           return launch_fused_qkv(c.st, c.Tp, w.H, B.g1, B.s1, B.Fqkv, B.bqkv, w.qkv);
@@ -1275,7 +1287,8 @@ int fmd_graphs_enable(fmd_model* m, int32_t enable) {
 
 int fmd_fused_enable(fmd_model* m, int32_t mask) {
   if (!m) return fail(FMD_E_INVALID, "null model");
-  if (mask < 0 || mask > FMD_FUSED_ALL) return fail(FMD_E_INVALID, "fused mask %d not in [0, 7]", mask);
+  if (mask < 0 || mask > FMD_FUSED_ALL)
+    return fail(FMD_E_INVALID, "fused mask %d not in [0, %d]", mask, (int)FMD_FUSED_ALL);
   if (mask && !m->fused_ok)
     return fail(FMD_E_UNSUPPORTED, "no fused kernels for this configuration (BF16, d_model 256 only)");
   if (m->fused != mask) {

@@ -190,6 +190,14 @@ hipError_t launch_pack_frag(hipStream_t st, const float* W, int K, int N, void* 
 // [Q | K | V] = LN(H; g, s) Wqkv + b, head-major: qkv [3][8 heads][Mp][32] (plane = Mp x 32)
 hipError_t launch_fused_qkv(hipStream_t st, int64_t Mp, const float* H, const float* g,
                             const float* s, const void* Wf, const float* bias, void* qkv);
+// As launch_fused_qkv for block 0, with the input embedding formed in the kernel for a
+// stage time shared by every row: H rows [0, T) = temb[0..255] + xs[r][0..8] W_xin (the
+// order of launch_embed's d = 256 kernel, so H is the same; rows [T, Mp) are zero) are
+// written to H and feed LN1 + QKV. xs has pitch 16 and at least Mp rows; f must be 9.
+hipError_t launch_fused_embed_qkv(hipStream_t st, int64_t Mp, const float* xs, int ldx, int f,
+                                  int64_t T, const float* temb, const float* W_xin, float* H,
+                                  const float* g, const float* s, const void* Wf,
+                                  const float* bias, void* qkv);
 // H += att Wo + b_o;  qc = LN(H; g, s) Wqc + b_qc, head-major: qc [8 heads][Mp][32]
 hipError_t launch_fused_oqc(hipStream_t st, int64_t Mp, const void* att, const void* Wf_o,
                             const float* b_o, float* H, const float* g, const float* s,

@@ -19,7 +19,7 @@ FP32, BF16 = 0, 1
 EULER, RK4, MIDPOINT = 0, 1, 2
 (K_GEMM_QKV, K_GEMM_PROJ, K_GEMM_QC, K_GEMM_UP, K_GEMM_DOWN, K_FUSED_OQC, K_FUSED_MLP,
  K_ATTN_SELF, K_ATTN_CROSS, K_OTHER) = range(10)
-FUSED_QKV, FUSED_OQC, FUSED_MLP, FUSED_ALL = 1, 2, 4, 7
+FUSED_QKV, FUSED_OQC, FUSED_MLP, FUSED_EMBED, FUSED_ALL = 1, 2, 4, 8, 15
 KERNEL_CLASSES = ("gemm_qkv", "gemm_proj", "gemm_qc", "gemm_up", "gemm_down", "fused_oqc",
                   "fused_mlp", "attn_self", "attn_cross", "other")
 

@@ -59,6 +59,26 @@ def test_fused_velocity_matches_oracle_and_unfused(env, sizes):
     assert not np.array_equal(v_fused, v_gemm)        # the two paths really differ
 
 
+def test_embedding_in_the_qkv_kernel_changes_nothing(env):
+    """Block 0's QKV kernel forms the input embedding itself (FUSED_EMBED) in the order of
+    the embedding kernel: velocity (per-event times) and a whole integration (stage times)
+    are bitwise the same as with the embedding kernel."""
+    torch, fmd = env
+    flat = params.draw(CFG, seed=8, perturbed=True)
+    off, feat, x, t = _inputs([1, 127, 128, 129, 0, 3, 260], 40)
+    m = fmd.Model(CFG, flat)
+    args = (off, dev(torch, feat), dev(torch, x), dev(torch, t))
+    sched = configs.Schedule(configs.RK4, 2)
+    res = {}
+    for mask in (fmd.FUSED_ALL, fmd.FUSED_ALL & ~fmd.FUSED_EMBED):
+        m.fused_enable(mask)
+        res[mask] = (m.velocity(*args).cpu().numpy(),
+                     m.simulate(off, dev(torch, feat), 3, sched).cpu().numpy())
+    m.close()
+    a, b = res.values()
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
 def test_fused_integration_matches_oracle(env):
     torch, fmd = env
     flat = params.draw(CFG, seed=7, perturbed=True)
