@@ -260,6 +260,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=0, help="oracle events (0: 6 per core)")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-reco", action="store_true", help="skip the reco-multiplicity leg")
     ap.add_argument("--serve-rates", default="1000,2000,5000")
     ap.add_argument("--serve-seconds", type=float, default=4.0)
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -315,9 +316,12 @@ def main():
     log(f"event observables: {obs['ms_per_call']:.3f} ms per call, {obs['events_per_s']:.0f} "
         f"events/s, {obs['cone_tests_per_s'] / 1e9:.2f} G cone tests/s")
 
-    reco = reco_leg(fmd, torch, w.model, flat, off, feat_d, w, 1)
-    log(f"reco multiplicities x[0.8, 1.3]: {reco['reco_slots']} slots for {reco['truth_particles']} "
-        f"truth particles, {reco['ms_per_step']:.1f} ms/step, {reco['events_per_s']:.1f} events/s")
+    reco = None
+    if not a.no_reco:
+        reco = reco_leg(fmd, torch, w.model, flat, off, feat_d, w, 1)
+        log(f"reco multiplicities x[0.8, 1.3]: {reco['reco_slots']} slots for "
+            f"{reco['truth_particles']} truth particles, {reco['ms_per_step']:.1f} ms/step, "
+            f"{reco['events_per_s']:.1f} events/s")
 
     fp32 = None
     out32 = None
