@@ -119,3 +119,26 @@ def test_event_alone_equals_event_in_batch_and_layouts_alternate(env):
     fresh = m2.simulate(off, dev(torch, feat), 4, sched, reco_offsets=r2).cpu().numpy()
     m2.close()
     assert np.array_equal(other, fresh)
+
+
+def test_full_base_workload_with_scaled_reco_counts(env):
+    """All 4096 events of the base workload in one call, with per-event reco counts scaled
+    by a seeded factor in [0.8, 1.3] (the bench's reco leg), in the bench's precision and
+    schedule; sampled events against the oracle."""
+    torch, fmd = env
+    w = configs.BASE_BF16
+    off, feat = events.for_workload(w)
+    n = np.diff(off)
+    f = np.random.default_rng(11).uniform(0.8, 1.3, len(n))
+    r = np.where(n > 0, np.clip(np.rint(n * f), 1, w.model.n_max), 0).astype(np.int64)
+    roff = np.r_[0, np.cumsum(r)].astype(np.int64)
+    flat = params.draw(w.model, w.weight_seed)
+    m = fmd.Model(w.model, flat)
+    out = m.simulate(off, dev(torch, feat), w.noise_seed, w.schedule, reco_offsets=roff).cpu().numpy()
+    m.close()
+    assert out.shape == (roff[-1], 9) and np.all(np.isfinite(out))
+    ids = [0, 1777, 4095]
+    ref = sample.simulate_events(flat, w.model, off, feat, w.schedule, seed=w.noise_seed,
+                                 event_ids=ids, reco_offsets=roff)
+    got = np.concatenate([out[roff[e]:roff[e + 1]] for e in ids])
+    assert errors.normwise_rel_err(got, np.concatenate(ref)).max() < 2e-2
