@@ -353,8 +353,17 @@ int fmd_server_create(fmd_model* m, const fmd_server_config* cfg, fmd_server** o
 int fmd_server_submit(fmd_server* s, const fmd_events_in* truth, uint64_t seed,
                       const fmd_schedule* schedule, uint64_t* req_id);
 
+/* As fmd_server_submit, with per-event reco counts (host reco_offsets [n_events + 1], copied
+ * before the call returns), as fmd_simulate_reco takes them (Sec. 2.2). The request takes
+ * max(truth particles, reco slots) pool rows; its result has reco_offsets[n] rows and is
+ * bitwise the result of fmd_simulate_reco for the same request. Errors as
+ * fmd_server_submit, plus those fmd_simulate_reco gives for the reco offsets. */
+int fmd_server_submit_reco(fmd_server* s, const fmd_events_in* truth,
+                           const int64_t* reco_offsets, uint64_t seed,
+                           const fmd_schedule* schedule, uint64_t* req_id);
+
 /* FMD_PENDING while the request runs. Once it has finished, copies the result
- * ([particles, 9] FP32, host) and the timestamps, forgets the request and returns its
+ * ([reco slots, 9] FP32, host) and the timestamps, forgets the request and returns its
  * status. A request is collected once. */
 int fmd_server_poll(fmd_server* s, uint64_t req_id, float* reco_host, fmd_request_stats* st);
 int fmd_server_wait(fmd_server* s, uint64_t req_id, float* reco_host, fmd_request_stats* st);

@@ -410,16 +410,18 @@ static hipError_t go_attn(bool cross, dim3 grid, hipStream_t st, const T* Q, int
   return hipGetLastError();
 }
 
-int64_t build_attention_work(const int64_t* q_off, const int64_t* kv_off, const int64_t* ids,
-                             int64_t n, int qt, AttnItem* items, AttnBins* bins) {
+namespace {
+// The builder over accessors: queries of event k at q_off[ids[k]], nq(k) rows; its keys at
+// k0(k), nk(k) rows.
+template <typename Nq, typename K0, typename Nk>
+int64_t build_work(const int64_t* q_off, const int64_t* ids, int64_t n, int qt, Nq nq, K0 k0,
+                   Nk nk, AttnItem* items, AttnBins* bins) {
   // longest-processing-time assignment of whole events to bins; cost = query tiles x keys
-  auto nq = [&](int64_t k) { return q_off[ids[k] + 1] - q_off[ids[k]]; };
-  auto nk = [&](int64_t k) { return kv_off[ids[k] + 1] - kv_off[ids[k]]; };
   std::vector<int64_t> order;
   order.reserve((size_t)n);
   for (int64_t k = 0; k < n; ++k) {
     if (nq(k) <= 0) continue;
-    if (q_off[ids[k] + 1] > INT32_MAX || kv_off[ids[k] + 1] > INT32_MAX) return -1;
+    if (q_off[ids[k]] + nq(k) > INT32_MAX || k0(k) + nk(k) > INT32_MAX) return -1;
     order.push_back(k);
   }
   auto tiles = [&](int64_t k) { return (nq(k) + qt - 1) / qt; };
@@ -448,10 +450,28 @@ int64_t build_attention_work(const int64_t* q_off, const int64_t* kv_off, const 
       for (int64_t q = 0; q < tiles(k); ++q)
         items[pos++] = AttnItem{(int32_t)(q_off[e] + q * qt),
                                 (int32_t)std::min<int64_t>(qt, nq(k) - q * qt),
-                                (int32_t)kv_off[e], (int32_t)nk(k)};
+                                (int32_t)k0(k), (int32_t)nk(k)};
     }
   }
   return pos;
+}
+}  // namespace
+
+int64_t build_attention_work(const int64_t* q_off, const int64_t* kv_off, const int64_t* ids,
+                             int64_t n, int qt, AttnItem* items, AttnBins* bins) {
+  return build_work(
+      q_off, ids, n, qt, [&](int64_t k) { return q_off[ids[k] + 1] - q_off[ids[k]]; },
+      [&](int64_t k) { return kv_off[ids[k]]; },
+      [&](int64_t k) { return kv_off[ids[k] + 1] - kv_off[ids[k]]; }, items, bins);
+}
+
+int64_t build_attention_work_kv(const int64_t* q_off, const int64_t* kv_start,
+                                const int64_t* kv_len, const int64_t* ids, int64_t n, int qt,
+                                AttnItem* items, AttnBins* bins) {
+  return build_work(
+      q_off, ids, n, qt, [&](int64_t k) { return q_off[ids[k] + 1] - q_off[ids[k]]; },
+      [&](int64_t k) { return kv_start[ids[k]]; }, [&](int64_t k) { return kv_len[ids[k]]; },
+      items, bins);
 }
 
 int attention_query_tile(bool bf16, int dh, int n_heads) {

@@ -128,6 +128,8 @@ inline void same_truth(Call& c) {
 
 int ensure_ws(fmd_model* m, int64_t T, int64_t E, int64_t items);
 int check_events(const fmd_model* m, const fmd_events_in* ev, int64_t* T_out, int64_t* max_n);
+int check_reco_offsets(const fmd_model* m, const fmd_events_in* truth, const int64_t* roff,
+                       int64_t* T_out);
 int check_schedule(const fmd_schedule* s);
 int stages_per_step(int scheme);
 StageDesc stage_desc(const fmd_schedule& s, int i);

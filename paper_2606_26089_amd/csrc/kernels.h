@@ -104,6 +104,11 @@ struct AttnItem {
 // without queries get no item. Returns the item count, or -1 if a row index exceeds 2^31-1.
 int64_t build_attention_work(const int64_t* q_off, const int64_t* kv_off, const int64_t* ids,
                              int64_t n, int qt, AttnItem* items, AttnBins* bins);
+// As build_attention_work, with the keys of event e at rows kv_start[e] .. + kv_len[e] (for
+// key sets that are not one CSR sequence, e.g. truth rows of pooled requests).
+int64_t build_attention_work_kv(const int64_t* q_off, const int64_t* kv_start,
+                                const int64_t* kv_len, const int64_t* ids, int64_t n, int qt,
+                                AttnItem* items, AttnBins* bins);
 
 // Masked multi-head attention over ragged events, one work item per (event, query tile).
 // Element (row, head, dim) of Q sits at Q[row * ldq + head * hsq + dim], of K / V at

@@ -2,11 +2,12 @@
 //
 // Requests (a set of truth events, a seed and a schedule) arrive at any time. A worker
 // thread runs the device loop:
-//   admission  FIFO; a request is admitted when a contiguous range of its token count is
-//              free in the device token pool, whose size is the HBM budget divided by the
-//              per-token footprint. Admission draws the request's noise, encodes its truth
-//              particles and fills its cross-attention K/V cache, all in its pool range.
-//              These stay resident until the request completes.
+//   admission  FIFO; a request is admitted when a contiguous range of max(truth particles,
+//              reco slots) rows is free in the device token pool, whose size is the HBM
+//              budget divided by the per-token footprint. Admission draws the noise of its
+//              reco slots, encodes its truth particles and fills its cross-attention K/V
+//              cache, all in its pool range (reco slot rows and truth rows both count from
+//              the range start). These stay resident until the request completes.
 //   iteration  one velocity evaluation over the pool prefix that holds resident events.
 //              Every event carries its own stage-table entry (time, step, Euler/RK4 stage),
 //              so requests with different schedules and at different points of their
@@ -45,14 +46,16 @@ uint64_t now_ns() {
 
 struct Req {
   uint64_t id = 0;
-  std::vector<int64_t> off;     // [n + 1]
+  std::vector<int64_t> off;     // [n + 1] truth offsets
+  std::vector<int64_t> roff;    // [n + 1] reco offsets (equal to off unless given)
   std::vector<float> feat;      // [T, 9]
   uint64_t seed = 0;
   fmd_schedule sched{};
-  int64_t T = 0, base = -1;     // token count and pool row of its first particle
+  int64_t T = 0, Tr = 0;        // truth particles, reco slots
+  int64_t rows = 0, base = -1;  // pool rows max(T, Tr) and the first of them
   int64_t n_events = 0;
   int stage = 0, n_stages = 0;  // all events of a request advance together
-  std::vector<float> out;       // [T, 9] result
+  std::vector<float> out;       // [Tr, 9] result
   fmd_request_stats stats{};
   int status = FMD_PENDING;
   std::string error;
@@ -139,20 +142,22 @@ int admit_device(fmd_server* S, Req* r) {
   fmd_model* m = S->m;
   Workspace& w = m->ws;
   const int d = m->cfg.d_model, L = m->cfg.n_blocks;
-  const int64_t E = r->n_events, nT = r->T, b = r->base;
+  const int64_t E = r->n_events, nT = r->T, nR = r->Tr, b = r->base;
   if (E + 1 > S->adm_cap_ev) {
     FMD_TRY(grow(S->adm_off, (size_t)(E + 1) * 8));
     S->adm_cap_ev = E + 1;
   }
-  if (nT > S->adm_cap_tok) {
-    FMD_TRY(grow(S->adm_tok, (size_t)nT * 4));
-    S->adm_cap_tok = nT;
+  if (nR > S->adm_cap_tok) {
+    FMD_TRY(grow(S->adm_tok, (size_t)nR * 4));
+    S->adm_cap_tok = nR;
   }
-  HIP_TRY(hipMemcpyAsync(S->adm_off, r->off.data(), (size_t)(E + 1) * 8, hipMemcpyHostToDevice, S->st));
-  HIP_TRY(hipMemcpyAsync(w.u + b * 9, r->feat.data(), (size_t)nT * 9 * 4, hipMemcpyHostToDevice, S->st));
-  HIP_TRY(launch_token_map(S->st, S->adm_off, E, nT, S->adm_tok));
-  HIP_TRY(launch_noise(S->st, r->seed, S->adm_off, S->adm_tok, nT, 9, w.x + b * kStateLd,
+  // noise of the reco slots, keyed by (seed, event, slot)
+  HIP_TRY(hipMemcpyAsync(S->adm_off, r->roff.data(), (size_t)(E + 1) * 8, hipMemcpyHostToDevice, S->st));
+  HIP_TRY(launch_token_map(S->st, S->adm_off, E, nR, S->adm_tok));
+  HIP_TRY(launch_noise(S->st, r->seed, S->adm_off, S->adm_tok, nR, 9, w.x + b * kStateLd,
                        w.xs + b * kStateLd, kStateLd));
+  if (nT == 0) return FMD_OK;
+  HIP_TRY(hipMemcpyAsync(w.u + b * 9, r->feat.data(), (size_t)nT * 9 * 4, hipMemcpyHostToDevice, S->st));
   const size_t es = sizeof(T);
   T* cb = (T*)w.c + b * d;
   HIP_TRY(launch_truth_encode<T>(S->st, w.u + b * 9, 9, 9, nT, m->W_tin, m->b_tin, m->g_t, m->s_t,
@@ -191,38 +196,47 @@ int iterate(fmd_server* S, std::vector<Req*>& finished) {
   std::vector<StageDesc> desc;
   std::vector<float> tev;
   std::vector<std::pair<int64_t, int64_t>> real;   // (segment index, length)
-  double sum_n2 = 0;
+  std::vector<int64_t> kv0, kvn;                   // per segment: first truth row, count
+  double sum_n2 = 0, sum_nx = 0;
   int64_t pos = 0, items = 0;
   for (Req* r : res) {
     if (r->base > pos) {
       off.push_back(r->base);
       desc.push_back(StageDesc{0.f, 0.f, UPD_NONE, 0});
       tev.push_back(0.f);
+      kv0.push_back(0);
+      kvn.push_back(0);
       pos = r->base;
     }
     const StageDesc sd = stage_desc(r->sched, r->stage);
     for (int64_t e = 0; e < r->n_events; ++e) {
-      const int64_t n = r->off[e + 1] - r->off[e];
+      const int64_t n = r->roff[e + 1] - r->roff[e], nt = r->off[e + 1] - r->off[e];
       if (n == 0) continue;
       real.emplace_back((int64_t)desc.size(), n);
+      kv0.push_back(r->base + r->off[e]);
+      kvn.push_back(nt);
       off.push_back(pos + n);
       desc.push_back(sd);
       tev.push_back(sd.t);
       pos += n;
       items += (n + qt - 1) / qt;
       sum_n2 += (double)n * (double)n;
+      sum_nx += (double)n * (double)nt;
     }
   }
   const int64_t E = (int64_t)desc.size(), span = pos;
   if (span == 0) return FMD_OK;
-  FMD_TRY(ensure_ws(m, span, E, items));
+  // self-attention items, then cross-attention items (reco queries, truth keys)
+  FMD_TRY(ensure_ws(m, span, E, 2 * items));
   std::memcpy(w.h_off, off.data(), (size_t)(E + 1) * 8);
-  AttnBins bins{};
+  AttnBins bins{}, bins_x{};
   {
     std::vector<int64_t> ids(real.size());
     for (size_t i = 0; i < real.size(); ++i) ids[i] = real[i].first;
     if (build_attention_work(off.data(), off.data(), ids.data(), (int64_t)real.size(), qt, w.h_work,
-                             &bins) != items)
+                             &bins) != items ||
+        build_attention_work_kv(off.data(), kv0.data(), kvn.data(), ids.data(),
+                                (int64_t)real.size(), qt, w.h_work + items, &bins_x) != items)
       return fail(FMD_E_INVALID, "token rows beyond 2^31");
   }
   if (E > w.cap_desc) {
@@ -233,7 +247,7 @@ int iterate(fmd_server* S, std::vector<Req*>& finished) {
   }
   std::memcpy(w.h_desc, desc.data(), (size_t)E * sizeof(StageDesc));
   HIP_TRY(hipMemcpyAsync(w.off, w.h_off, (size_t)(E + 1) * 8, hipMemcpyHostToDevice, S->st));
-  HIP_TRY(hipMemcpyAsync(w.work, w.h_work, (size_t)items * sizeof(AttnItem), hipMemcpyHostToDevice, S->st));
+  HIP_TRY(hipMemcpyAsync(w.work, w.h_work, (size_t)(2 * items) * sizeof(AttnItem), hipMemcpyHostToDevice, S->st));
   HIP_TRY(hipMemcpyAsync(w.desc, w.h_desc, (size_t)E * sizeof(StageDesc), hipMemcpyHostToDevice, S->st));
   HIP_TRY(hipMemcpyAsync(w.tev, tev.data(), (size_t)E * 4, hipMemcpyHostToDevice, S->st));
 
@@ -246,6 +260,10 @@ int iterate(fmd_server* S, std::vector<Req*>& finished) {
   c.bins = bins;
   c.sum_n2 = sum_n2;
   same_truth(c);
+  c.items_x = items;
+  c.work_x = items;
+  c.bins_x = bins_x;
+  c.sum_nx = sum_nx;
   c.u = w.u;
   HIP_TRY(launch_token_map(S->st, w.off, E, span, w.tok_event));
   FMD_TRY(autotune<T>(m, c));
@@ -265,7 +283,7 @@ int iterate(fmd_server* S, std::vector<Req*>& finished) {
   }
   for (Req* r : res)
     if (r->stage == r->n_stages - 1) {
-      HIP_TRY(hipMemcpyAsync(r->out.data(), w.io + r->base * 9, (size_t)r->T * 9 * 4,
+      HIP_TRY(hipMemcpyAsync(r->out.data(), w.io + r->base * 9, (size_t)r->Tr * 9 * 4,
                              hipMemcpyDeviceToHost, S->st));
       finished.push_back(r);
     }
@@ -308,15 +326,15 @@ void worker_main(fmd_server* S) {
         Req* r = S->queue.front();
         if (S->cfg.max_requests > 0 && (int64_t)S->resident.size() >= S->cfg.max_requests) break;
         if (S->cfg.max_tokens_per_iter > 0 && !S->resident.empty() &&
-            S->resident_tokens + r->T > S->cfg.max_tokens_per_iter)
+            S->resident_tokens + r->rows > S->cfg.max_tokens_per_iter)
           break;
-        const int64_t b = S->pool.alloc(std::max<int64_t>(r->T, 1));
+        const int64_t b = S->pool.alloc(std::max<int64_t>(r->rows, 1));
         if (b < 0) break;
         S->queue.pop_front();
         r->base = b;
         r->stats.t_admit_ns = now_ns();
         S->resident.push_back(r);
-        S->resident_tokens += r->T;
+        S->resident_tokens += r->rows;
         admitted.push_back(r);
       }
     }
@@ -338,8 +356,8 @@ void worker_main(fmd_server* S) {
     for (Req* r : finished) {
       r->status = FMD_OK;
       r->stats.t_done_ns = t;
-      S->pool.release(r->base, std::max<int64_t>(r->T, 1));
-      S->resident_tokens -= r->T;
+      S->pool.release(r->base, std::max<int64_t>(r->rows, 1));
+      S->resident_tokens -= r->rows;
       S->resident.erase(std::find(S->resident.begin(), S->resident.end(), r));
     }
     if (!finished.empty()) S->cv_done.notify_all();
@@ -350,7 +368,7 @@ void worker_main(fmd_server* S) {
 int collect(fmd_server* S, Req* r, float* reco, fmd_request_stats* stats) {
   const int status = r->status;
   if (stats) *stats = r->stats;
-  if (status == FMD_OK && reco && r->T) std::memcpy(reco, r->out.data(), (size_t)r->T * 9 * 4);
+  if (status == FMD_OK && reco && r->Tr) std::memcpy(reco, r->out.data(), (size_t)r->Tr * 9 * 4);
   const std::string err = r->error;
   S->reqs.erase(r->id);
   delete r;
@@ -392,27 +410,37 @@ int fmd_server_create(fmd_model* m, const fmd_server_config* cfg, fmd_server** o
   return FMD_OK;
 }
 
-int fmd_server_submit(fmd_server* S, const fmd_events_in* truth, uint64_t seed,
-                      const fmd_schedule* sched, uint64_t* req_id) {
+namespace {
+int submit(fmd_server* S, const fmd_events_in* truth, const int64_t* reco_offsets, uint64_t seed,
+           const fmd_schedule* sched, uint64_t* req_id) {
   if (!S || !req_id) return fail(FMD_E_INVALID, "null argument");
-  int64_t T = 0;
+  int64_t T = 0, Tr = 0;
   FMD_TRY(check_events(S->m, truth, &T, nullptr));
+  Tr = T;
+  if (reco_offsets) FMD_TRY(check_reco_offsets(S->m, truth, reco_offsets, &Tr));
   FMD_TRY(check_schedule(sched));
   if (truth->on_device) return fail(FMD_E_INVALID, "the server takes host event arrays");
-  if (T > S->pool_tokens)
-    return fail(FMD_E_BUDGET, "request of %lld particles exceeds the pool of %lld", (long long)T,
+  const int64_t rows = std::max(T, Tr);
+  if (rows > S->pool_tokens)
+    return fail(FMD_E_BUDGET, "request of %lld rows exceeds the pool of %lld", (long long)rows,
                 (long long)S->pool_tokens);
-  if (S->cfg.max_tokens_per_iter > 0 && T > S->cfg.max_tokens_per_iter)
-    return fail(FMD_E_BUDGET, "request of %lld particles exceeds max_tokens_per_iter", (long long)T);
+  if (S->cfg.max_tokens_per_iter > 0 && rows > S->cfg.max_tokens_per_iter)
+    return fail(FMD_E_BUDGET, "request of %lld rows exceeds max_tokens_per_iter", (long long)rows);
   Req* r = new Req();
   r->off.assign(truth->offsets, truth->offsets + truth->n_events + 1);
+  if (reco_offsets)
+    r->roff.assign(reco_offsets, reco_offsets + truth->n_events + 1);
+  else
+    r->roff = r->off;
   r->feat.assign(truth->feat, truth->feat + T * 9);
   r->seed = seed;
   r->sched = *sched;
   r->T = T;
+  r->Tr = Tr;
+  r->rows = rows;
   r->n_events = truth->n_events;
   r->n_stages = sched->n_steps * stages_per_step(sched->scheme);
-  r->out.assign((size_t)T * 9, 0.f);
+  r->out.assign((size_t)Tr * 9, 0.f);
   r->stats.t_submit_ns = now_ns();
   std::lock_guard<std::mutex> lk(S->mu);
   if (S->dead != FMD_OK || S->stop) {
@@ -421,7 +449,7 @@ int fmd_server_submit(fmd_server* S, const fmd_events_in* truth, uint64_t seed,
   }
   r->id = S->next_id++;
   S->reqs[r->id] = r;
-  if (T == 0) {        // nothing to integrate
+  if (Tr == 0) {       // nothing to integrate
     r->status = FMD_OK;
     r->stats.t_admit_ns = r->stats.t_done_ns = r->stats.t_submit_ns;
   } else {
@@ -430,6 +458,19 @@ int fmd_server_submit(fmd_server* S, const fmd_events_in* truth, uint64_t seed,
   }
   *req_id = r->id;
   return FMD_OK;
+}
+}  // namespace
+
+int fmd_server_submit(fmd_server* S, const fmd_events_in* truth, uint64_t seed,
+                      const fmd_schedule* sched, uint64_t* req_id) {
+  return submit(S, truth, nullptr, seed, sched, req_id);
+}
+
+int fmd_server_submit_reco(fmd_server* S, const fmd_events_in* truth,
+                           const int64_t* reco_offsets, uint64_t seed,
+                           const fmd_schedule* sched, uint64_t* req_id) {
+  if (!reco_offsets) return fail(FMD_E_INVALID, "null reco offsets");
+  return submit(S, truth, reco_offsets, seed, sched, req_id);
 }
 
 int fmd_server_poll(fmd_server* S, uint64_t req_id, float* reco, fmd_request_stats* stats) {

@@ -120,6 +120,9 @@ def lib():
         "fmd_server_create": (c_int32, [c_void_p, ctypes.POINTER(ServerConfig), ctypes.POINTER(c_void_p)]),
         "fmd_server_submit": (c_int32, [c_void_p, ctypes.POINTER(EventsIn), ctypes.c_uint64,
                                         ctypes.POINTER(Schedule), ctypes.POINTER(ctypes.c_uint64)]),
+        "fmd_server_submit_reco": (c_int32, [c_void_p, ctypes.POINTER(EventsIn), P_int64,
+                                             ctypes.c_uint64, ctypes.POINTER(Schedule),
+                                             ctypes.POINTER(ctypes.c_uint64)]),
         "fmd_server_poll": (c_int32, [c_void_p, ctypes.c_uint64, c_void_p, ctypes.POINTER(RequestStats)]),
         "fmd_server_wait": (c_int32, [c_void_p, ctypes.c_uint64, c_void_p, ctypes.POINTER(RequestStats)]),
         "fmd_server_get_info": (c_int32, [c_void_p, ctypes.POINTER(ServerInfo)]),
@@ -336,15 +339,28 @@ class Server:
         self.model = model
         self._sizes = {}
 
-    def submit(self, offsets, feat, seed, sched):
+    def submit(self, offsets, feat, seed, sched, reco_offsets=None):
+        """Queues a request; with reco_offsets ([E + 1] ints) its events get that many reco
+        slots each (fmd_server_submit_reco)."""
         feat = np.ascontiguousarray(np.asarray(feat, dtype=np.float32))
         ev, off = _events(offsets, feat)
         s = schedule(sched)
         rid = ctypes.c_uint64()
         # the library copies the request before returning
-        _check(lib().fmd_server_submit(self._h, ctypes.byref(ev), ctypes.c_uint64(seed),
-                                       ctypes.byref(s), ctypes.byref(rid)))
-        self._sizes[rid.value] = int(off[-1])
+        if reco_offsets is None:
+            rows = int(off[-1])
+            _check(lib().fmd_server_submit(self._h, ctypes.byref(ev), ctypes.c_uint64(seed),
+                                           ctypes.byref(s), ctypes.byref(rid)))
+        else:
+            roff = np.ascontiguousarray(np.asarray(reco_offsets, dtype=np.int64))
+            if len(roff) != len(off):
+                raise ValueError("reco_offsets needs one entry per event plus one")
+            rows = int(roff[-1])
+            _check(lib().fmd_server_submit_reco(self._h, ctypes.byref(ev),
+                                                roff.ctypes.data_as(P_int64),
+                                                ctypes.c_uint64(seed), ctypes.byref(s),
+                                                ctypes.byref(rid)))
+        self._sizes[rid.value] = rows
         return rid.value
 
     def _collect(self, fn, rid):

@@ -57,6 +57,39 @@ def test_mix_equals_alone_bitwise(env, precision):
     m.close()
 
 
+def _reco_offsets(off, seed):
+    """Per-event reco counts from 0 to 2x the truth count (none where there is no truth)."""
+    n = np.diff(off)
+    r = np.random.default_rng(seed).integers(0, 2 * n + 1)
+    r = np.minimum(r, 64)
+    return np.r_[0, np.cumsum(np.where(n > 0, r, 0))].astype(np.int64)
+
+
+@pytest.mark.parametrize("cfg", [CFG, configs.BASE_MODEL.with_precision(configs.BF16)],
+                         ids=["small-fp32", "base-bf16"])
+def test_reco_counts_in_the_mix_equal_alone_bitwise(env, cfg):
+    """Requests with reco counts that differ from their truth counts (more, fewer, none),
+    mixed with plain requests: each equals fmd_simulate_reco / fmd_simulate alone."""
+    torch, fmd = env
+    flat = params.draw(cfg, 11, perturbed=True)
+    reqs = _requests(8, seed=5)
+    roffs = [_reco_offsets(off, 50 + i) if i % 4 != 3 else None
+             for i, (off, _, _, _) in enumerate(reqs)]
+    m = fmd.Model(cfg, flat)
+    alone = [m.simulate(off, feat, seed, sched, reco_offsets=ro)
+             for (off, feat, seed, sched), ro in zip(reqs, roffs)]
+    srv = fmd.Server(m, hbm_budget_bytes=512 << 20)
+    ids = [srv.submit(off, feat, seed, sched, reco_offsets=ro)
+           for (off, feat, seed, sched), ro in zip(reqs, roffs)]
+    for rid, ref, ro in zip(ids, alone, roffs):
+        out, _ = srv.wait(rid)
+        assert out.shape == ref.shape and np.array_equal(out, ref)
+    srv.close()
+    m.close()
+    assert any(ro is not None and ro[-1] > off[-1] for ro, (off, *_) in zip(roffs, reqs))
+    assert any(ro is not None and ro[-1] < off[-1] for ro, (off, *_) in zip(roffs, reqs))
+
+
 @pytest.mark.parametrize("cfg", [configs.ModelCfg(d_model=64, n_blocks=2, n_heads=2, n_max=64),
                                  configs.BASE_MODEL],
                          ids=["d64-heads32", "base-fused"])
