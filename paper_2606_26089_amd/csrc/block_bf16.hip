@@ -130,7 +130,7 @@ __device__ __forceinline__ void zero(f32x16 (&acc)[TM], const float* __restrict_
 }
 
 // ROWS x 256 BF16 tile of S (pitch lds_) at rows m0.. into LDS (pitch kLdA).
-template <int ROWS, int NT = kThreads>
+template <int ROWS, int NT = kThreads, bool STREAM = false>
 __device__ __forceinline__ void tile_to_lds(bf16* __restrict__ A, const bf16* __restrict__ S,
                                             int lds_, int64_t m0, int tid) {
   constexpr int kChunks = ROWS * kD / 8;                // 16-byte chunks
@@ -139,8 +139,10 @@ __device__ __forceinline__ void tile_to_lds(bf16* __restrict__ A, const bf16* __
 #pragma unroll
   for (int i = 0; i < kPer; ++i) {
     const int idx = tid + i * NT;
-    v[i] = *(const u32x4*)((const char*)(S + m0 * lds_) +
-                           (uint32_t)(((idx / (kD / 8)) * lds_ + (idx % (kD / 8)) * 8) * 2));
+    const u32x4* src = (const u32x4*)((const char*)(S + m0 * lds_) +
+                                      (uint32_t)(((idx / (kD / 8)) * lds_ + (idx % (kD / 8)) * 8) * 2));
+    if constexpr (STREAM) v[i] = __builtin_nontemporal_load(src);
+    else v[i] = *src;
   }
 #pragma unroll
   for (int i = 0; i < kPer; ++i) {
@@ -653,7 +655,7 @@ __global__ __launch_bounds__(kThreads4) __attribute__((amdgpu_waves_per_eu(2))) 
   auto dn_c = [&](int c) { return Wf_dn + 2 * w * kDnStride + c * kDnKs * 64; };
   u32x4 ring[kRing];
   ring_fill_nc<2>(ring, woc, kOcStride, lane);
-  tile_to_lds<ROWS, kThreads4>(A, att, kD, m0, tid);
+  tile_to_lds<ROWS, kThreads4, true>(A, att, kD, m0, tid);
   f32x16 acc[TM][2];
 #pragma unroll
   for (int nj = 0; nj < 2; ++nj) {
@@ -662,7 +664,7 @@ __global__ __launch_bounds__(kThreads4) __attribute__((amdgpu_waves_per_eu(2))) 
 #pragma unroll
     for (int mi = 0; mi < TM; ++mi)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) acc[mi][nj][r] = *io.at(mi, r) + bv;
+      for (int r = 0; r < 16; ++r) acc[mi][nj][r] = __builtin_nontemporal_load(io.at(mi, r)) + bv;
   }
   __syncthreads();
   mfma_phase_nc<TM, 2, kKs, 1, false>(acc, A, kLdA, 0, ring, woc, kOcStride, woc, 0, lane);
@@ -736,7 +738,7 @@ __global__ __launch_bounds__(kThreads4) __attribute__((amdgpu_waves_per_eu(2))) 
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         acc[mi][nj][r] += bv;
-        if constexpr (TAIL != kTailHead) *io.at(mi, r) = acc[mi][nj][r];
+        if constexpr (TAIL != kTailHead) __builtin_nontemporal_store(acc[mi][nj][r], io.at(mi, r));
       }
   }
   if constexpr (TAIL == kTailStats) {
@@ -834,7 +836,7 @@ __global__ __launch_bounds__(kThreads4) __attribute__((amdgpu_waves_per_eu(2))) 
 #pragma unroll
         for (int mi = 0; mi < TM; ++mi)
 #pragma unroll
-          for (int r = 0; r < 16; ++r) *io.at(mi, r) = (bf16)acc[mi][nj][r];
+          for (int r = 0; r < 16; ++r) __builtin_nontemporal_store((bf16)acc[mi][nj][r], io.at(mi, r));
       }
     }
   }
