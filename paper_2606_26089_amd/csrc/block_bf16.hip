@@ -107,6 +107,10 @@ struct RowIo {
   }
 };
 
+// Every row and tile transfer of these kernels is a non-temporal load or store: the rows
+// stream through once, and kept in L2 they would evict the weight fragments that every
+// workgroup re-reads.
+//
 // acc = rows m0.. of X (FP32, pitch kD) at the wave's columns, plus bias (may be null).
 template <int TM>
 __device__ __forceinline__ void load_rows(f32x16 (&acc)[TM], const float* __restrict__ X,
@@ -117,7 +121,7 @@ __device__ __forceinline__ void load_rows(f32x16 (&acc)[TM], const float* __rest
 #pragma unroll
   for (int mi = 0; mi < TM; ++mi)
 #pragma unroll
-    for (int r = 0; r < 16; ++r) acc[mi][r] = *io.at(mi, r) + bv;
+    for (int r = 0; r < 16; ++r) acc[mi][r] = __builtin_nontemporal_load(io.at(mi, r)) + bv;
 }
 
 template <int TM>
@@ -130,7 +134,7 @@ __device__ __forceinline__ void zero(f32x16 (&acc)[TM], const float* __restrict_
 }
 
 // ROWS x 256 BF16 tile of S (pitch lds_) at rows m0.. into LDS (pitch kLdA).
-template <int ROWS, int NT = kThreads, bool STREAM = false>
+template <int ROWS, int NT = kThreads>
 __device__ __forceinline__ void tile_to_lds(bf16* __restrict__ A, const bf16* __restrict__ S,
                                             int lds_, int64_t m0, int tid) {
   constexpr int kChunks = ROWS * kD / 8;                // 16-byte chunks
@@ -141,8 +145,7 @@ __device__ __forceinline__ void tile_to_lds(bf16* __restrict__ A, const bf16* __
     const int idx = tid + i * NT;
     const u32x4* src = (const u32x4*)((const char*)(S + m0 * lds_) +
                                       (uint32_t)(((idx / (kD / 8)) * lds_ + (idx % (kD / 8)) * 8) * 2));
-    if constexpr (STREAM) v[i] = __builtin_nontemporal_load(src);
-    else v[i] = *src;
+    v[i] = __builtin_nontemporal_load(src);
   }
 #pragma unroll
   for (int i = 0; i < kPer; ++i) {
@@ -294,7 +297,7 @@ __device__ __forceinline__ void store_rows_f32(const f32x16 (&acc)[TM], float* _
 #pragma unroll
   for (int mi = 0; mi < TM; ++mi)
 #pragma unroll
-    for (int r = 0; r < 16; ++r) *io.at(mi, r) = acc[mi][r];
+    for (int r = 0; r < 16; ++r) __builtin_nontemporal_store(acc[mi][r], io.at(mi, r));
 }
 
 template <int LD, int TM>
@@ -304,7 +307,7 @@ __device__ __forceinline__ void store_rows_bf16(const f32x16 (&acc)[TM], bf16* _
 #pragma unroll
   for (int mi = 0; mi < TM; ++mi)
 #pragma unroll
-    for (int r = 0; r < 16; ++r) *io.at(mi, r) = (bf16)acc[mi][r];
+    for (int r = 0; r < 16; ++r) __builtin_nontemporal_store((bf16)acc[mi][r], io.at(mi, r));
 }
 
 // GELU(z) = z/2 (1 + erf(z / sqrt 2)) with erf by Abramowitz & Stegun 7.1.25:
@@ -655,7 +658,7 @@ __global__ __launch_bounds__(kThreads4) __attribute__((amdgpu_waves_per_eu(2))) 
   auto dn_c = [&](int c) { return Wf_dn + 2 * w * kDnStride + c * kDnKs * 64; };
   u32x4 ring[kRing];
   ring_fill_nc<2>(ring, woc, kOcStride, lane);
-  tile_to_lds<ROWS, kThreads4, true>(A, att, kD, m0, tid);
+  tile_to_lds<ROWS, kThreads4>(A, att, kD, m0, tid);
   f32x16 acc[TM][2];
 #pragma unroll
   for (int nj = 0; nj < 2; ++nj) {
