@@ -32,6 +32,11 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 PEAK_TFLOPS = {"bf16": 2500.0, "fp32": 157.3}    # MI355X dense matrix peaks
+WORKLOAD_TEXT = {
+    "base": "4096 events, N~U{20..200}, d=256, 6 blocks, 8 heads, RK4 16 steps (64 evaluations)",
+    "batch": "65536 events, N~lognormal(median 60, sigma 0.8) in [1, 1000], d=256, 6 blocks, "
+             "8 heads, RK4 16 steps (64 evaluations)",
+}
 PEAK_HBM_GBS = 8000.0
 # HBM bytes per launch measured with rocprofv3 byte counters (FETCH_SIZE, WRITE_SIZE), scaled
 # by the counts of a 1 GiB copy; valid while the kernel's source is unchanged
@@ -166,7 +171,7 @@ def bound_of(k, dtype):
         else "mfma"
 
 
-def roofline(kern, dtype):
+def roofline(kern, dtype, traffic_known=True):
     gemm_attn = {k: v for k, v in kern.items() if not k.startswith("_") and k != "other"
                  and v["launches"]}
     name, k = max(gemm_attn.items(), key=lambda kv: kv[1]["ms"])
@@ -179,7 +184,7 @@ def roofline(kern, dtype):
         achieved, peak, unit = nbytes / avg_s / 1e9, PEAK_HBM_GBS, "GB/s"
     else:
         achieved, peak, unit = flops / avg_s / 1e12, PEAK_TFLOPS[dtype], "TFLOP/s"
-    traffic = measured_traffic(k["kernel"]) if dtype == "bf16" else None
+    traffic = measured_traffic(k["kernel"]) if dtype == "bf16" and traffic_known else None
     return {"bound": bound, "achieved": round(achieved, 2), "peak": peak, "unit": unit,
             "frac": round(achieved / peak, 4), "traffic": traffic, "kernel": k["kernel"],
             "class": name, "avg_launch_ms": round(k["ms"] / k["launches"], 4),
@@ -273,6 +278,9 @@ def main():
     ap.add_argument("--no-reco", action="store_true", help="skip the reco-multiplicity leg")
     ap.add_argument("--serve-rates", default="1000,2000,5000")
     ap.add_argument("--serve-seconds", type=float, default=4.0)
+    ap.add_argument("--workload", choices=["base", "batch"], default="base",
+                    help="base: 4096 events, N~U{20..200} (the headline); batch: 65,536 events "
+                         "with heavy-tailed N (FP32, reco and serving legs skipped)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run a plain device-to-device copy of this many MiB three times "
                          "(reference kernel of known traffic for HBM byte counters)")
@@ -298,6 +306,9 @@ def main():
         del src, dst
 
     w = configs.BASE_BF16
+    if a.workload == "batch":
+        w = configs.BATCH_BF16
+        a.no_fp32 = a.no_reco = a.no_serve = True
     off, feat = events.for_workload(w)
     T = int(off[-1])
     E = len(off) - 1
@@ -319,7 +330,7 @@ def main():
         log(f"  {name:11s} {k['kernel']:14s} {k['ms'] / a.steps:9.1f} ms/step  {k['launches'] // a.steps:5d} "
             f"launches/step  {k['work'] / max(k['ms'], 1e-9) / 1e9:8.1f} TFLOP/s "
             f"{k['bytes'] / max(k['ms'], 1e-9) / 1e6:8.1f} GB/s  ({bound_of(k, 'bf16')}-bound)")
-    rl = roofline(kern16, "bf16")
+    rl = roofline(kern16, "bf16", traffic_known=a.workload == "base")
     log(f"dominant kernel {rl['kernel']}: {rl['achieved']} {rl['unit']} ({rl['frac']:.3f} of peak), "
         f"HBM traffic {rl['traffic']} bytes/launch (algorithmic {rl['bytes_per_launch']:.0f})")
 
@@ -377,8 +388,7 @@ def main():
         "warmup": a.warmup, "ms_per_step": round(dt16 / a.steps * 1e3, 2),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
         "data": "synthetic (seeded truth events and stand-in weights)",
-        "config": {"workload": "4096 events, N~U{20..200}, d=256, 6 blocks, 8 heads, "
-                               "RK4 16 steps (64 evaluations)", "events": E, "particles": T,
+        "config": {"workload": WORKLOAD_TEXT[a.workload], "events": E, "particles": T,
                    "precision": "bf16 operands, fp32 accumulation and state",
                    "tiles": kern16["_tiles"]},
         "graph_replay": graph, "fp32": fp32, "error": err,
