@@ -382,8 +382,7 @@ def main():
         serve = serve_leg(fmd, ws, flat, rates, a.serve_seconds, ws.extra["hbm_budget_bytes"])
 
     line = {
-        "metric": "sampled events/s (BF16 path; FP32 plain path and errors vs the FP64 oracle "
-                  "alongside; p50/p99 event latency from the serving loop)",
+        "metric": "sampled events/s, BF16 vs FP32 plain at stated error; p50/p99 event latency",
         "value": round(ev16, 2), "unit": "events/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": round(dt16 / a.steps * 1e3, 2),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
