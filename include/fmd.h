@@ -154,19 +154,25 @@ int fmd_simulate_reco(fmd_model* m, const fmd_events_in* truth, const int64_t* r
                       void* hip_stream);
 
 /* As fmd_simulate, but starts from a given state x0 [offsets[n], f_reco] FP32. x0 lives
- * where truth->feat lives (on_device). */
+ * where truth->feat lives (on_device). Passage: Sec. 2.2 (the sampler integrates the learned
+ * vector field from a starting sample; here the caller supplies that sample instead of the
+ * seeded noise, which lets tests pin the integrator against closed forms). */
 int fmd_simulate_from_state(fmd_model* m, const fmd_events_in* truth, const float* x0,
                             const fmd_schedule* schedule, fmd_events_out* reco,
                             void* hip_stream);
 
 /* One evaluation of the velocity field: v = v(x, t_e | truth). x and v are
  * [offsets[n], f_reco] FP32. t_per_event is [n_events] FP32. All three live where
- * truth->feat lives. */
+ * truth->feat lives. Passage: Sec. 2.2 (the learned vector field over the reco set,
+ * conditioned on the event's truth particles, at continuous time t). */
 int fmd_velocity(fmd_model* m, const fmd_events_in* truth, const float* x,
                  const float* t_per_event, float* v, void* hip_stream);
 
 /* The initial noise alone: x0 [offsets[n_events], n_feat] FP32 in DEVICE memory, with
- * n_feat <= 12 and the law of fmd_simulate. */
+ * n_feat <= 12 and the law of fmd_simulate. Passage: Sec. 2.2 (flow-matching samples start
+ * from Gaussian noise); the counter-based law is this library's reading. The call ends with
+ * the stream synchronized. Errors: FMD_E_INVALID (bad offsets, n_feat), FMD_E_NOMEM,
+ * FMD_E_DEVICE. */
 int fmd_noise(uint64_t seed, const int64_t* offsets, int64_t n_events, int32_t n_feat,
               float* x0_device, void* hip_stream);
 
@@ -208,7 +214,9 @@ int fmd_truth_select(const fmd_events_in* truth, double pt_cut_gev, int32_t max_
  * [n_events] (device); lengths are clamped to [0, n_max]. The call writes offsets_out
  * int64[n_events + 1] (device, exclusive prefix sum of the lengths) and feat_out
  * [sum(lengths), f] (device, rows of each event in order). Pad rows are never read.
- * The capacity of feat_out is n_events * n_max rows. */
+ * The capacity of feat_out is n_events * n_max rows. Passage: none in the paper's method
+ * (a data-layout helper: the paper batches a fixed number of events padded to the model's
+ * particle limit, App. C batch_size; this library works on packed CSR sets instead). */
 int fmd_pack_padded(const float* padded, const int32_t* lengths, int64_t n_events,
                     int32_t n_max, int32_t f, int64_t* offsets_out, float* feat_out,
                     void* hip_stream);

@@ -551,7 +551,7 @@ int net_forward(fmd_model* m, Call& c, const float* t_ev) {
       const bool fold = l + 1 == L && c.head && c.head->nf == 9;
       const double Tv = (double)c.T;
       FMD_TRY(timed(m, c.st, FMD_K_FUSED_MLP,
-                    2.0 * Td * dd * dd * (chain ? 15 : 9) + (fold ? 2.0 * Tv * dd * 9 : 0.0),
+                    2.0 * Td * dd * dd * (chain ? 12 : 9) + (fold ? 2.0 * Tv * dd * 9 : 0.0),
                     Td * (dd * (es + (fold ? 4 : 8)) + (fold ? 0 : 8)) + 9 * dd * dd * es +
                         (chain ? Td * 3 * dd * es + 3 * dd * dd * es : 0.0) +
                         (fold ? Tv * 9 * 4 * 5 : 0.0), [&] {
@@ -680,8 +680,8 @@ int run_stages(fmd_model* m, Call& c, int n_stages, float* out, int ldo) {
     for (int i = 0; i < n_stages; ++i) FMD_TRY(run_stage<T>(m, c, out, ldo));
     return FMD_OK;
   }
-  const GraphKey key{c.Tp, c.T, c.E, c.items, out, ldo, m->ws.generation, m->tune_gen, c.bins,
-                     c.items_x, c.bins_x};
+  const GraphKey key{c.Tp,   c.T,       c.E,    c.items,  out,      ldo, m->ws.generation,
+                     m->tune_gen, c.bins, c.items_x, c.work_x, c.bins_x, c.Tt};
   if (!m->gexec || !(key == m->gkey)) {
     if (m->gexec) (void)hipGraphExecDestroy(m->gexec);
     m->gexec = nullptr;
@@ -889,7 +889,8 @@ int fmd_model_create(const fmd_model_config* cfg, const float* params, size_t n_
   if (grow(m->bkv, (size_t)(L * 2 * d) * 4) != FMD_OK) return bail(FMD_E_NOMEM);
   if (grow(m->Wout_pk, (size_t)64 * d * 4) != FMD_OK) return bail(FMD_E_NOMEM);
   if (grow(m->bout_pk, (size_t)64 * 4) != FMD_OK) return bail(FMD_E_NOMEM);
-  m->fused_ok = cfg->precision == FMD_BF16 && fused_supported(cfg->d_model, cfg->mlp_ratio);
+  m->fused_ok = cfg->precision == FMD_BF16 &&
+                fused_supported(cfg->d_model, cfg->n_heads, cfg->mlp_ratio);
   m->kv_hm = cfg->precision == FMD_BF16 && cfg->d_model == 32 * cfg->n_heads;
   m->fused = m->fused_ok ? FMD_FUSED_ALL : 0;
   if (m->fused_ok && grow(m->frag, (size_t)(L * blk_elems) * 2) != FMD_OK) return bail(FMD_E_NOMEM);

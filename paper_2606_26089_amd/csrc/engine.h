@@ -58,13 +58,15 @@ struct GraphKey {
   int ldo;
   uint64_t ws_gen, tune_gen;
   AttnBins bins;  // kernel arguments and grid size of the attention launches
-  int64_t items_x;
+  int64_t items_x, work_x;   // cross-attention list: size and offset in the work buffer
   AttnBins bins_x;
+  int64_t Tt;                // truth rows (the reco side may differ in size)
   bool operator==(const GraphKey& o) const {
     return Tp == o.Tp && T == o.T && E == o.E && items == o.items && out == o.out &&
            ldo == o.ldo && ws_gen == o.ws_gen && tune_gen == o.tune_gen &&
            std::memcmp(&bins, &o.bins, sizeof(AttnBins)) == 0 && items_x == o.items_x &&
-           std::memcmp(&bins_x, &o.bins_x, sizeof(AttnBins)) == 0;
+           work_x == o.work_x && std::memcmp(&bins_x, &o.bins_x, sizeof(AttnBins)) == 0 &&
+           Tt == o.Tt;
   }
 };
 

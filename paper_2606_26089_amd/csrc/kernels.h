@@ -187,9 +187,10 @@ hipError_t launch_linear_update(hipStream_t st, float alpha, float beta, const S
 template <typename T>
 hipError_t launch_pack_weight(hipStream_t st, const float* W, int K, int N, T* Wt);
 
-// Fused BF16 block kernels for d = 256 and a 4x MLP (block_bf16.hip). Row counts Mp are
+// Fused BF16 block kernels for d = 256 with 8 heads of 32 and a 4x MLP (block_bf16.hip):
+// their Q/K/V and cross-query stores are 8 head-major planes of width 32. Row counts Mp are
 // multiples of 128; weights are in the fragment layout of launch_pack_frag.
-bool fused_supported(int d_model, int mlp_ratio);
+bool fused_supported(int d_model, int n_heads, int mlp_ratio);
 // W: FP32 K x N (y = x W) -> BF16 MFMA B fragments [N/32][K/16][64 lanes][8].
 hipError_t launch_pack_frag(hipStream_t st, const float* W, int K, int N, void* Wf);
 // [Q | K | V] = LN(H; g, s) Wqkv + b, head-major: qkv [3][8 heads][Mp][32] (plane = Mp x 32)

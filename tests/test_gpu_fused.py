@@ -163,3 +163,30 @@ def test_graph_recaptured_when_only_event_lengths_change(env):
     m.close()
     for eager, graph in outs.values():
         assert np.array_equal(eager, graph)
+
+
+@pytest.mark.parametrize("heads", [4, 16])
+def test_bf16_width_256_with_other_head_counts_runs_unfused(env, heads):
+    """The fused kernels write 8 head-major planes of width 32, so a BF16 d = 256 model with
+    4 or 16 heads must take the GEMM path (and say so) and still match the oracle."""
+    torch, fmd = env
+    cfg = dataclasses.replace(CFG, n_heads=heads)
+    flat = params.draw(cfg, seed=8, perturbed=True)
+    off, feat, x, t = _inputs([40, 0, 130, 7], 70 + heads)
+    m = fmd.Model(cfg, flat)
+    with pytest.raises(fmd.FmdError):
+        m.fused_enable(True)
+    m.timing_enable(True)
+    v = m.velocity(off, dev(torch, feat), dev(torch, x), dev(torch, t)).cpu().numpy()
+    sched = configs.Schedule(configs.RK4, 2)
+    out = m.simulate(off, dev(torch, feat), 3, sched).cpu().numpy()
+    fused_launches = m.timing_read(fmd.K_FUSED_MLP)[1] + m.timing_read(fmd.K_FUSED_OQC)[1]
+    gemm_launches = m.timing_read(fmd.K_GEMM_UP)[1]
+    m.close()
+    assert fused_launches == 0 and gemm_launches > 0
+    P = net.unpack(flat, cfg)
+    ref = np.concatenate([net.velocity(P, feat[off[e]:off[e + 1]], x[off[e]:off[e + 1]], float(t[e]))
+                          for e in range(4) if off[e + 1] > off[e]])
+    assert errors.normwise_rel_err(v, ref).max() < 2e-2
+    ref_s = sample.simulate(flat, cfg, off, feat, sched, seed=3)
+    assert errors.normwise_rel_err(out, ref_s).max() < 2e-2

@@ -142,3 +142,35 @@ def test_full_base_workload_with_scaled_reco_counts(env):
                                  event_ids=ids, reco_offsets=roff)
     got = np.concatenate([out[roff[e]:roff[e + 1]] for e in ids])
     assert errors.normwise_rel_err(got, np.concatenate(ref)).max() < 2e-2
+
+
+@pytest.mark.parametrize("precision", [configs.FP32, configs.BF16])
+def test_plain_and_reco_calls_alternate_on_one_output_buffer(env, precision):
+    """A reco call (50 truth particles, 30 reco slots) and a plain call (30 particles) have
+    the same reco-side shapes, so only the cross-attention work list tells their stage
+    graphs apart. Alternating them on one model and one output buffer must give each call
+    the result a fresh model gives."""
+    torch, fmd = env
+    cfg = configs.BASE_MODEL.with_precision(precision)
+    flat = params.draw(cfg, seed=4)
+    off50, f50 = _events_with_counts([50], 45)
+    off30 = np.array([0, 30], np.int64)
+    f30 = f50[:30].copy()
+    roff = np.array([0, 30], np.int64)
+    sched = configs.Schedule(configs.EULER, 2)
+    out = torch.empty((30, 9), dtype=torch.float32, device="cuda")
+
+    def fresh(o, f, r):
+        m2 = fmd.Model(cfg, flat)
+        y = m2.simulate(o, dev(torch, f), 6, sched, reco_offsets=r).cpu().numpy()
+        m2.close()
+        return y
+
+    want_reco, want_plain = fresh(off50, f50, roff), fresh(off30, f30, None)
+    assert not np.array_equal(want_reco, want_plain)
+    m = fmd.Model(cfg, flat)
+    for _ in range(2):
+        a = m.simulate(off50, dev(torch, f50), 6, sched, out=out, reco_offsets=roff).cpu().numpy()
+        b = m.simulate(off30, dev(torch, f30), 6, sched, out=out).cpu().numpy()
+        assert np.array_equal(a, want_reco) and np.array_equal(b, want_plain)
+    m.close()
