@@ -210,6 +210,20 @@ int fmd_event_observables(const fmd_events_in* reco, float* ht, float* met, floa
 int fmd_truth_select(const fmd_events_in* truth, double pt_cut_gev, int32_t max_particles,
                      int64_t* offsets_out, float* feat_out, void* hip_stream);
 
+/* As fmd_truth_select, for callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc): no device or pinned memory
+ * is allocated. Every intermediate buffer (device offsets, per-event counts, keep flags) lives
+ * in one fixed device array of the library, 9.5 MiB per GPU, held from the first call on a
+ * device until the process ends. Limits: n_events <= 65536 and offsets[n_events] <= 8388608
+ * (2^23) particles, else FMD_E_UNSUPPORTED; truth->feat and feat_out must be DEVICE memory
+ * (truth->on_device = 1), else FMD_E_INVALID. Results are those of fmd_truth_select bit for
+ * bit; offsets_out is a HOST array [n_events + 1], written; the call returns after the
+ * results are complete. All calls on one GPU share its array: calls from different host
+ * threads are serialized by the library, but work of one call that overlaps another's on the
+ * same GPU (for instance replays of captured work on several streams) races on it. */
+int fmd_truth_select_noalloc(const fmd_events_in* truth, double pt_cut_gev, int32_t max_particles,
+                             int64_t* offsets_out, float* feat_out, void* hip_stream);
+
 /* Ragged packing. `padded` is [n_events, n_max, f] FP32 (device), lengths is int32
  * [n_events] (device); lengths are clamped to [0, n_max]. The call writes offsets_out
  * int64[n_events + 1] (device, exclusive prefix sum of the lengths) and feat_out

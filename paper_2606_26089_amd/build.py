@@ -18,7 +18,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libfmdet.so")
 
 SOURCES = ["gemm_bf16.hip", "gemm_f32.hip", "kernels_misc.hip", "gemm.hip", "attention.hip", "block_bf16.hip",
-           "engine.cpp", "server.cpp"]
+           "engine.cpp", "server.cpp", "select_noalloc.hip"]
 HEADERS = ["common.h", "kernels.h", "engine.h", "engine_impl.h", "gemm_body.h", "gemm_inst.h",
            os.path.join("..", "..", "include", "fmd.h")]
 

@@ -104,6 +104,8 @@ def lib():
                                             c_void_p]),
         "fmd_truth_select": (c_int32, [ctypes.POINTER(EventsIn), ctypes.c_double, c_int32, P_int64,
                                        c_void_p, c_void_p]),
+        "fmd_truth_select_noalloc": (c_int32, [ctypes.POINTER(EventsIn), ctypes.c_double, c_int32,
+                                               P_int64, c_void_p, c_void_p]),
         "fmd_debug_philox": (c_int32, [ctypes.c_uint64, ctypes.c_uint64, c_void_p, c_int64,
                                        c_void_p, c_void_p]),
         "fmd_pack_padded": (c_int32, [c_void_p, c_void_p, c_int64, c_int32, c_int32, c_void_p,
@@ -447,6 +449,18 @@ def truth_select(offsets, feat, pt_cut_gev, max_particles, stream=None):
         op = c_void_p(out.ctypes.data)
     _check(lib().fmd_truth_select(ctypes.byref(ev), float(pt_cut_gev), int(max_particles),
                                   out_off.ctypes.data_as(P_int64), op, _stream(stream)))
+    return out_off, out[: int(out_off[-1])]
+
+
+def truth_select_noalloc(offsets, feat, pt_cut_gev, max_particles, out, stream=None):
+    """As truth_select for device data, through the entry point that allocates no device
+    memory: feat [T, 9] and out (capacity T rows) are caller-owned device tensors. Returns
+    (offsets_out [E+1] int64 NumPy, out[:offsets_out[-1]])."""
+    ev, off = _events(offsets, feat)
+    out_off = np.zeros(len(off), dtype=np.int64)
+    _check(lib().fmd_truth_select_noalloc(ctypes.byref(ev), float(pt_cut_gev), int(max_particles),
+                                          out_off.ctypes.data_as(P_int64), c_void_p(out.data_ptr()),
+                                          _stream(stream)))
     return out_off, out[: int(out_off[-1])]
 
 
