@@ -153,6 +153,31 @@ int fmd_simulate_reco(fmd_model* m, const fmd_events_in* truth, const int64_t* r
                       uint64_t seed, const fmd_schedule* schedule, fmd_events_out* reco,
                       void* hip_stream);
 
+/* Reco multiplicities drawn on the device before sampling, for fmd_simulate_reco. The paper's
+ * model can emit particles that correspond to no truth particle (pile-up-like "fake"
+ * particles it generates implicitly, Sec. 2.2 and the configuration appendix on pile-up) but
+ * does not say how their number is drawn; this is a stand-in law. For event e (index within
+ * the call) with N truth particles: N_reco = min(n_max, N - lost + fakes) if N > 0, else 0,
+ * where lost counts the truth particles missed (each with probability loss_prob) and fakes
+ * the successes of fake_trials Bernoulli trials of probability fake_prob. Every trial
+ * compares one 64-bit word of Philox4x64-10 (key (seed, 1), counters (c, e, 0, 0), four words
+ * per counter: the N loss words first, then the fake words) with floor(prob 2^64), so the
+ * counts are exact integers, independent of the other events of the call and of the slot
+ * noise (key (seed, 0)).
+ * truth_offsets: HOST int64 [n_events + 1], offsets[0] = 0, nondecreasing. reco_offsets_out:
+ * HOST int64 [n_events + 1], written (reco_offsets_out[0] = 0). Returns after the results are
+ * complete. Errors: FMD_E_INVALID (null pointers, bad offsets, probabilities outside [0, 1),
+ * fake_trials outside [0, 4096], n_max < 0), FMD_E_NOMEM, FMD_E_DEVICE. */
+typedef struct {
+  double loss_prob;      /* probability that a truth particle gets no reco slot, [0, 1) */
+  double fake_prob;      /* success probability of each fake trial, [0, 1) */
+  int32_t fake_trials;   /* Bernoulli trials for extra slots, [0, 4096] */
+} fmd_multiplicity_law;
+
+int fmd_reco_multiplicity(const int64_t* truth_offsets, int64_t n_events, uint64_t seed,
+                          const fmd_multiplicity_law* law, int32_t n_max, int64_t* reco_offsets_out,
+                          void* hip_stream);
+
 /* As fmd_simulate, but starts from a given state x0 [offsets[n], f_reco] FP32. x0 lives
  * where truth->feat lives (on_device). Passage: Sec. 2.2 (the sampler integrates the learned
  * vector field from a starting sample; here the caller supplies that sample instead of the
@@ -306,6 +331,18 @@ int fmd_fused_enable(fmd_model* m, int32_t mask);
  * keeps the fastest. Tilings differ only in speed: every tiling produces bitwise-identical
  * results. */
 int fmd_autotune_enable(fmd_model* m, int32_t enable);
+
+/* On the fused BF16 path (d = 256, heads of 32) the autotuner also chooses, per token bucket,
+ * the attention query tile (work items of 64 or 128 queries of one event and head) and the
+ * row tile of block 0's fused QKV kernel and of the OQC kernel (64 or 128 rows). These too
+ * change only the speed: every candidate gives bitwise-identical results.
+ * fmd_tuning_set fixes the choice of one of these sites for the padded token counts in
+ * [2^tokens_log2, 2^(tokens_log2 + 1)) (rows padded to a multiple of 256), e.g. to reuse a
+ * table measured earlier or to compare candidates; candidate indexes are 0 (64) and 1 (128).
+ * Errors: FMD_E_INVALID for a null model, another site, a bucket outside [0, 40) or a
+ * candidate the model's kernels do not offer. */
+enum { FMD_TUNE_ATTN_QUERY_TILE = 5, FMD_TUNE_FUSED_QKV = 6, FMD_TUNE_FUSED_OQC = 7 };
+int fmd_tuning_set(fmd_model* m, int32_t site, int32_t tokens_log2, int32_t candidate);
 
 /* The chosen tilings as a JSON object (site, log2 token bucket, tile id and shape, measured
  * microseconds). Writes at most cap bytes including the terminator; *needed receives

@@ -240,10 +240,11 @@ __device__ __forceinline__ int vt_pos(int k) {
 }
 }  // namespace
 
+template <int TPW>
 __device__ __forceinline__ void attention32_body(
     const bf16* __restrict__ Q, int ldq, int64_t hsq, const bf16* __restrict__ Kp,
     const bf16* __restrict__ Vp, int ldkv, int64_t hskv, bf16* __restrict__ O, int ldo,
-    const AttnItem* __restrict__ work, const AttnBins& bins, int n_heads, float sl2e) {
+    int64_t hso, const AttnItem* __restrict__ work, const AttnBins& bins, int n_heads, float sl2e) {
   __shared__ __attribute__((aligned(16))) bf16 Ks[kKc2 * kLdK32];
   // V^T rows 0-31; row 32 = key validity (1 for a key of the event, 0 past its end), rows
   // 33-47 = 0: the A operand of the row-sum block of P V
@@ -260,21 +261,24 @@ __device__ __forceinline__ void attention32_body(
   const int h = k % n_heads;
   const int64_t qs0 = wk.q0, ks0 = wk.k0;
   const int nq = wk.nq, nk = wk.nk;
-  const int qbase = wave * 16;
-  const bool wave_active = qbase < nq;
-  const int qi = qbase + j;
+  // query tile t of this wave (16 queries): tiles are dealt to the waves round-robin
+  auto qbase = [&](int t) { return (t * 4 + wave) * 16; };
 
-  bf16x8 qf;
-  {
+  bf16x8 qf[TPW];
+  float m_run[TPW];
+  // o[t][0], o[t][1]: output dims 0-15, 16-31; o[t][2] row 0 (lanes 0-15, register 0): sum of P
+  f32x4 o[TPW][3];
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) {
+    const int qi = qbase(t) + j;
     const char* qc = (const char*)(Q + qs0 * ldq + h * hsq);
     u32x4 v = *(const u32x4*)(qc + (uint32_t)((min(qi, nq - 1) * ldq + 8 * g) * 2));
     if (qi >= nq) v = u32x4{0u, 0u, 0u, 0u};
-    qf = __builtin_bit_cast(bf16x8, v);
+    qf[t] = __builtin_bit_cast(bf16x8, v);
+    m_run[t] = -INFINITY;
+#pragma unroll
+    for (int db = 0; db < 3; ++db) o[t][db] = f32x4{0.f, 0.f, 0.f, 0.f};
   }
-  float m_run = -INFINITY;
-  // o[0], o[1]: output dims 0-15, 16-31; o[2] row 0 (lanes 0-15, register 0): sum of P
-  f32x4 o[3] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f},
-                f32x4{0.f, 0.f, 0.f, 0.f}};
 
   for (int c0 = 0; c0 < nk; c0 += kKc2) {
     // Keys past the event end are read clamped to its last key: their scores repeat a real
@@ -321,14 +325,16 @@ __device__ __forceinline__ void attention32_body(
       }
     }
     __syncthreads();
-    if (wave_active) {
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+      if (qbase(t) >= nq) continue;   // wave-uniform
       // all 8 key blocks, also past the event end: no branches, and the zero accumulator
       // is an inline constant
       f32x4 s[8];
 #pragma unroll
       for (int kb = 0; kb < 8; ++kb) {
         const bf16x8 kf = *(const bf16x8*)&Ks[(kb * 16 + j) * kLdK32 + 8 * g];
-        s[kb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kf, qf, f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+        s[kb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kf, qf[t], f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
       }
       float cmax = -INFINITY;
 #pragma unroll
@@ -337,16 +343,16 @@ __device__ __forceinline__ void attention32_body(
         for (int r = 0; r < 4; ++r) cmax = fmaxf(cmax, s[kb][r]);
       cmax = fmaxf(cmax, __shfl_xor(cmax, 16, kWave));
       cmax = fmaxf(cmax, __shfl_xor(cmax, 32, kWave));
-      const float m_new = fmaxf(m_run, cmax);       // finite: key c0 < nk is in this chunk
-      const float alpha = __builtin_amdgcn_exp2f((m_run - m_new) * sl2e);
+      const float m_new = fmaxf(m_run[t], cmax);    // finite: key c0 < nk is in this chunk
+      const float alpha = __builtin_amdgcn_exp2f((m_run[t] - m_new) * sl2e);
 #pragma unroll
-      for (int db = 0; db < 3; ++db) o[db] *= alpha;
+      for (int db = 0; db < 3; ++db) o[t][db] *= alpha;
       const float mb = -m_new * sl2e;
 #pragma unroll
       for (int kb = 0; kb < 8; ++kb)
 #pragma unroll
         for (int r = 0; r < 4; ++r) s[kb][r] = __builtin_amdgcn_exp2f(fmaf(s[kb][r], sl2e, mb));
-      m_run = m_new;
+      m_run[t] = m_new;
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         bf16x8 pb;
@@ -358,44 +364,50 @@ __device__ __forceinline__ void attention32_body(
 #pragma unroll
         for (int db = 0; db < 2; ++db) {
           const bf16x8 vf = *(const bf16x8*)&Vt[(db * 16 + j) * kLdV32 + 32 * c + 8 * g];
-          o[db] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vf, pb, o[db], 0, 0, 0);
+          o[t][db] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vf, pb, o[t][db], 0, 0, 0);
         }
         const bf16x8 vld = *(const bf16x8*)&Vt[(kH32 + j) * kLdV32 + 32 * c + 8 * g];
-        o[2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vld, pb, o[2], 0, 0, 0);
+        o[t][2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vld, pb, o[t][2], 0, 0, 0);
       }
     }
     __syncthreads();
   }
 
-  if (wave_active) {
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) {
+    const int qi = qbase(t) + j;
+    if (qbase(t) >= nq) continue;
     // row 0 of the row-sum block sits in register 0 of lanes 0-15 (query j)
-    const float l = __shfl(o[2][0], j, kWave);
+    const float l = __shfl(o[t][2][0], j, kWave);
     const float inv = 1.0f / l;
     if (qi < nq) {
-      bf16* orow = O + (qs0 + qi) * ldo + h * kH32;
+      bf16* orow = O + (qs0 + qi) * ldo + h * hso;
 #pragma unroll
       for (int db = 0; db < 2; ++db) {
         bf16x4 w4;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) w4[r] = (bf16)(o[db][r] * inv);
+        for (int r = 0; r < 4; ++r) w4[r] = (bf16)(o[t][db][r] * inv);
         *(bf16x4*)(orow + db * 16 + 4 * g) = w4;
       }
     }
   }
 }
 
+template <int TPW>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_attn32_self(
     const bf16* __restrict__ Q, int ldq, int64_t hsq, const bf16* __restrict__ K,
     const bf16* __restrict__ V, int ldkv, int64_t hskv, bf16* __restrict__ O, int ldo,
-    const AttnItem* __restrict__ work, AttnBins bins, int n_heads, float sl2e) {
-  attention32_body(Q, ldq, hsq, K, V, ldkv, hskv, O, ldo, work, bins, n_heads, sl2e);
+    int64_t hso, const AttnItem* __restrict__ work, AttnBins bins, int n_heads, float sl2e) {
+  attention32_body<TPW>(Q, ldq, hsq, K, V, ldkv, hskv, O, ldo, hso, work, bins, n_heads, sl2e);
 }
+template <int TPW>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_attn32_cross(
     const bf16* __restrict__ Q, int ldq, int64_t hsq, const bf16* __restrict__ K,
     const bf16* __restrict__ V, int ldkv, int64_t hskv, bf16* __restrict__ O, int ldo,
-    const AttnItem* __restrict__ work, AttnBins bins, int n_heads, float sl2e) {
-  attention32_body(Q, ldq, hsq, K, V, ldkv, hskv, O, ldo, work, bins, n_heads, sl2e);
+    int64_t hso, const AttnItem* __restrict__ work, AttnBins bins, int n_heads, float sl2e) {
+  attention32_body<TPW>(Q, ldq, hsq, K, V, ldkv, hskv, O, ldo, hso, work, bins, n_heads, sl2e);
 }
+
 
 template <typename T, int DH>
 static hipError_t go_attn(bool cross, dim3 grid, hipStream_t st, const T* Q, int ldq,
@@ -475,39 +487,58 @@ int64_t build_attention_work_kv(const int64_t* q_off, const int64_t* kv_start,
 }
 
 int attention_query_tile(bool bf16, int dh, int n_heads) {
-  (void)bf16;
-  (void)dh;
   (void)n_heads;
-  return QT;
+  return bf16 && dh == kH32 ? 128 : QT;
+}
+
+int attention_query_tiles(bool bf16, int dh, int* tiles) {
+  if (bf16 && dh == kH32) {
+    tiles[0] = 64;    // one 16-query tile per wave
+    tiles[1] = 128;   // two
+    return 2;
+  }
+  tiles[0] = QT;
+  return 1;
 }
 
 template <typename T>
-hipError_t launch_attention(hipStream_t st, bool cross, int dh, int n_heads, int64_t n_items,
-                            const AttnBins& bins, const AttnItem* work, const T* Q, int ldq,
+hipError_t launch_attention(hipStream_t st, bool cross, int dh, int n_heads, int qt,
+                            int64_t n_items, const AttnBins& bins, const AttnItem* work, const T* Q, int ldq,
                             int64_t hsq, const T* K, const T* V, int ldkv, int64_t hskv, T* O,
-                            int ldo) {
+                            int ldo, int64_t hso) {
   if (n_items <= 0) return hipSuccess;
   if (n_items > 0x7fffffff) return hipErrorInvalidValue;
   const float sl2e = 1.4426950408889634f / sqrtf((float)dh);
   if constexpr (std::is_same<T, bf16>::value) {
     if (dh == kH32) {
       // 16-byte row chunks: row pitches and head offsets are multiples of 8 elements
-      if (ldq % 8 || ldkv % 8 || ldo % 8 || hsq % 8 || hskv % 8 || hsq < dh || hskv < dh)
+      if (ldq % 8 || ldkv % 8 || ldo % 4 || hsq % 8 || hskv % 8 || hso % 4 || hsq < dh ||
+          hskv < dh || hso < dh)
         return hipErrorInvalidValue;
       const int64_t blocks = (int64_t)kAttnBins * bins.max_len * n_heads;
       if (blocks > 0x7fffffff) return hipErrorInvalidValue;
       if (blocks == 0) return hipSuccess;
-      if (cross)
-        hipLaunchKernelGGL(k_attn32_cross, dim3((unsigned)blocks), dim3(256), 0, st, Q, ldq, hsq,
-                           K, V, ldkv, hskv, O, ldo, work, bins, n_heads, sl2e);
+#define FMD_ATTN32_GO(TPW)                                                                     \
+  do {                                                                                          \
+    if (cross)                                                                                  \
+      hipLaunchKernelGGL((k_attn32_cross<TPW>), dim3((unsigned)blocks), dim3(256), 0, st, Q,     \
+                         ldq, hsq, K, V, ldkv, hskv, O, ldo, hso, work, bins, n_heads, sl2e);   \
+    else                                                                                        \
+      hipLaunchKernelGGL((k_attn32_self<TPW>), dim3((unsigned)blocks), dim3(256), 0, st, Q,      \
+                         ldq, hsq, K, V, ldkv, hskv, O, ldo, hso, work, bins, n_heads, sl2e);   \
+  } while (0)
+      if (qt == 64)
+        FMD_ATTN32_GO(1);
+      else if (qt == 128)
+        FMD_ATTN32_GO(2);
       else
-        hipLaunchKernelGGL(k_attn32_self, dim3((unsigned)blocks), dim3(256), 0, st, Q, ldq, hsq,
-                           K, V, ldkv, hskv, O, ldo, work, bins, n_heads, sl2e);
+        return hipErrorInvalidValue;
+#undef FMD_ATTN32_GO
       return hipGetLastError();
     }
   }
-  // the general kernel takes row-major operands only
-  if (hsq != dh || hskv != dh) return hipErrorInvalidValue;
+  // the general kernel takes row-major operands only, in work items of QT queries
+  if (hsq != dh || hskv != dh || hso != dh || qt != QT) return hipErrorInvalidValue;
   const dim3 grid((unsigned)n_items, n_heads);
   switch (dh) {
     case 16: return go_attn<T, 16>(cross, grid, st, Q, ldq, K, V, ldkv, O, ldo, work, sl2e);
@@ -517,13 +548,13 @@ hipError_t launch_attention(hipStream_t st, bool cross, int dh, int n_heads, int
   }
 }
 
-template hipError_t launch_attention<float>(hipStream_t, bool, int, int, int64_t,
+template hipError_t launch_attention<float>(hipStream_t, bool, int, int, int, int64_t,
                                             const AttnBins&, const AttnItem*, const float*, int,
                                             int64_t, const float*, const float*, int, int64_t,
-                                            float*, int);
-template hipError_t launch_attention<bf16>(hipStream_t, bool, int, int, int64_t,
+                                            float*, int, int64_t);
+template hipError_t launch_attention<bf16>(hipStream_t, bool, int, int, int, int64_t,
                                            const AttnBins&, const AttnItem*, const bf16*, int,
                                            int64_t, const bf16*, const bf16*, int, int64_t,
-                                           bf16*, int);
+                                           bf16*, int, int64_t);
 
 }  // namespace fmd

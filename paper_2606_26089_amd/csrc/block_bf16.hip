@@ -135,24 +135,26 @@ __device__ __forceinline__ void zero(f32x16 (&acc)[TM], const float* __restrict_
     for (int r = 0; r < 16; ++r) acc[mi][r] = bv;
 }
 
-// ROWS x 256 BF16 tile of S (pitch lds_) at rows m0.. into LDS (pitch kLdA).
+// ROWS x 256 BF16 tile at rows m0.. of a head-major attention output [8 heads][Mp][32]
+// (plane = Mp x 32 elements) into LDS (pitch kLdA, row-major): consecutive threads read
+// consecutive 16-byte chunks of one head's rows.
 template <int ROWS, int NT = kThreads>
-__device__ __forceinline__ void tile_to_lds(bf16* __restrict__ A, const bf16* __restrict__ S,
-                                            int lds_, int64_t m0, int tid) {
+__device__ __forceinline__ void tile_hm_to_lds(bf16* __restrict__ A, const bf16* __restrict__ S,
+                                               int64_t plane, int64_t m0, int tid) {
   constexpr int kChunks = ROWS * kD / 8;                // 16-byte chunks
   constexpr int kPer = kChunks / NT;
+  constexpr int kHeadChunks = ROWS * kDh / 8;           // chunks of one head's rows
   u32x4 v[kPer];
 #pragma unroll
   for (int i = 0; i < kPer; ++i) {
-    const int idx = tid + i * NT;
-    const u32x4* src = (const u32x4*)((const char*)(S + m0 * lds_) +
-                                      (uint32_t)(((idx / (kD / 8)) * lds_ + (idx % (kD / 8)) * 8) * 2));
+    const int idx = tid + i * NT, hd = idx / kHeadChunks, rem = idx % kHeadChunks;
+    const u32x4* src = (const u32x4*)((const char*)(S + hd * plane + m0 * kDh) + (uint32_t)rem * 16);
     v[i] = __builtin_nontemporal_load(src);
   }
 #pragma unroll
   for (int i = 0; i < kPer; ++i) {
-    const int idx = tid + i * NT;
-    *(u32x4*)(A + (idx / (kD / 8)) * kLdA + (idx % (kD / 8)) * 8) = v[i];
+    const int idx = tid + i * NT, hd = idx / kHeadChunks, rem = idx % kHeadChunks;
+    *(u32x4*)(A + (rem / (kDh / 8)) * kLdA + hd * kDh + (rem % (kDh / 8)) * 8) = v[i];
   }
 }
 
@@ -516,7 +518,7 @@ constexpr int kEmbLd = 16;     // pitch of the ODE state rows
 constexpr int kEmbF9 = 9;
 
 template <int TM, bool EMBED>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_fused_qkv(const float* __restrict__ H,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(TM == 2 ? 4 : 2))) void k_fused_qkv(const float* __restrict__ H,
                                                         const float* __restrict__ g,
                                                         const float* __restrict__ s,
                                                         const u32x4* __restrict__ Wf,
@@ -593,7 +595,7 @@ __global__ __launch_bounds__(kThreads) void k_fused_oqc(
   const u32x4* wq = Wf_qc + w * kKs * 64;
   u32x4 ring[kRing];
   ring_fill(ring, wo, lane);
-  tile_to_lds<ROWS>(A, att, kD, m0, tid);
+  tile_hm_to_lds<ROWS>(A, att, plane, m0, tid);   // head-major attention output
   f32x16 acc[TM];
   load_rows(acc, H, m0, col, b_o, lane);
   __syncthreads();
@@ -660,7 +662,8 @@ __global__ __launch_bounds__(kThreads4) __attribute__((amdgpu_waves_per_eu(2))) 
   auto dn_c = [&](int c) { return Wf_dn + 2 * w * kDnStride + c * kDnKs * 64; };
   u32x4 ring[kRing];
   ring_fill_nc<2>(ring, woc, kOcStride, lane);
-  tile_to_lds<ROWS, kThreads4>(A, att, kD, m0, tid);
+  // head-major attention output [8 heads][Mp][32]
+  tile_hm_to_lds<ROWS, kThreads4>(A, att, (int64_t)gridDim.x * ROWS * kDh, m0, tid);
   f32x16 acc[TM][2];
 #pragma unroll
   for (int nj = 0; nj < 2; ++nj) {
@@ -875,41 +878,54 @@ hipError_t launch_pack_frag(hipStream_t st, const float* W, int K, int N, void* 
   return hipGetLastError();
 }
 
-// 64-row tiles for the two HBM-bound kernels: half the accumulator, so two workgroups share a
-// CU and one's loads overlap the other's products
-constexpr int kTmIo = 2;
+// The QKV and OQC kernels come in 64-row tiles (half the accumulator: two workgroups share a
+// CU and one's loads overlap the other's products) and 128-row tiles (twice the reuse of
+// each weight fragment); the autotuner picks one per token-count bucket.
 
 hipError_t launch_fused_qkv(hipStream_t st, int64_t Mp, const float* H, const float* g,
-                            const float* s, const void* Wf, const float* bias, void* qkv) {
-  if (Mp % (32 * kTmIo)) return hipErrorInvalidValue;
+                            const float* s, const void* Wf, const float* bias, void* qkv,
+                            int rows) {
+  if ((rows != 64 && rows != 128) || Mp % rows) return hipErrorInvalidValue;
   if (Mp == 0) return hipSuccess;
-  hipLaunchKernelGGL((k_fused_qkv<kTmIo, false>), dim3((unsigned)(Mp / (32 * kTmIo))),
-                     dim3(kThreads), 0, st, H, g, s, (const u32x4*)Wf, bias, (bf16*)qkv,
-                     EmbedRows{});
+  if (rows == 64)
+    hipLaunchKernelGGL((k_fused_qkv<2, false>), dim3((unsigned)(Mp / 64)), dim3(kThreads), 0, st,
+                       H, g, s, (const u32x4*)Wf, bias, (bf16*)qkv, EmbedRows{});
+  else
+    hipLaunchKernelGGL((k_fused_qkv<4, false>), dim3((unsigned)(Mp / 128)), dim3(kThreads), 0, st,
+                       H, g, s, (const u32x4*)Wf, bias, (bf16*)qkv, EmbedRows{});
   return hipGetLastError();
 }
 
 hipError_t launch_fused_embed_qkv(hipStream_t st, int64_t Mp, const float* xs, int ldx, int f,
                                   int64_t T, const float* temb, const float* W_xin, float* H,
                                   const float* g, const float* s, const void* Wf,
-                                  const float* bias, void* qkv) {
-  if (Mp % (32 * kTmIo) || ldx != kEmbLd || f != kEmbF9 || T > Mp) return hipErrorInvalidValue;
+                                  const float* bias, void* qkv, int rows) {
+  if ((rows != 64 && rows != 128) || Mp % rows || ldx != kEmbLd || f != kEmbF9 || T > Mp)
+    return hipErrorInvalidValue;
   if (Mp == 0) return hipSuccess;
   const EmbedRows em{xs, T, temb, W_xin, H};
-  hipLaunchKernelGGL((k_fused_qkv<kTmIo, true>), dim3((unsigned)(Mp / (32 * kTmIo))),
-                     dim3(kThreads), 0, st, nullptr, g, s, (const u32x4*)Wf, bias, (bf16*)qkv,
-                     em);
+  if (rows == 64)
+    hipLaunchKernelGGL((k_fused_qkv<2, true>), dim3((unsigned)(Mp / 64)), dim3(kThreads), 0, st,
+                       nullptr, g, s, (const u32x4*)Wf, bias, (bf16*)qkv, em);
+  else
+    hipLaunchKernelGGL((k_fused_qkv<4, true>), dim3((unsigned)(Mp / 128)), dim3(kThreads), 0, st,
+                       nullptr, g, s, (const u32x4*)Wf, bias, (bf16*)qkv, em);
   return hipGetLastError();
 }
 
 hipError_t launch_fused_oqc(hipStream_t st, int64_t Mp, const void* att, const void* Wf_o,
                             const float* b_o, float* H, const float* g, const float* s,
-                            const void* Wf_qc, const float* b_qc, void* qc) {
-  if (Mp % (32 * kTmIo)) return hipErrorInvalidValue;
+                            const void* Wf_qc, const float* b_qc, void* qc, int rows) {
+  if ((rows != 64 && rows != 128) || Mp % rows) return hipErrorInvalidValue;
   if (Mp == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fused_oqc<kTmIo>, dim3((unsigned)(Mp / (32 * kTmIo))), dim3(kThreads), 0, st,
-                     (const bf16*)att, (const u32x4*)Wf_o, b_o, H, g, s, (const u32x4*)Wf_qc,
-                     b_qc, (bf16*)qc);
+  if (rows == 64)
+    hipLaunchKernelGGL(k_fused_oqc<2>, dim3((unsigned)(Mp / 64)), dim3(kThreads), 0, st,
+                       (const bf16*)att, (const u32x4*)Wf_o, b_o, H, g, s, (const u32x4*)Wf_qc,
+                       b_qc, (bf16*)qc);
+  else
+    hipLaunchKernelGGL(k_fused_oqc<4>, dim3((unsigned)(Mp / 128)), dim3(kThreads), 0, st,
+                       (const bf16*)att, (const u32x4*)Wf_o, b_o, H, g, s, (const u32x4*)Wf_qc,
+                       b_qc, (bf16*)qc);
   return hipGetLastError();
 }
 

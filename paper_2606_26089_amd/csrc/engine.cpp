@@ -243,6 +243,15 @@ void flush_timing(fmd_model* m) {
 // ---------------------------------------------------------------------------------------
 // one call's device state
 
+int bucket_of(int64_t Tp);
+int attn_tiles(const fmd_model* m, int* tiles);
+int attn_tile_for(const fmd_model* m, int64_t Tp);
+template <typename F>
+float time_best_us(hipStream_t st, hipEvent_t e0, hipEvent_t e1, F&& launch);
+template <typename T>
+hipError_t launch_self_attention(fmd_model* m, const Call& c, int qt, int64_t items,
+                                 const AttnBins& bins, const AttnItem* work);
+
 // Uploads offsets and the attention work lists; runs the token map. With reco_off (host,
 // [E + 1], already checked) the reco slots of event e are reco_off[e] .. reco_off[e + 1]
 // and their cross-attention keys the event's truth particles; otherwise reco = truth.
@@ -252,24 +261,72 @@ int stage_events(fmd_model* m, const fmd_events_in* ev, Call& c, const int64_t* 
   const int64_t* roff = reco_off ? reco_off : ev->offsets;
   const int64_t Tt = ev->offsets[E];
   // work items: (event, query tile), in bins of whole events balanced by attention work
-  const int qt = attention_query_tile(m->cfg.precision == FMD_BF16, m->cfg.d_model / std::max(m->cfg.n_heads, 1),
-                                      m->cfg.n_heads);
+  int tiles[4];
+  const int n_tiles = attn_tiles(m, tiles);
   std::vector<int64_t> ids((size_t)E);
-  int64_t items = 0;
+  auto count_items = [&](int qt) {
+    int64_t k = 0;
+    for (int64_t e = 0; e < E; ++e) k += (roff[e + 1] - roff[e] + qt - 1) / qt;
+    return k;
+  };
   double s2 = 0, sx = 0;
   for (int64_t e = 0; e < E; ++e) {
     const int64_t n = roff[e + 1] - roff[e], nt = ev->offsets[e + 1] - ev->offsets[e];
     ids[e] = e;
-    items += (n + qt - 1) / qt;
     s2 += (double)n * (double)n;
     sx += (double)n * (double)nt;
   }
-  c.items = items;
   c.sum_n2 = s2;
-  const int64_t all_items = reco_off ? 2 * items : items;
-  FMD_TRY(ensure_ws(m, std::max(c.T, Tt), E, all_items));
+  // capacity for the smallest candidate tile (the most items)
+  const int64_t cap_items = count_items(tiles[0]) * (reco_off ? 2 : 1);
+  FMD_TRY(ensure_ws(m, std::max(c.T, Tt), E, cap_items));
   // The pinned staging buffers may still feed the previous call's copies.
   HIP_TRY(hipStreamSynchronize(c.st));
+  const int b = bucket_of(c.Tp);
+  if (n_tiles > 1 && m->autotune && m->kind == 0 && m->tune[TS_ATTN][b] < 0) {
+    // the attention query tile: time the self-attention with each candidate's work list on
+    // the call's shapes (the buffers hold nothing used later)
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    int best = -1;
+    float best_us = 0.f;
+    int status = FMD_OK;
+    for (int k = 0; k < n_tiles && status == FMD_OK; ++k) {
+      const int64_t nk = count_items(tiles[k]);
+      AttnBins bk{};
+      if (build_attention_work(roff, roff, ids.data(), E, tiles[k], w.h_work, &bk) != nk) {
+        status = fail(FMD_E_INVALID, "token rows beyond 2^31");
+        break;
+      }
+      if (hipMemcpyAsync(w.work, w.h_work, (size_t)nk * sizeof(AttnItem), hipMemcpyHostToDevice, c.st) !=
+              hipSuccess ||
+          hipStreamSynchronize(c.st) != hipSuccess) {
+        status = fail(FMD_E_DEVICE, "autotune upload failed");
+        break;
+      }
+      const float us = time_best_us(c.st, e0, e1, [&] {
+        return launch_self_attention<bf16>(m, c, tiles[k], nk, bk, w.work);
+      });
+      if (us < 0.f) {
+        status = fail(FMD_E_DEVICE, "autotune launch failed");
+        break;
+      }
+      m->tune_all[TS_ATTN][b][k] = us;
+      if (best < 0 || us < best_us) best = k, best_us = us;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    FMD_TRY(status);
+    m->tune[TS_ATTN][b] = (int8_t)best;
+    m->tune_us[TS_ATTN][b] = best_us;
+    m->tune_gen++;
+  }
+  const int qt = attn_tile_for(m, c.Tp);
+  const int64_t items = count_items(qt);
+  c.qt = qt;
+  c.items = items;
+  const int64_t all_items = reco_off ? 2 * items : items;
   std::memcpy(w.h_off, roff, (size_t)(E + 1) * 8);
   if (build_attention_work(w.h_off, w.h_off, ids.data(), E, qt, w.h_work, &c.bins) != items)
     return fail(FMD_E_INVALID, "token rows beyond 2^31");
@@ -358,6 +415,25 @@ int tile_for(const fmd_model* m, int slot, int64_t Tp, int N) {
 
 int resid_epi(const fmd_model* m) { return m->fuse_stats ? EPI_RESID_LN : EPI_RESID; }
 
+// Attention query tiles the model's kernel takes (candidates of the autotuner) and the one
+// used for a padded token count: the tuned one, else the default.
+int attn_tiles(const fmd_model* m, int* tiles) {
+  return attention_query_tiles(m->cfg.precision == FMD_BF16,
+                               m->cfg.d_model / std::max(m->cfg.n_heads, 1), tiles);
+}
+int attn_tile_for(const fmd_model* m, int64_t Tp) {
+  int tiles[4];
+  const int n = attn_tiles(m, tiles);
+  const int t = m->tune[TS_ATTN][bucket_of(Tp)];
+  if (t >= 0 && t < n) return tiles[t];
+  return attention_query_tile(m->cfg.precision == FMD_BF16,
+                              m->cfg.d_model / std::max(m->cfg.n_heads, 1), m->cfg.n_heads);
+}
+// Row tile of the fused QKV / OQC kernels (candidate 0: 64 rows, 1: 128 rows).
+int fused_rows_for(const fmd_model* m, int slot, int64_t Tp) {
+  return m->tune[slot][bucket_of(Tp)] == 1 ? 128 : 64;
+}
+
 // Launches the GEMM of one tuning slot with a given tiling on the live workspace.
 template <typename T>
 hipError_t slot_gemm(fmd_model* m, Call& c, int slot, int tile, const DevBlock& B) {
@@ -390,17 +466,88 @@ hipError_t slot_gemm(fmd_model* m, Call& c, int slot, int tile, const DevBlock& 
 // k-slice accumulation order per element), so the choice affects speed only. Runs before
 // the first evaluation of a call, while the activation buffers hold nothing that is used
 // later (the residual stream is rebuilt by the next input embedding).
+// Times one launch sequence: 1 warm-up + 3 timed launches, best of the three, in
+// microseconds (negative if a launch failed).
+template <typename F>
+float time_best_us(hipStream_t st, hipEvent_t e0, hipEvent_t e1, F&& launch) {
+  if (launch() != hipSuccess) {
+    (void)hipGetLastError();
+    return -1.f;
+  }
+  float best = 1e30f;
+  for (int rep = 0; rep < 3; ++rep) {
+    float ms = 0.f;
+    if (hipEventRecord(e0, st) != hipSuccess || launch() != hipSuccess ||
+        hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+      return -1.f;
+    best = std::min(best, ms * 1e3f);
+  }
+  return best;
+}
+
+// Fused BF16 path: the row tile (64 or 128 rows) of block 0's QKV kernel and of the OQC
+// kernel, timed on the call's shapes and buffers like the GEMM tilings. Both candidates give
+// bitwise-identical rows (each row's LayerNorm statistics and products are formed in the
+// same order whatever its tile).
+int autotune_fused(fmd_model* m, Call& c, int b) {
+  Workspace& w = m->ws;
+  const DevBlock& B = m->blk[0];
+  const int sites[2] = {TS_FQKV, TS_FOQC};
+  const int bits[2] = {FMD_FUSED_QKV, FMD_FUSED_OQC};
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  int status = FMD_OK;
+  for (int i = 0; i < 2 && status == FMD_OK; ++i) {
+    const int sl = sites[i];
+    if (!(m->fused & bits[i]) || m->tune[sl][b] >= 0) continue;
+    int best = -1;
+    float best_us = 0.f;
+    for (int k = 0; k < 2; ++k) {
+      const int rows = 64 << k;
+      if (c.Tp % rows) continue;
+      // block 0's QKV kernel is timed in the form sampler stages run: with the input embedding
+      // when that is folded in (calls with per-event times run the plain form with the same
+      // row tile)
+      const float us = time_best_us(c.st, e0, e1, [&] {
+        if (sl == TS_FOQC)
+          return launch_fused_oqc(c.st, c.Tp, w.att, B.Fo, B.bo, w.H, B.g2, B.s2, B.Fqc, B.bqc,
+                                  w.qc, rows);
+        if (m->fused & FMD_FUSED_EMBED)
+          return launch_fused_embed_qkv(c.st, c.Tp, w.xs, kStateLd, 9, c.T, w.temb, m->W_xin, w.H,
+                                        B.g1, B.s1, B.Fqkv, B.bqkv, w.qkv, rows);
+        return launch_fused_qkv(c.st, c.Tp, w.H, B.g1, B.s1, B.Fqkv, B.bqkv, w.qkv, rows);
+      });
+      if (us < 0.f) {
+        status = fail(FMD_E_DEVICE, "autotune launch failed");
+        break;
+      }
+      m->tune_all[sl][b][k] = us;
+      if (best < 0 || us < best_us) best = k, best_us = us;
+    }
+    m->tune[sl][b] = (int8_t)std::max(best, 0);
+    m->tune_us[sl][b] = best_us;
+    m->tune_gen++;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return status;
+}
+
 template <typename T>
 int autotune(fmd_model* m, Call& c) {
-  const int blocks_fused = FMD_FUSED_QKV | FMD_FUSED_OQC | FMD_FUSED_MLP;
-  if (!m->autotune || m->kind != 0 || (m->fused & blocks_fused) == blocks_fused)
-    return FMD_OK;   // fixed tiling
+  if (!m->autotune || m->kind != 0) return FMD_OK;   // fixed tiling
   const int b = bucket_of(c.Tp);
+  if (std::is_same<T, bf16>::value && m->fused) FMD_TRY(autotune_fused(m, c, b));
+  const int blocks_fused = FMD_FUSED_QKV | FMD_FUSED_OQC | FMD_FUSED_MLP;
+  if (std::is_same<T, bf16>::value && (m->fused & blocks_fused) == blocks_fused)
+    return FMD_OK;   // no GEMM site runs
   const int d = m->cfg.d_model;
-  const int N[TS_COUNT] = {3 * d, d, d, 4 * d, d};
-  const int K[TS_COUNT] = {d, d, d, d, 4 * d};
+  const int N[TS_GEMM] = {3 * d, d, d, 4 * d, d};
+  const int K[TS_GEMM] = {d, d, d, d, 4 * d};
   bool any = false;
-  for (int sl = 0; sl < TS_COUNT; ++sl) any |= m->tune[sl][b] < 0;
+  for (int sl = 0; sl < TS_GEMM; ++sl) any |= m->tune[sl][b] < 0;
   if (!any) return FMD_OK;
   c.sargs = OdeArgs{};
   c.sargs.stats_out = m->ws.stats;
@@ -408,7 +555,7 @@ int autotune(fmd_model* m, Call& c) {
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
   int status = FMD_OK;
-  for (int sl = 0; sl < TS_COUNT && status == FMD_OK; ++sl) {
+  for (int sl = 0; sl < TS_GEMM && status == FMD_OK; ++sl) {
     if (m->tune[sl][b] >= 0) continue;
     int best = -1;
     float best_us = 0.f;
@@ -441,6 +588,32 @@ int autotune(fmd_model* m, Call& c) {
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   return status;
+}
+
+// Self-attention of one evaluation over the live workspace, with a work list of query tile qt.
+// Q/K/V are head-major [3][heads][Tp][dh] when the fused QKV kernels formed them, row-major
+// [Tp][3d] otherwise; the output is head-major [heads][Tp][dh] when the fused OQC kernel reads
+// it, row-major [Tp][d] otherwise.
+template <typename T>
+hipError_t launch_self_attention(fmd_model* m, const Call& c, int qt, int64_t items,
+                                 const AttnBins& bins, const AttnItem* work) {
+  Workspace& w = m->ws;
+  const int d = m->cfg.d_model, Hh = m->cfg.n_heads, dh = d / Hh;
+  const size_t es = sizeof(T);
+  const int fz = std::is_same<T, bf16>::value ? m->fused : 0;
+  const char* qkv = (const char*)w.qkv;
+  const bool ohm = (fz & FMD_FUSED_OQC) != 0;
+  const int ldo = ohm ? dh : d;
+  const int64_t hso = ohm ? c.Tp * dh : dh;
+  if (fz & FMD_FUSED_QKV) {
+    const int64_t pl = c.Tp * dh;
+    return launch_attention<T>(c.st, false, dh, Hh, qt, items, bins, work, (const T*)qkv, dh, pl,
+                               (const T*)(qkv + Hh * pl * es), (const T*)(qkv + 2 * Hh * pl * es),
+                               dh, pl, (T*)w.att, ldo, hso);
+  }
+  return launch_attention<T>(c.st, false, dh, Hh, qt, items, bins, work, (const T*)qkv, 3 * d, dh,
+                             (const T*)(qkv + d * es), (const T*)(qkv + 2 * d * es), 3 * d, dh,
+                             (T*)w.att, ldo, hso);
 }
 
 // One evaluation of the velocity network at xs; leaves the residual stream in w.H.
@@ -484,12 +657,14 @@ int net_forward(fmd_model* m, Call& c, const float* t_ev) {
         FMD_TRY(timed(m, c.st, FMD_K_GEMM_QKV, 2.0 * Td * dd * 3 * dd + 2.0 * Td * 9 * dd,
                       Td * (dd * 4 + kStateLd * 4) + (Td + dd) * 3 * dd * es, [&] {
           return launch_fused_embed_qkv(c.st, c.Tp, w.xs, kStateLd, 9, c.T, w.temb, m->W_xin,
-                                        w.H, B.g1, B.s1, B.Fqkv, B.bqkv, w.qkv);
+                                        w.H, B.g1, B.s1, B.Fqkv, B.bqkv, w.qkv,
+                                        fused_rows_for(m, TS_FQKV, c.Tp));
         }));
       else if (!qkv_ready)
         FMD_TRY(timed(m, c.st, FMD_K_GEMM_QKV, 2.0 * Td * dd * 3 * dd,
                       Td * dd * 4 + (Td + dd) * 3 * dd * es, [&] {
-          return launch_fused_qkv(c.st, c.Tp, w.H, B.g1, B.s1, B.Fqkv, B.bqkv, w.qkv);
+          return launch_fused_qkv(c.st, c.Tp, w.H, B.g1, B.s1, B.Fqkv, B.bqkv, w.qkv,
+                                  fused_rows_for(m, TS_FQKV, c.Tp));
         }));
     } else {
       if (l > 0) FMD_TRY(row_stats(m, c));
@@ -500,20 +675,13 @@ int net_forward(fmd_model* m, Call& c, const float* t_ev) {
       }));
     }
     FMD_TRY(timed(m, c.st, FMD_K_ATTN_SELF, 4.0 * c.sum_n2 * d, Td * 4 * d * es, [&] {
-      if (fz & FMD_FUSED_QKV) {   // head-major [3][heads][Tp][dh]
-        const int64_t pl = c.Tp * dh;
-        return launch_attention<T>(c.st, false, dh, Hh, c.items, c.bins, w.work, (const T*)qkv, dh,
-                                   pl, (const T*)(qkv + Hh * pl * es),
-                                   (const T*)(qkv + 2 * Hh * pl * es), dh, pl, (T*)w.att, d);
-      }
-      return launch_attention<T>(c.st, false, dh, Hh, c.items, c.bins, w.work, (const T*)qkv, 3 * d,
-                                 dh, (const T*)(qkv + d * es), (const T*)(qkv + 2 * d * es), 3 * d,
-                                 dh, (T*)w.att, d);
+      return launch_self_attention<T>(m, c, c.qt, c.items, c.bins, w.work);
     }));
     if (fz & FMD_FUSED_OQC) {
       FMD_TRY(timed(m, c.st, FMD_K_FUSED_OQC, 2.0 * Td * dd * dd * 2,
                     Td * dd * (es + 8 + es) + 2 * dd * dd * es, [&] {
-        return launch_fused_oqc(c.st, c.Tp, w.att, B.Fo, B.bo, w.H, B.g2, B.s2, B.Fqc, B.bqc, w.qc);
+        return launch_fused_oqc(c.st, c.Tp, w.att, B.Fo, B.bo, w.H, B.g2, B.s2, B.Fqc, B.bqc, w.qc,
+                                fused_rows_for(m, TS_FOQC, c.Tp));
       }));
     } else {
       FMD_TRY(timed(m, c.st, FMD_K_GEMM_PROJ, 2.0 * Td * d * d, (Td + d) * d * es + resid, [&] {
@@ -530,18 +698,22 @@ int net_forward(fmd_model* m, Call& c, const float* t_ev) {
     }
     FMD_TRY(timed(m, c.st, FMD_K_ATTN_CROSS, 4.0 * c.sum_nx * d, (Td * 2 + c.Tt * 2.0) * d * es, [&] {
       const size_t o = (size_t)l * 2 * d * es;
-      // the cross query is head-major [heads][Tp][dh] when the fused kernel formed it
+      // the cross query is head-major [heads][Tp][dh] when the fused kernel formed it, and
+      // the output when the fused MLP kernel reads it
       const bool hm = (fz & FMD_FUSED_OQC) != 0;
+      const bool ohm = (fz & FMD_FUSED_MLP) != 0;
+      const int ldo = ohm ? dh : d;
+      const int64_t hso = ohm ? c.Tp * dh : dh;
       if (m->kv_hm) {   // cache planes [L][K, V][heads][cap rows][dh]
         const int64_t pl = w.cap_tok * dh;
         const char* kb = kv + (size_t)l * 2 * Hh * pl * es;
-        return launch_attention<T>(c.st, true, dh, Hh, c.items_x, c.bins_x, w.work + c.work_x, (const T*)w.qc,
+        return launch_attention<T>(c.st, true, dh, Hh, c.qt, c.items_x, c.bins_x, w.work + c.work_x, (const T*)w.qc,
                                    hm ? dh : d, hm ? c.Tp * dh : dh, (const T*)kb,
-                                   (const T*)(kb + Hh * pl * es), dh, pl, (T*)w.att, d);
+                                   (const T*)(kb + Hh * pl * es), dh, pl, (T*)w.att, ldo, hso);
       }
-      return launch_attention<T>(c.st, true, dh, Hh, c.items_x, c.bins_x, w.work + c.work_x, (const T*)w.qc,
+      return launch_attention<T>(c.st, true, dh, Hh, c.qt, c.items_x, c.bins_x, w.work + c.work_x, (const T*)w.qc,
                                  hm ? dh : d, hm ? c.Tp * dh : dh, (const T*)(kv + o),
-                                 (const T*)(kv + o + d * es), 2 * d * L, dh, (T*)w.att, d);
+                                 (const T*)(kv + o + d * es), 2 * d * L, dh, (T*)w.att, ldo, hso);
     }));
     if (fz & FMD_FUSED_MLP) {
       // chained with the next block's LN1 + QKV when that segment is fused too
@@ -1225,6 +1397,49 @@ int fmd_truth_select(const fmd_events_in* truth, double pt_cut_gev, int32_t max_
   return FMD_OK;
 }
 
+int fmd_reco_multiplicity(const int64_t* truth_offsets, int64_t n_events, uint64_t seed,
+                          const fmd_multiplicity_law* law, int32_t n_max, int64_t* reco_offsets_out,
+                          void* hip_stream) {
+  if (!truth_offsets || !law || !reco_offsets_out || n_events < 0) return fail(FMD_E_INVALID, "null argument");
+  if (!(law->loss_prob >= 0.0 && law->loss_prob < 1.0) || !(law->fake_prob >= 0.0 && law->fake_prob < 1.0))
+    return fail(FMD_E_INVALID, "probabilities must lie in [0, 1)");
+  if (law->fake_trials < 0 || law->fake_trials > 4096) return fail(FMD_E_INVALID, "fake_trials must lie in [0, 4096]");
+  if (n_max < 0) return fail(FMD_E_INVALID, "negative n_max");
+  if (truth_offsets[0] != 0) return fail(FMD_E_INVALID, "offsets[0] must be 0");
+  for (int64_t e = 0; e < n_events; ++e)
+    if (truth_offsets[e + 1] < truth_offsets[e]) return fail(FMD_E_INVALID, "offsets decrease at event %lld", (long long)e);
+  reco_offsets_out[0] = 0;
+  if (n_events == 0) return FMD_OK;
+  // floor(p 2^64): exact, and below 2^64 for p < 1
+  const uint64_t thr_q = (uint64_t)std::ldexp(law->loss_prob, 64);
+  const uint64_t thr_p = (uint64_t)std::ldexp(law->fake_prob, 64);
+  hipStream_t st = (hipStream_t)hip_stream;
+  static std::mutex mu;
+  static void* buf = nullptr;
+  static size_t cap = 0;
+  std::lock_guard<std::mutex> lock(mu);
+  const size_t b_off = ((size_t)(n_events + 1) * 8 + 255) & ~(size_t)255;
+  const size_t need = b_off + (size_t)n_events * 4;
+  if (need > cap) {
+    if (buf) (void)hipFree(buf);
+    buf = nullptr;
+    cap = 0;
+    if (hipMalloc(&buf, need) != hipSuccess) return fail(FMD_E_NOMEM, "allocation failed");
+    cap = need;
+  }
+  int64_t* d_off = (int64_t*)buf;
+  int32_t* d_cnt = (int32_t*)((char*)buf + b_off);
+  std::vector<int32_t> cnt((size_t)n_events);
+  hipError_t e = hipMemcpyAsync(d_off, truth_offsets, (size_t)(n_events + 1) * 8, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    e = launch_reco_counts(st, d_off, n_events, seed, thr_q, thr_p, law->fake_trials, n_max, d_cnt);
+  if (e == hipSuccess) e = hipMemcpyAsync(cnt.data(), d_cnt, (size_t)n_events * 4, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return fail(FMD_E_DEVICE, "reco multiplicity: %s", hipGetErrorString(e));
+  for (int64_t i = 0; i < n_events; ++i) reco_offsets_out[i + 1] = reco_offsets_out[i] + cnt[(size_t)i];
+  return FMD_OK;
+}
+
 int fmd_debug_philox(uint64_t key0, uint64_t key1, const uint64_t* counters, int64_t n,
                      uint64_t* out, void* hip_stream) {
   if (n < 0 || (n > 0 && (!counters || !out))) return fail(FMD_E_INVALID, "bad arguments");
@@ -1305,9 +1520,27 @@ int fmd_autotune_enable(fmd_model* m, int32_t enable) {
   return FMD_OK;
 }
 
+int fmd_tuning_set(fmd_model* m, int32_t site, int32_t tokens_log2, int32_t candidate) {
+  if (!m) return fail(FMD_E_INVALID, "null model");
+  if (site < FMD_TUNE_ATTN_QUERY_TILE || site > FMD_TUNE_FUSED_OQC)
+    return fail(FMD_E_INVALID, "site %d is not a fused-path site", site);
+  if (tokens_log2 < 0 || tokens_log2 >= kTuneBuckets) return fail(FMD_E_INVALID, "bad token bucket");
+  int tiles[4];
+  const int n = site == FMD_TUNE_ATTN_QUERY_TILE ? attn_tiles(m, tiles) : (m->fused_ok ? 2 : 1);
+  if (candidate < 0 || candidate >= n) return fail(FMD_E_INVALID, "candidate %d not in [0, %d)", candidate, n);
+  const int sl = TS_ATTN + (site - FMD_TUNE_ATTN_QUERY_TILE);
+  m->tune[sl][tokens_log2] = (int8_t)candidate;
+  m->tune_us[sl][tokens_log2] = 0.f;
+  m->tune_gen++;   // captured graphs hold the previous choice
+  return FMD_OK;
+}
+
 int fmd_tuning_table(fmd_model* m, char* buf, size_t cap, size_t* needed) {
   if (!m) return fail(FMD_E_INVALID, "null model");
-  static const char* slot_names[TS_COUNT] = {"qkv", "proj_residual", "proj_ln", "mlp_up", "mlp_down"};
+  static const char* slot_names[TS_COUNT] = {"qkv", "proj_residual", "proj_ln", "mlp_up", "mlp_down",
+                                             "attn_query_tile", "fused_qkv", "fused_oqc"};
+  int tiles[4];
+  attn_tiles(m, tiles);
   std::string js = "{\"precision\": \"";
   js += m->cfg.precision == FMD_BF16 ? "bf16" : "fp32";
   js += "\", \"d_model\": " + std::to_string(m->cfg.d_model) + ", \"entries\": [";
@@ -1315,7 +1548,15 @@ int fmd_tuning_table(fmd_model* m, char* buf, size_t cap, size_t* needed) {
   for (int sl = 0; sl < TS_COUNT; ++sl)
     for (int b = 0; b < kTuneBuckets; ++b) {
       if (m->tune[sl][b] < 0) continue;
-      const TileDims t = tile_dims(m->tune[sl][b]);
+      // GEMM sites: the tiling; attention: queries per work item (BM) x keys per chunk (BN) x
+      // head width (BK); fused kernels: rows per workgroup (BM) x model width (BN) x MFMA depth
+      TileDims t{};
+      if (sl < TS_GEMM)
+        t = tile_dims(m->tune[sl][b]);
+      else if (sl == TS_ATTN)
+        t = TileDims{tiles[m->tune[sl][b]], 128, m->cfg.d_model / m->cfg.n_heads, 256};
+      else
+        t = TileDims{64 << m->tune[sl][b], m->cfg.d_model, 16, 512};
       char e[256];
       snprintf(e, sizeof(e),
                "%s{\"site\": \"%s\", \"tokens_log2\": %d, \"tile\": %d, \"BM\": %d, \"BN\": %d, "
@@ -1412,7 +1653,7 @@ int fmd_debug_attention(int32_t precision, int64_t n_events, const int64_t* q_of
   if (dh != 16 && dh != 32 && dh != 64) return fail(FMD_E_UNSUPPORTED, "dh must be 16, 32 or 64");
   if (n_heads < 1 || n_events < 0 || !q_offsets || !kv_offsets) return fail(FMD_E_INVALID, "bad arguments");
   if (q_offsets[0] != 0 || kv_offsets[0] != 0) return fail(FMD_E_INVALID, "offsets must start at 0");
-  const int qt = attention_query_tile(precision == FMD_BF16, dh, n_heads);
+  const int qt = attention_query_tile(precision == FMD_BF16, dh, n_heads);   // the default tile
   std::vector<int64_t> ids((size_t)n_events);
   int64_t n_items = 0;
   for (int64_t e = 0; e < n_events; ++e) {
@@ -1447,13 +1688,13 @@ int fmd_debug_attention(int32_t precision, int64_t n_events, const int64_t* q_of
       if (e == hipSuccess) e = launch_convert<bf16>(st, K, Tk * ld, (bf16*)Kp);
       if (e == hipSuccess) e = launch_convert<bf16>(st, V, Tk * ld, (bf16*)Vp);
       if (e == hipSuccess)
-        e = launch_attention<bf16>(st, false, dh, n_heads, (int64_t)work.size(), bins, wk, (const bf16*)Qp, ld,
-                                   dh, (const bf16*)Kp, (const bf16*)Vp, ld, dh, (bf16*)Op, ld);
+        e = launch_attention<bf16>(st, false, dh, n_heads, qt, (int64_t)work.size(), bins, wk, (const bf16*)Qp, ld,
+                                   dh, (const bf16*)Kp, (const bf16*)Vp, ld, dh, (bf16*)Op, ld, dh);
       if (e == hipSuccess) e = launch_to_f32<bf16>(st, (const bf16*)Op, Tq * ld, O);
     } else {
       if (e == hipSuccess)
-        e = launch_attention<float>(st, false, dh, n_heads, (int64_t)work.size(), bins, wk, Q, ld, dh, K, V, ld,
-                                    dh, O, ld);
+        e = launch_attention<float>(st, false, dh, n_heads, qt, (int64_t)work.size(), bins, wk, Q, ld, dh, K, V, ld,
+                                    dh, O, ld, dh);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) status = fail(FMD_E_DEVICE, "debug attention: %s", hipGetErrorString(e));

@@ -70,8 +70,11 @@ struct GraphKey {
   }
 };
 
-// GEMM sites the autotuner chooses a tiling for.
-enum TuneSlot { TS_QKV = 0, TS_PROJ_RES = 1, TS_PROJ_LN = 2, TS_UP = 3, TS_DOWN = 4, TS_COUNT = 5 };
+// Sites the autotuner chooses a variant for: the GEMM sites (a tiling of the matrix-core
+// GEMM kernel), then on the fused BF16 path the attention query tile (work items of 64 or
+// 128 queries) and the row tile of the fused QKV and OQC kernels (64 or 128 rows).
+enum TuneSlot { TS_QKV = 0, TS_PROJ_RES = 1, TS_PROJ_LN = 2, TS_UP = 3, TS_DOWN = 4, TS_GEMM = 5,
+                TS_ATTN = 5, TS_FQKV = 6, TS_FOQC = 7, TS_COUNT = 8 };
 constexpr int kTuneBuckets = 40;   // floor(log2(padded token count))
 
 struct TimingRec {

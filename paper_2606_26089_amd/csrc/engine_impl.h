@@ -99,6 +99,7 @@ int timed(fmd_model* m, hipStream_t st, int cls, double work, F&& launch) {
 struct Call {
   hipStream_t st;
   int64_t E, T, Tp, items;   // T reco slots (rows of the state and residual stream)
+  int qt;               // queries per attention work item (the lists are built with it)
   AttnBins bins;        // bins of the attention work list
   double sum_n2;        // sum over events of N_e^2 (attention work)
   // Truth side: Tt truth particles (rows of the truth encoding and cross K/V cache) and the
@@ -134,6 +135,7 @@ int check_schedule(const fmd_schedule* s);
 int stages_per_step(int scheme);
 StageDesc stage_desc(const fmd_schedule& s, int i);
 int row_stats(fmd_model* m, Call& c);
+int attn_tile_for(const fmd_model* m, int64_t Tp);   // attention query tile for a padded size
 int enter_stream(fmd_model* m, hipStream_t caller, Call& c);
 int leave_stream(fmd_model* m, hipStream_t caller);
 template <typename T> int truth_cache(fmd_model* m, Call& c);

@@ -80,9 +80,12 @@ int default_tile_rows(int N);   // a full-row tiling for N, or -1
 hipError_t launch_row_stats(hipStream_t st, const float* A, int ld, int K, int64_t M,
                             float2* stats);
 
-// Queries per attention work item (event, query tile) for a precision and head shape; the
-// work lists passed to launch_attention are built with this tile.
+// Queries per attention work item (event, query tile) for a precision and head shape, by
+// default; BF16 with heads of 32 also accepts the tiles of attention_query_tiles (64 and 128),
+// among which the autotuner chooses. The work lists passed to launch_attention are built
+// with the tile it is given.
 int attention_query_tile(bool bf16, int dh, int n_heads);
+int attention_query_tiles(bool bf16, int dh, int* tiles);   // candidates; returns their count
 
 // Attention work list split into kAttnBins bins of whole events with about equal work, each
 // bin's items stored contiguously (bin i: items [start[i], start[i] + len[i])). Workgroup b
@@ -112,13 +115,14 @@ int64_t build_attention_work_kv(const int64_t* q_off, const int64_t* kv_start,
 
 // Masked multi-head attention over ragged events, one work item per (event, query tile).
 // Element (row, head, dim) of Q sits at Q[row * ldq + head * hsq + dim], of K / V at
-// [row * ldkv + head * hskv + dim]: hs = dh for row-major [rows, heads x dh] operands,
-// ld = dh and hs = plane size for head-major ones (BF16 with dh 32 only). O is row-major.
+// [row * ldkv + head * hskv + dim], of O at [row * ldo + head * hso + dim]: hs = dh for
+// row-major [rows, heads x dh] operands, ld = dh and hs = plane size for head-major ones
+// (BF16 with dh 32 only).
 template <typename T>
-hipError_t launch_attention(hipStream_t st, bool cross, int dh, int n_heads, int64_t n_items,
-                            const AttnBins& bins,
+hipError_t launch_attention(hipStream_t st, bool cross, int dh, int n_heads, int qt,
+                            int64_t n_items, const AttnBins& bins,
                             const AttnItem* work, const T* Q, int ldq, int64_t hsq, const T* K,
-                            const T* V, int ldkv, int64_t hskv, T* O, int ldo);
+                            const T* V, int ldkv, int64_t hskv, T* O, int ldo, int64_t hso);
 
 hipError_t launch_token_map(hipStream_t st, const int64_t* off, int64_t E, int64_t T,
                             int32_t* tok_event);
@@ -169,6 +173,10 @@ hipError_t launch_event_observables(hipStream_t st, const float* feat, int ldf,
                                     float* met, float* iso);
 // Truth preprocessing: per-event keep flags and counts (pass 1), then the kept rows in input
 // order at off_out (pass 2); see fmd_truth_select.
+// Reco multiplicity per event under the stand-in law (cnt [E] int32; off device [E + 1]).
+hipError_t launch_reco_counts(hipStream_t st, const int64_t* off, int64_t n_events, uint64_t seed,
+                              uint64_t thr_q, uint64_t thr_p, int fake_trials, int n_max,
+                              int32_t* cnt);
 hipError_t launch_select_count(hipStream_t st, const float* feat, int ldf, const int64_t* off,
                                int64_t n_events, float c0, int limit, uint8_t* keep,
                                int32_t* cnt);
@@ -193,9 +201,11 @@ hipError_t launch_pack_weight(hipStream_t st, const float* W, int K, int N, T* W
 bool fused_supported(int d_model, int n_heads, int mlp_ratio);
 // W: FP32 K x N (y = x W) -> BF16 MFMA B fragments [N/32][K/16][64 lanes][8].
 hipError_t launch_pack_frag(hipStream_t st, const float* W, int K, int N, void* Wf);
-// [Q | K | V] = LN(H; g, s) Wqkv + b, head-major: qkv [3][8 heads][Mp][32] (plane = Mp x 32)
+// [Q | K | V] = LN(H; g, s) Wqkv + b, head-major: qkv [3][8 heads][Mp][32] (plane = Mp x 32).
+// rows: the workgroup's row tile, 64 or 128 (the autotuner's candidates; same results).
 hipError_t launch_fused_qkv(hipStream_t st, int64_t Mp, const float* H, const float* g,
-                            const float* s, const void* Wf, const float* bias, void* qkv);
+                            const float* s, const void* Wf, const float* bias, void* qkv,
+                            int rows = 64);
 // As launch_fused_qkv for block 0, with the input embedding formed in the kernel for a
 // stage time shared by every row: H rows [0, T) = temb[0..255] + xs[r][0..8] W_xin (the
 // order of launch_embed's d = 256 kernel, so H is the same; rows [T, Mp) are zero) are
@@ -203,12 +213,13 @@ hipError_t launch_fused_qkv(hipStream_t st, int64_t Mp, const float* H, const fl
 hipError_t launch_fused_embed_qkv(hipStream_t st, int64_t Mp, const float* xs, int ldx, int f,
                                   int64_t T, const float* temb, const float* W_xin, float* H,
                                   const float* g, const float* s, const void* Wf,
-                                  const float* bias, void* qkv);
-// H += att Wo + b_o;  qc = LN(H; g, s) Wqc + b_qc, head-major: qc [8 heads][Mp][32]
+                                  const float* bias, void* qkv, int rows = 64);
+// H += att Wo + b_o;  qc = LN(H; g, s) Wqc + b_qc, head-major: qc [8 heads][Mp][32]. The
+// attention output att is head-major [8 heads][Mp][32] as well. rows: 64 or 128.
 hipError_t launch_fused_oqc(hipStream_t st, int64_t Mp, const void* att, const void* Wf_o,
                             const float* b_o, float* H, const float* g, const float* s,
-                            const void* Wf_qc, const float* b_qc, void* qc);
-// H += att Woc + b_oc;  H += GELU(LN(H; g, s) Wup + b_up) Wdn + b_dn;  stats_out = LN stats of
+                            const void* Wf_qc, const float* b_qc, void* qc, int rows = 64);
+// att (head-major [8 heads][Mp][32]): H += att Woc + b_oc;  H += GELU(LN(H; g, s) Wup + b_up) Wdn + b_dn;  stats_out = LN stats of
 // H. With qkv set, also the next block's [Q | K | V] = LN(H; g1n, s1n) Wqkv_n + b_qkv_n into
 // qkv, head-major like launch_fused_qkv (the next block then skips its QKV kernel). With head
 // set instead (the last block, 9 features), the output head LN_f(H; gf, sf) Wt_out^T + b_out

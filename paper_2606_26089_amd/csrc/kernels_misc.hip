@@ -836,6 +836,53 @@ __global__ __launch_bounds__(256) void k_select_write(const float* __restrict__ 
   }
 }
 
+// Reco multiplicity per event (a stand-in law; the model can emit particles that match no
+// truth particle, Sec. 2.2): N_reco = min(n_max, N - lost + fakes) for N > 0 truth particles,
+// else 0. lost counts the words w_i, i < N, below thr_q (each truth particle missed with
+// probability q), fakes the words w_(N + j), j < M, below thr_p (M trials of probability p).
+// The words are those of Philox4x64-10 with key (seed, 1) at counters (c, e, 0, 0), four per
+// counter in order. One wave per event: lane l takes counters l, l + 64, ...; the integer
+// counts are summed across the wave (order-free).
+__global__ __launch_bounds__(64) void k_reco_counts(const int64_t* __restrict__ off, int64_t E,
+                                                    uint64_t seed, uint64_t thr_q, uint64_t thr_p,
+                                                    int M, int n_max, int32_t* __restrict__ cnt) {
+  const int64_t e = blockIdx.x;
+  if (e >= E) return;
+  const int lane = threadIdx.x;
+  const int64_t n = off[e + 1] - off[e];
+  if (n <= 0) {
+    if (lane == 0) cnt[e] = 0;
+    return;
+  }
+  const int64_t words = n + M, ctrs = (words + 3) / 4;
+  int lost = 0, fakes = 0;
+  for (int64_t c = lane; c < ctrs; c += 64) {
+    const Philox4x64 w = philox4x64_10((uint64_t)c, (uint64_t)e, 0ull, 0ull, seed, 1ull);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int64_t i = 4 * c + k;
+      if (i < n) lost += w.c[k] < thr_q;
+      else if (i < words) fakes += w.c[k] < thr_p;
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    lost += __shfl_xor(lost, o, 64);
+    fakes += __shfl_xor(fakes, o, 64);
+  }
+  if (lane == 0) cnt[e] = (int32_t)min<int64_t>(n_max, n - lost + fakes);
+}
+
+hipError_t launch_reco_counts(hipStream_t st, const int64_t* off, int64_t n_events, uint64_t seed,
+                              uint64_t thr_q, uint64_t thr_p, int fake_trials, int n_max,
+                              int32_t* cnt) {
+  if (n_events <= 0) return hipSuccess;
+  if (n_events > 0x7fffffff || fake_trials < 0 || n_max < 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_reco_counts, dim3((unsigned)n_events), dim3(64), 0, st, off, n_events, seed,
+                     thr_q, thr_p, fake_trials, n_max, cnt);
+  return hipGetLastError();
+}
+
 hipError_t launch_select_count(hipStream_t st, const float* feat, int ldf, const int64_t* off,
                                int64_t n_events, float c0, int limit, uint8_t* keep,
                                int32_t* cnt) {

@@ -187,8 +187,6 @@ template <typename T>
 int iterate(fmd_server* S, std::vector<Req*>& finished) {
   fmd_model* m = S->m;
   Workspace& w = m->ws;
-  const int qt = attention_query_tile(m->cfg.precision == FMD_BF16, m->cfg.d_model / m->cfg.n_heads,
-                                      m->cfg.n_heads);
   std::vector<Req*> res = S->resident;
   std::sort(res.begin(), res.end(), [](Req* a, Req* b) { return a->base < b->base; });
   // segments: dummy gaps and real events, in pool order
@@ -219,13 +217,15 @@ int iterate(fmd_server* S, std::vector<Req*>& finished) {
       desc.push_back(sd);
       tev.push_back(sd.t);
       pos += n;
-      items += (n + qt - 1) / qt;
       sum_n2 += (double)n * (double)n;
       sum_nx += (double)n * (double)nt;
     }
   }
   const int64_t E = (int64_t)desc.size(), span = pos;
   if (span == 0) return FMD_OK;
+  // work items of the query tile tuned for this size (the default where none is)
+  const int qt = attn_tile_for(m, round_up(span, kGemmBM));
+  for (const auto& rs : real) items += (rs.second + qt - 1) / qt;
   // self-attention items, then cross-attention items (reco queries, truth keys)
   FMD_TRY(ensure_ws(m, span, E, 2 * items));
   std::memcpy(w.h_off, off.data(), (size_t)(E + 1) * 8);
@@ -256,6 +256,7 @@ int iterate(fmd_server* S, std::vector<Req*>& finished) {
   c.E = E;
   c.T = span;
   c.Tp = round_up(span, kGemmBM);
+  c.qt = qt;
   c.items = items;
   c.bins = bins;
   c.sum_n2 = sum_n2;

@@ -20,6 +20,7 @@ EULER, RK4, MIDPOINT = 0, 1, 2
 (K_GEMM_QKV, K_GEMM_PROJ, K_GEMM_QC, K_GEMM_UP, K_GEMM_DOWN, K_FUSED_OQC, K_FUSED_MLP,
  K_ATTN_SELF, K_ATTN_CROSS, K_OTHER) = range(10)
 FUSED_QKV, FUSED_OQC, FUSED_MLP, FUSED_EMBED, FUSED_ALL = 1, 2, 4, 8, 15
+TUNE_ATTN_QUERY_TILE, TUNE_FUSED_QKV, TUNE_FUSED_OQC = 5, 6, 7
 KERNEL_CLASSES = ("gemm_qkv", "gemm_proj", "gemm_qc", "gemm_up", "gemm_down", "fused_oqc",
                   "fused_mlp", "attn_self", "attn_cross", "other")
 
@@ -64,6 +65,11 @@ class ServerInfo(ctypes.Structure):
                                         "rows_processed", "busy_ns")]
 
 
+class MultiplicityLaw(ctypes.Structure):
+    _fields_ = [("loss_prob", ctypes.c_double), ("fake_prob", ctypes.c_double),
+                ("fake_trials", c_int32)]
+
+
 class FmdError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"fmd status {status}: {msg}")
@@ -104,6 +110,9 @@ def lib():
                                             c_void_p]),
         "fmd_truth_select": (c_int32, [ctypes.POINTER(EventsIn), ctypes.c_double, c_int32, P_int64,
                                        c_void_p, c_void_p]),
+        "fmd_reco_multiplicity": (c_int32, [P_int64, c_int64, ctypes.c_uint64,
+                                            ctypes.POINTER(MultiplicityLaw), c_int32, P_int64,
+                                            c_void_p]),
         "fmd_truth_select_noalloc": (c_int32, [ctypes.POINTER(EventsIn), ctypes.c_double, c_int32,
                                                P_int64, c_void_p, c_void_p]),
         "fmd_debug_philox": (c_int32, [ctypes.c_uint64, ctypes.c_uint64, c_void_p, c_int64,
@@ -119,6 +128,7 @@ def lib():
         "fmd_graphs_enable": (c_int32, [c_void_p, c_int32]),
         "fmd_fused_enable": (c_int32, [c_void_p, c_int32]),
         "fmd_tuning_table": (c_int32, [c_void_p, ctypes.c_char_p, c_size_t, ctypes.POINTER(c_size_t)]),
+        "fmd_tuning_set": (c_int32, [c_void_p, c_int32, c_int32, c_int32]),
         "fmd_server_create": (c_int32, [c_void_p, ctypes.POINTER(ServerConfig), ctypes.POINTER(c_void_p)]),
         "fmd_server_submit": (c_int32, [c_void_p, ctypes.POINTER(EventsIn), ctypes.c_uint64,
                                         ctypes.POINTER(Schedule), ctypes.POINTER(ctypes.c_uint64)]),
@@ -326,6 +336,11 @@ class Model:
         _check(lib().fmd_tuning_table(self._h, buf, need.value, None))
         return json.loads(buf.value.decode())
 
+    def tuning_set(self, site, tokens_log2, candidate):
+        """Fixes the autotuner's choice for a fused-path site (TUNE_ATTN_QUERY_TILE,
+        TUNE_FUSED_QKV, TUNE_FUSED_OQC) and a log2 token bucket: candidate 0 (64) or 1 (128)."""
+        _check(lib().fmd_tuning_set(self._h, int(site), int(tokens_log2), int(candidate)))
+
     def kernel_name(self, cls):
         return lib().fmd_kernel_name(self._h, int(cls)).decode()
 
@@ -450,6 +465,19 @@ def truth_select(offsets, feat, pt_cut_gev, max_particles, stream=None):
     _check(lib().fmd_truth_select(ctypes.byref(ev), float(pt_cut_gev), int(max_particles),
                                   out_off.ctypes.data_as(P_int64), op, _stream(stream)))
     return out_off, out[: int(out_off[-1])]
+
+
+def reco_multiplicity(offsets, seed, loss_prob, fake_prob, fake_trials, n_max, stream=None):
+    """Reco offsets [E+1] int64 (NumPy) drawn on the device under the stand-in multiplicity
+    law (truth particles missed with probability loss_prob, Binomial(fake_trials, fake_prob)
+    extra slots, at most n_max per event), to pass as reco_offsets to Model.simulate."""
+    off, p = _offsets(offsets)
+    out = np.zeros(len(off), dtype=np.int64)
+    law = MultiplicityLaw(float(loss_prob), float(fake_prob), int(fake_trials))
+    _check(lib().fmd_reco_multiplicity(p, len(off) - 1, ctypes.c_uint64(seed & (2**64 - 1)),
+                                       ctypes.byref(law), int(n_max), out.ctypes.data_as(P_int64),
+                                       _stream(stream)))
+    return out
 
 
 def truth_select_noalloc(offsets, feat, pt_cut_gev, max_particles, out, stream=None):
