@@ -60,7 +60,9 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def time_path(fmd, torch, cfg, flat, off, feat_d, w, steps, warmup, timing):
+def time_path(fmd, torch, cfg, flat, off, feat_d, w, steps, warmup, timing, per_step=False):
+    """Times `steps` sampling calls after `warmup` untimed ones; with per_step each call is
+    timed on its own (synchronized before and after) and their durations are kept too."""
     m = fmd.Model(cfg, flat)
     out = torch.empty((int(off[-1]), 9), dtype=torch.float32, device="cuda")
     for _ in range(warmup):
@@ -68,12 +70,16 @@ def time_path(fmd, torch, cfg, flat, off, feat_d, w, steps, warmup, timing):
     torch.cuda.synchronize()
     if timing:
         m.timing_enable(True)
+    step_s = []
     t0 = time.perf_counter()
     for _ in range(steps):
         m.simulate(off, feat_d, w.noise_seed, w.schedule, out=out)
+        if per_step:
+            torch.cuda.synchronize()
+            step_s.append(time.perf_counter() - (t0 + sum(step_s)))
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    kern = {}
+    kern = {"_step_s": step_s}
     if timing:
         for cls, name in enumerate(fmd.KERNEL_CLASSES):
             ms, n, work, nbytes = m.timing_read(cls)
@@ -193,6 +199,47 @@ def roofline(kern, dtype, traffic_known=True):
             "share_of_device_time": round(k["ms"] / total_ms, 3)}
 
 
+# FP64 oracle outputs of the first 256 base-workload events, written by
+# tests/golden/make_oracle_outputs.py (which runs the oracle only)
+GOLDEN_BASE = os.path.join(ROOT, "tests", "golden", "oracle_base_rk4x16_first256.npz")
+
+
+def precision_report(off, feat, out16, out32, label="bf16", resp_frac=0.01):
+    """Errors of the BF16 path (and the FP32 one) on the first 256 events against the FP64
+    oracle, BF16 against FP32 on all events, and the pT / eta response (slot i of an event
+    against truth particle i: pT ratio and eta difference, mean and population width) of
+    each source with its agreement with the oracle's at 1%. Normwise per feature:
+    max|dy| / max|ref| (the headline, worst feature); elementwise diagnostic: max |dy| /
+    (|ref| + rms of the feature)."""
+    from workload import errors
+    g = np.load(GOLDEN_BASE)
+    n = len(g["offsets"]) - 1
+    assert np.array_equal(g["offsets"], off[:n + 1]), "golden events differ from the workload"
+    rows = int(off[n])
+    ref = g["reco"]
+    truth = feat[:rows]
+    srcs = {label: out16}
+    if out32 is not None:
+        srcs["fp32"] = out32
+    rep = {"events_checked": n, "oracle": "FP64 oracle outputs of the first 256 events"}
+    resp_ref = errors.response(ref, truth)
+    rep["response_oracle"] = resp_ref
+    for name, y in srcs.items():
+        rep[f"{name}_vs_oracle"] = float(errors.normwise_rel_err(y[:rows], ref).max())
+        rep[f"{name}_vs_oracle_elementwise"] = float(errors.elementwise_rel_err(y[:rows], ref).max())
+        resp = errors.response(y[:rows], truth)
+        rep[f"response_{name}"] = resp
+        frac = resp_frac if name == label else 0.01
+        rep[f"response_{name}_within_{round(frac * 100)}pct_of_oracle"] = errors.response_agrees(
+            resp, resp_ref, frac)
+    if out32 is not None:
+        rep["bf16_vs_fp32_all_events"] = float(errors.normwise_rel_err(out16, out32).max())
+        rep["bf16_vs_fp32_all_events_elementwise"] = float(errors.elementwise_rel_err(out16, out32).max())
+        rep["response_bf16_within_1pct_of_fp32"] = errors.response_agrees(
+            rep["response_bf16"], errors.response(out32[:rows], truth))
+    return rep
+
+
 def cpu_baseline(w, flat, off, feat, sample_events, processes):
     from oracle import sample
     ids = list(range(sample_events))
@@ -204,7 +251,92 @@ def cpu_baseline(w, flat, off, feat, sample_events, processes):
     return dt, np.concatenate(outs)
 
 
-def serve_leg(fmd, w_serve, flat, rates, seconds, budget):
+def event_flops(cfg, n, evals):
+    """Algorithmic flops of sampling one event of n particles with `evals` network evaluations:
+    per evaluation L (28 d^2 n + 8 d n^2) + 4 F d n (matrix products, both attentions, input
+    embedding and output head), plus once per event the truth encoder (2 F d n) and the cross
+    K/V cache (4 L d^2 n)."""
+    d, L, F = cfg.d_model, cfg.n_blocks, 9
+    n = np.asarray(n, dtype=np.float64)
+    return float(np.sum(evals * (L * (28 * d * d * n + 8 * d * n * n) + 4 * F * d * n)
+                        + 2 * F * d * n + 4 * L * d * d * n))
+
+
+def run_rate(fmd, srv, reqs, model_cfg):
+    """Submits `reqs` at their arrival times (open loop, from a thread) and collects them;
+    returns the latency and throughput record."""
+    import threading
+
+    n_req = len(reqs)
+    ids = [None] * n_req
+    t_start = time.perf_counter()
+
+    def submit():
+        for i, r in enumerate(reqs):
+            dt = r.t_arrive - (time.perf_counter() - t_start)
+            if dt > 0:
+                time.sleep(dt)
+            ids[i] = srv.submit(r.offsets, r.feat, r.seed, r.schedule)
+
+    info0 = srv.info()
+    th = threading.Thread(target=submit)
+    th.start()
+    lat_req, lat_ev, n_events, t_first, t_last, flops = [], [], 0, None, None, 0.0
+    for i in range(n_req):
+        while ids[i] is None:
+            time.sleep(0.0005)
+        _, st = srv.wait(ids[i])
+        lat = (st["t_done_ns"] - st["t_submit_ns"]) * 1e-6
+        ne = len(reqs[i].offsets) - 1
+        lat_req.append(lat)
+        lat_ev += [lat] * ne
+        n_events += ne
+        flops += event_flops(model_cfg, np.diff(reqs[i].offsets), reqs[i].schedule.evals)
+        t_first = st["t_submit_ns"] if t_first is None else min(t_first, st["t_submit_ns"])
+        t_last = st["t_done_ns"] if t_last is None else max(t_last, st["t_done_ns"])
+    th.join()
+    info1 = srv.info()
+    wall = (t_last - t_first) * 1e-9
+    rows = info1["rows_processed"] - info0["rows_processed"]
+    return {"requests": n_req, "events": n_events,
+            "achieved_events_per_s": round(n_events / wall, 1),
+            "p50_event_ms": round(float(np.percentile(lat_ev, 50)), 2),
+            "p99_event_ms": round(float(np.percentile(lat_ev, 99)), 2),
+            "p50_request_ms": round(float(np.percentile(lat_req, 50)), 2),
+            "p99_request_ms": round(float(np.percentile(lat_req, 99)), 2),
+            "device_busy_frac": round((info1["busy_ns"] - info0["busy_ns"]) * 1e-9 / wall, 3),
+            "live_row_frac": round((info1["rows_live"] - info0["rows_live"]) / max(rows, 1), 3),
+            "iterations": info1["iterations"] - info0["iterations"],
+            "mfma_frac": round(flops / wall / (PEAK_TFLOPS["bf16"] * 1e12), 4)}
+
+
+def batch_reference(fmd, torch, model, reqs, model_cfg):
+    """The batch path on the same events and schedules as `reqs`: one fmd_simulate call per
+    schedule over all its events (inputs resident on the device), timed after a warm-up."""
+    groups = {}
+    for r in reqs:
+        groups.setdefault((r.schedule.scheme, r.schedule.n_steps), []).append(r)
+    calls = []
+    for key, rs in groups.items():
+        off = np.r_[0, np.cumsum(np.concatenate([np.diff(r.offsets) for r in rs]))].astype(np.int64)
+        feat = torch.from_numpy(np.concatenate([r.feat for r in rs])).cuda()
+        out = torch.empty((int(off[-1]), 9), dtype=torch.float32, device="cuda")
+        calls.append((off, feat, out, rs[0].schedule))
+    for off, feat, out, sch in calls:
+        model.simulate(off, feat, 5, sch, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for off, feat, out, sch in calls:
+        model.simulate(off, feat, 5, sch, out=out)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    n_ev = sum(len(off) - 1 for off, _, _, _ in calls)
+    flops = sum(event_flops(model_cfg, np.diff(r.offsets), r.schedule.evals) for r in reqs)
+    return {"events": n_ev, "events_per_s": round(n_ev / dt, 1),
+            "mfma_frac": round(flops / dt / (PEAK_TFLOPS["bf16"] * 1e12), 4)}
+
+
+def serve_leg(fmd, torch, w_serve, flat, rates, n_requests, budget):
     """Open-loop Poisson load on the continuous-batching server, one run per offered rate.
 
     Requests arrive at exponential gaps (mean = E[events per request] / rate). Each carries
@@ -212,57 +344,35 @@ def serve_leg(fmd, w_serve, flat, rates, seconds, budget):
     probability 1/2. They are submitted at their arrival times whatever the server's state,
     so queueing counts in the latency. Latency = completion - submission on the server's
     monotonic clock, weighted per event (each event takes its request's latency) and per
-    request.
+    request. A warm-up stream runs first (allocation and tuning of the sizes it meets). The
+    saturation throughput is the largest achieved rate; the batch path is timed on the
+    request mix of the highest rate for comparison.
     """
-    import threading
-
     from workload import arrivals
 
+    cfg = w_serve.model
     out = []
-    m = fmd.Model(w_serve.model, flat)
+    m = fmd.Model(cfg, flat)
     srv = fmd.Server(m, hbm_budget_bytes=budget)
-    for rate in rates:
-        n_req = max(4, int(rate * seconds / 256.5))
-        reqs = arrivals.stream(rate, n_req, seed=w_serve.extra["arrival_seed"])
-        ids = [None] * n_req
-        t_start = time.perf_counter()
-
-        def submit():
-            for i, r in enumerate(reqs):
-                dt = r.t_arrive - (time.perf_counter() - t_start)
-                if dt > 0:
-                    time.sleep(dt)
-                ids[i] = srv.submit(r.offsets, r.feat, r.seed, r.schedule)
-
-        th = threading.Thread(target=submit)
-        th.start()
-        lat_req, lat_ev, n_events, t_first, t_last = [], [], 0, None, None
-        for i in range(n_req):
-            while ids[i] is None:
-                time.sleep(0.0005)
-            _, st = srv.wait(ids[i])
-            lat = (st["t_done_ns"] - st["t_submit_ns"]) * 1e-6
-            ne = len(reqs[i].offsets) - 1
-            lat_req.append(lat)
-            lat_ev += [lat] * ne
-            n_events += ne
-            t_first = st["t_submit_ns"] if t_first is None else min(t_first, st["t_submit_ns"])
-            t_last = st["t_done_ns"] if t_last is None else max(t_last, st["t_done_ns"])
-        th.join()
-        wall = (t_last - t_first) * 1e-9
-        rec = {"offered_events_per_s": rate, "requests": n_req, "events": n_events,
-               "achieved_events_per_s": round(n_events / wall, 1),
-               "p50_event_ms": round(float(np.percentile(lat_ev, 50)), 2),
-               "p99_event_ms": round(float(np.percentile(lat_ev, 99)), 2),
-               "p50_request_ms": round(float(np.percentile(lat_req, 50)), 2),
-               "p99_request_ms": round(float(np.percentile(lat_req, 99)), 2)}
+    seed = w_serve.extra["arrival_seed"]
+    run_rate(fmd, srv, arrivals.stream(20000.0, max(20, n_requests // 2), seed=seed + 100), cfg)
+    last = None
+    for i, rate in enumerate(rates):
+        reqs = arrivals.stream(rate, n_requests, seed=seed + i)
+        rec = {"offered_events_per_s": rate, **run_rate(fmd, srv, reqs, cfg)}
         log(f"serve @ {rate} ev/s offered: {rec}")
         out.append(rec)
+        last = reqs
     info = srv.info()
     srv.close()
+    batch = batch_reference(fmd, torch, m, last, cfg)
     m.close()
-    return {"rates": out, "hbm_budget_bytes": budget, "pool_tokens": info["pool_tokens"],
-            "iterations": info["iterations"]}
+    sat = max(r["achieved_events_per_s"] for r in out)
+    log(f"serve: saturation {sat} events/s; batch path on the same mix {batch}")
+    return {"rates": out, "saturation_events_per_s": sat,
+            "batch_path_same_mix": batch, "saturation_vs_batch": round(sat / batch["events_per_s"], 3),
+            "hbm_budget_bytes": budget, "pool_tokens": info["pool_tokens"],
+            "requests_per_rate": n_requests}
 
 
 def main():
@@ -270,14 +380,16 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--fp32-steps", type=int, default=1)
+    ap.add_argument("--fp32-steps", type=int, default=5, help="FP32 calls timed (median reported)")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp8", action="store_true", help="skip the FP8-operand leg")
+    ap.add_argument("--fp8-steps", type=int, default=3)
     ap.add_argument("--cpu-sample", type=int, default=0, help="oracle events (0: 6 per core)")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-reco", action="store_true", help="skip the reco-multiplicity leg")
-    ap.add_argument("--serve-rates", default="1000,2000,5000")
-    ap.add_argument("--serve-seconds", type=float, default=4.0)
+    ap.add_argument("--serve-rates", default="1000,2000,5000,10000,20000,50000")
+    ap.add_argument("--serve-requests", type=int, default=200, help="requests per offered rate")
     ap.add_argument("--workload", choices=["base", "batch"], default="base",
                     help="base: 4096 events, N~U{20..200} (the headline); batch: 65,536 events "
                          "with heavy-tailed N (FP32, reco and serving legs skipped)")
@@ -352,12 +464,33 @@ def main():
     out32 = None
     if not a.no_fp32:
         cfg32 = w.model.with_precision(configs.FP32)
-        dt32, out32, kern32 = time_path(fmd, torch, cfg32, flat, off, feat_d, w, a.fp32_steps, 1, True)
-        ev32 = E * a.fp32_steps / dt32
-        log(f"fp32: {dt32 / a.fp32_steps * 1e3:.1f} ms/step, {ev32:.1f} events/s")
+        dt32, out32, kern32 = time_path(fmd, torch, cfg32, flat, off, feat_d, w, a.fp32_steps, 1,
+                                        True, per_step=True)
+        med32 = float(np.median(kern32["_step_s"]))
+        ev32 = E / med32
+        log(f"fp32: median {med32 * 1e3:.1f} ms/step over {a.fp32_steps}, {ev32:.1f} events/s")
         rl32 = roofline(kern32, "fp32")
-        fp32 = {"events_per_s": round(ev32, 2), "ms_per_step": round(dt32 / a.fp32_steps * 1e3, 2),
+        fp32 = {"events_per_s": round(ev32, 2), "ms_per_step": round(med32 * 1e3, 2),
+                "steps": a.fp32_steps, "timing": "median of per-call times",
                 "roofline": rl32, "tiles": kern32["_tiles"]}
+
+    fp8 = None
+    if not a.no_fp8 and a.workload == "base":
+        cfg8 = w.model.with_precision(configs.FP8)
+        dt8, out8, kern8 = time_path(fmd, torch, cfg8, flat, off, feat_d, w, a.fp8_steps, 1, True,
+                                     per_step=True)
+        med8 = float(np.median(kern8["_step_s"]))
+        rl8 = roofline(kern8, "bf16", traffic_known=False)
+        mlp = kern8["fused_mlp"]
+        fp8 = {"events_per_s": round(E / med8, 2), "ms_per_step": round(med8 * 1e3, 2),
+               "steps": a.fp8_steps, "timing": "median of per-call times",
+               "precision": "fp8 (e4m3) operands for W_up and W_dn, bf16 elsewhere, fp32 "
+                            "accumulation and state",
+               "mlp_kernel_ms_per_launch": round(mlp["ms"] / max(mlp["launches"], 1), 4),
+               "dominant_kernel": {k: rl8[k] for k in ("kernel", "avg_launch_ms", "tflops")},
+               "error": precision_report(off, feat, out8, None, label="fp8", resp_frac=0.03)}
+        log(f"fp8: median {med8 * 1e3:.1f} ms/step, {fp8['events_per_s']} events/s, "
+            f"error {fp8['error']['fp8_vs_oracle']:.3e}")
 
     cpu = None
     err = None
@@ -369,17 +502,16 @@ def main():
         cpu = {"value": round(n / dt_cpu, 4), "unit": "events/s", "cores": cores, "kind": "oracle",
                "sample": f"first {n} events of the workload ({rows} particles), full RK4 16 "
                          f"integration in NumPy float64, {cores} processes, {dt_cpu:.1f} s"}
-        err = {"bf16_vs_oracle": float(errors.normwise_rel_err(out16[:rows], ref).max()),
-               "events_checked": n}
-        if out32 is not None:
-            err["fp32_vs_oracle"] = float(errors.normwise_rel_err(out32[:rows], ref).max())
-        log(f"oracle: {cpu['value']} events/s on {cores} cores; errors {err}")
+        log(f"oracle: {cpu['value']} events/s on {cores} cores")
+    if a.workload == "base":
+        err = precision_report(off, feat, out16, out32)
+        log(f"errors: {json.dumps(err)}")
 
     serve = None
     if not a.no_serve:
         ws = configs.SERVE_BF16
         rates = [float(r) for r in a.serve_rates.split(",") if r]
-        serve = serve_leg(fmd, ws, flat, rates, a.serve_seconds, ws.extra["hbm_budget_bytes"])
+        serve = serve_leg(fmd, torch, ws, flat, rates, a.serve_requests, ws.extra["hbm_budget_bytes"])
 
     line = {
         "metric": "sampled events/s, BF16 vs FP32 plain at stated error; p50/p99 event latency",
@@ -392,7 +524,7 @@ def main():
                    "tiles": kern16["_tiles"]},
         "graph_replay": graph, "fp32": fp32, "error": err,
         "latency": serve, "truth_selection": selection, "observables": obs,
-        "reco_multiplicity": reco,
+        "reco_multiplicity": reco, "fp8": fp8,
         "roofline": rl, "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -53,7 +53,13 @@ typedef enum {
 
 typedef struct fmd_model fmd_model;     /* opaque */
 
-enum { FMD_FP32 = 0, FMD_BF16 = 1 };   /* precision of GEMM / attention operands */
+/* Precision of GEMM / attention operands. FMD_FP8: the BF16 form with the two MLP projections
+ * on FP8 (OCP e4m3) operands: the LayerNorm output and the GELU output rounded to e4m3, W_up
+ * and W_dn times a power of two per output column rounded to e4m3, FP32 accumulation; the
+ * paper lets the user trade generation speed for quality (Sec. 2.2), and this is one more
+ * such step. It exists for the fused kernels' shape only (d_model 256, 8 heads of 32, MLP
+ * ratio 4; FMD_E_UNSUPPORTED otherwise). */
+enum { FMD_FP32 = 0, FMD_BF16 = 1, FMD_FP8 = 2 };
 /* integration scheme: Euler (one evaluation per step, the paper's), classic RK4 (four),
  * explicit midpoint (two: x <- x + h v(x + h/2 v(x, t), t + h/2)) */
 enum { FMD_EULER = 0, FMD_RK4 = 1, FMD_MIDPOINT = 2 };
@@ -375,11 +381,14 @@ int fmd_debug_attention(int32_t precision, int64_t n_events, const int64_t* q_of
 /* ---- serving ----------------------------------------------------------------------------- */
 
 /* A continuous-batching server over one model. Requests are admitted FIFO when a
- * contiguous range of their particle count is free in a device token pool. The pool is
- * sized as hbm_budget_bytes divided by the per-token footprint: ODE state, activations,
- * truth encoding, cross K/V cache and output. An admitted request's state stays on the
- * device until it completes.
- * Each server iteration advances every resident event by one stage of its own schedule.
+ * contiguous range of their particle count, rounded up to whole 64-row tiles, is free in a
+ * device token pool. The pool is sized as hbm_budget_bytes divided by the per-token
+ * footprint (ODE state, activations, truth encoding, cross K/V cache and output), rounded
+ * down to whole tiles. An admitted request's state stays on the device until it completes.
+ * Each server iteration advances every resident event by one stage of its own schedule; the
+ * block kernels run only the tiles of resident requests. The worker enqueues the next
+ * iteration before it waits for the current one to end, so the device does not idle while
+ * the host prepares work.
  * Euler and RK4 requests and requests at different points of their integration share
  * one launch. A request's result is bitwise the same alone and in any mix: noise is
  * keyed by (seed, event index in the request, slot). The batch-of-the-paper knob
@@ -398,9 +407,13 @@ typedef struct {
   uint64_t t_submit_ns, t_admit_ns, t_done_ns;   /* CLOCK_MONOTONIC */
 } fmd_request_stats;
 
+/* Server counters: pool size (rows) and bytes per row; requests queued and resident and the
+ * rows they hold; iterations run; rows processed by them (the span from the first pool row
+ * to the last resident one, gaps between requests included) and the live rows among them;
+ * device time of the iterations (admission included), in nanoseconds. */
 typedef struct {
   int64_t pool_tokens, bytes_per_token, queued_requests, resident_requests, resident_tokens;
-  int64_t iterations, rows_processed, busy_ns;
+  int64_t iterations, rows_processed, busy_ns, rows_live;
 } fmd_server_info;
 
 /* Starts the worker thread. FMD_E_BUDGET if the budget holds less than one particle. */

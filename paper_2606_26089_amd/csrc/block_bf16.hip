@@ -517,20 +517,33 @@ struct EmbedRows {
 constexpr int kEmbLd = 16;     // pitch of the ODE state rows
 constexpr int kEmbF9 = 9;
 
+// Which row tiles a launch covers: tile b of the grid is rows [ROWS t, ROWS t + ROWS) with
+// t = tiles[b] when a map is given (the serving loop skips the tiles of gaps between
+// requests), t = b otherwise. Mp is the padded row count of the call: the head-major planes
+// hold Mp rows each, whatever tiles run.
+struct RowMap {
+  const int32_t* tiles;
+  int64_t Mp;
+  __device__ __forceinline__ int64_t first_row(int rows) const {
+    return (int64_t)(tiles ? tiles[blockIdx.x] : (int32_t)blockIdx.x) * rows;
+  }
+};
+
 template <int TM, bool EMBED>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(TM == 2 ? 4 : 2))) void k_fused_qkv(const float* __restrict__ H,
                                                         const float* __restrict__ g,
                                                         const float* __restrict__ s,
                                                         const u32x4* __restrict__ Wf,
                                                         const float* __restrict__ bias,
-                                                        bf16* __restrict__ qkv, EmbedRows em) {
+                                                        bf16* __restrict__ qkv, EmbedRows em,
+                                                        RowMap rm) {
   constexpr int ROWS = 32 * TM;
   __shared__ __attribute__((aligned(16))) bf16 A[ROWS * kLdA];
   __shared__ SharedLn sl;
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int64_t m0 = (int64_t)blockIdx.x * ROWS;
-  const int64_t plane = (int64_t)gridDim.x * ROWS * kDh;   // Mp rows x 32 per head
+  const int64_t m0 = rm.first_row(ROWS);
+  const int64_t plane = rm.Mp * kDh;   // Mp rows x 32 per head
   const int col = w * 32 + (lane & 31);
   const u32x4* wf = Wf + w * kKs * 64;            // slab s: + s * kWaves * kKs * 64
   u32x4 ring[kRing];
@@ -582,14 +595,15 @@ template <int TM>
 __global__ __launch_bounds__(kThreads) void k_fused_oqc(
     const bf16* __restrict__ att, const u32x4* __restrict__ Wf_o, const float* __restrict__ b_o,
     float* __restrict__ H, const float* __restrict__ g, const float* __restrict__ s,
-    const u32x4* __restrict__ Wf_qc, const float* __restrict__ b_qc, bf16* __restrict__ qc) {
+    const u32x4* __restrict__ Wf_qc, const float* __restrict__ b_qc, bf16* __restrict__ qc,
+    RowMap rm) {
   constexpr int ROWS = 32 * TM;
   __shared__ __attribute__((aligned(16))) bf16 A[ROWS * kLdA];
   __shared__ SharedLn sl;
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int64_t m0 = (int64_t)blockIdx.x * ROWS;
-  const int64_t plane = (int64_t)gridDim.x * ROWS * kDh;   // Mp rows x 32 per head
+  const int64_t m0 = rm.first_row(ROWS);
+  const int64_t plane = rm.Mp * kDh;   // Mp rows x 32 per head
   const int col = w * 32 + (lane & 31);
   const u32x4* wo = Wf_o + w * kKs * 64;
   const u32x4* wq = Wf_qc + w * kKs * 64;
@@ -608,6 +622,54 @@ __global__ __launch_bounds__(kThreads) void k_fused_oqc(
   zero(acc, b_qc, col);
   mfma_phase<TM>(acc, A, kLdA, 0, kKs, ring, wq, wq, lane);
   store_rows_bf16<kDh>(acc, qc + (int64_t)w * plane, m0, lane & 31, lane);   // head-major
+}
+
+// ---- FP8 (OCP e4m3) operands of the MLP's two projections (the FP8 precision form).
+// The LayerNorm tile and the hidden chunks are FP8 bytes in LDS; W_up and W_dn are FP8
+// fragments of the weights times a power of two per output column (so that the column's
+// largest magnitude lies in (224, 448]) for the 32 x 32 x 64 matrix instruction: fragment
+// (nb, ks) of lane l holds W[64 ks + 32 (l/32) + j][32 nb + l%32] s_col, j < 32, as 32 bytes,
+// stored [N/32][K/64][64 lanes]. A operands from LDS take the same k order (row l%32, bytes
+// 64 ks + 32 (l/32) ..), so products pair the same k on both sides. The up-projection output
+// is scaled back by 1/s per hidden column before the GELU; the down-projection accumulates
+// onto the residual rows multiplied by s per output column and divides by it afterwards,
+// exact for powers of two. Accumulation, statistics, GELU and residual stay FP32.
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+
+struct Mlp8 {
+  const i32x8* up;      // W_up s_up fragments [1024/32][256/64][64]
+  const i32x8* dn;      // W_dn s_dn fragments [256/32][1024/64][64]
+  const float* up_inv;  // 1 / s_up per hidden column [1024]
+  const float* dn_scale;   // s_dn per output column [256]
+  const float* dn_inv;  // 1 / s_dn [256]
+};
+
+constexpr int kLdA8 = kD + 16;        // bytes per row of the FP8 LayerNorm tile
+constexpr int kLdH8 = kBH + 16;       // bytes per row of an FP8 hidden chunk
+constexpr int kKs8 = kD / 64;         // 64-deep K steps over d
+
+__device__ __forceinline__ f32x16 mfma_f8(i32x8 a, i32x8 b, f32x16 c) {
+  // block scales 2^(127 - 127) = 1: plain FP8 x FP8 products
+  return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 0, 127, 0, 127);
+}
+
+// x rounded to the nearest e4m3 value (ties to even), as one byte
+__device__ __forceinline__ uint32_t to_fp8(float x) {
+  return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(x, x, 0, false) & 0xFFu;
+}
+
+// A operand of one 32-row block: row `row` of an FP8 tile (pitch ld bytes), K step ks
+__device__ __forceinline__ i32x8 lds_frag8(const uint8_t* __restrict__ t, int ld, int row, int ks,
+                                           int lane) {
+  const uint8_t* p = t + row * ld + ks * 64 + (lane >> 5) * 32;
+  const u32x4 lo = *(const u32x4*)p, hi = *(const u32x4*)(p + 16);
+  i32x8 r;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    r[i] = (int)lo[i];
+    r[4 + i] = (int)hi[i];
+  }
+  return r;
 }
 
 // MLP block on 64-row tiles with four waves: two workgroups share a CU, one wave of each per
@@ -636,13 +698,13 @@ struct NextHead {
 
 enum MlpTail { kTailStats = 0, kTailQkv = 1, kTailHead = 2 };
 
-template <int TM, int TAIL>
+template <int TM, int TAIL, bool F8>
 __global__ __launch_bounds__(kThreads4) __attribute__((amdgpu_waves_per_eu(2))) void k_fused_mlp(
     const bf16* __restrict__ att, const u32x4* __restrict__ Wf_oc, const float* __restrict__ b_oc,
     float* __restrict__ H, const float* __restrict__ g, const float* __restrict__ s,
     const u32x4* __restrict__ Wf_up, const float* __restrict__ b_up,
     const u32x4* __restrict__ Wf_dn, const float* __restrict__ b_dn,
-    float2* __restrict__ stats_out, NextQkv nq, NextHead nh) {
+    float2* __restrict__ stats_out, NextQkv nq, NextHead nh, Mlp8 f8, RowMap rm) {
   constexpr bool QKV = TAIL == kTailQkv;
   constexpr int ROWS = 32 * TM;
   static_assert(ROWS == 64, "statistics scratch sized for 64 rows");
@@ -651,7 +713,7 @@ __global__ __launch_bounds__(kThreads4) __attribute__((amdgpu_waves_per_eu(2))) 
   __shared__ SharedLn4 sl;
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int64_t m0 = (int64_t)blockIdx.x * ROWS;
+  const int64_t m0 = rm.first_row(ROWS);
   const int col0 = 64 * w + (lane & 31);     // column of block nj: col0 + 32 nj
   constexpr int kChunks = 4 * kD / kBH;      // 8
   constexpr int kDnKs = kBH / 16;            // 8 K steps per down-projection chunk
@@ -663,7 +725,7 @@ __global__ __launch_bounds__(kThreads4) __attribute__((amdgpu_waves_per_eu(2))) 
   u32x4 ring[kRing];
   ring_fill_nc<2>(ring, woc, kOcStride, lane);
   // head-major attention output [8 heads][Mp][32]
-  tile_hm_to_lds<ROWS, kThreads4>(A, att, (int64_t)gridDim.x * ROWS * kDh, m0, tid);
+  tile_hm_to_lds<ROWS, kThreads4>(A, att, rm.Mp * kDh, m0, tid);
   f32x16 acc[TM][2];
 #pragma unroll
   for (int nj = 0; nj < 2; ++nj) {
@@ -677,66 +739,147 @@ __global__ __launch_bounds__(kThreads4) __attribute__((amdgpu_waves_per_eu(2))) 
   __syncthreads();
   mfma_phase_nc<TM, 2, kKs, 1, false>(acc, A, kLdA, 0, ring, woc, kOcStride, woc, 0, lane);
   row_stats_nc(acc, sl, nullptr, m0, lane, w);   // barriers: A reads done
-  ring_fill_nc<1>(ring, up_c(0), 0, lane);
-  {
-    const float* mu = sl.mu[w];
-    const float* rs = sl.rs[w];
+  if constexpr (!F8) {
+    ring_fill_nc<1>(ring, up_c(0), 0, lane);
+    {
+      const float* mu = sl.mu[w];
+      const float* rs = sl.rs[w];
 #pragma unroll
-    for (int nj = 0; nj < 2; ++nj) {
-      const int col = col0 + 32 * nj;
-      const float gv = g[col], sv = s[col];
+      for (int nj = 0; nj < 2; ++nj) {
+        const int col = col0 + 32 * nj;
+        const float gv = g[col], sv = s[col];
+#pragma unroll
+        for (int mi = 0; mi < TM; ++mi)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const int row = acc_row(mi, r, lane);
+            A[row * kLdA + col] = (bf16)((acc[mi][nj][r] - mu[row]) * rs[row] * gv + sv);
+          }
+      }
+    }
+    __syncthreads();
+    const int hcol = 32 * w + (lane & 31);
+    f32x16 h2[2][TM][1];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
 #pragma unroll
       for (int mi = 0; mi < TM; ++mi)
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int row = acc_row(mi, r, lane);
-          A[row * kLdA + col] = (bf16)((acc[mi][nj][r] - mu[row]) * rs[row] * gv + sv);
-        }
-    }
-  }
-  __syncthreads();
-  const int hcol = 32 * w + (lane & 31);
-  f32x16 h2[2][TM][1];
+        for (int r = 0; r < 16; ++r) h2[u][mi][0][r] = 0.f;
+    mfma_phase_nc<TM, 1, kKs, 1, true>(h2[0], A, kLdA, 0, ring, up_c(0), 0, up_c(1), 0, lane);
+    // chunk cc: [up-projection cc+1 | GELU cc] -> barrier -> down-projection cc. Weight stream
+    // order: up 0, up 1, down 0, up 2, down 1, ..., up 7, down 6, down 7.
+#pragma unroll 1
+    for (int c = 0; c < kChunks - 2; c += 2) {
 #pragma unroll
-  for (int u = 0; u < 2; ++u)
+      for (int u = 0; u < 2; ++u) {
+        const int cc = c + u;
+#pragma unroll
+        for (int mi = 0; mi < TM; ++mi)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) h2[u ^ 1][mi][0][r] = 0.f;
+        up_gelu_nc<true, TM, 2>(h2[u ^ 1], h2[u], A, ring, up_c(cc + 1), dn_c(cc), kDnStride,
+                                kGeluU * b_up[cc * kBH + hcol], Hc[u], hcol, lane);
+        __syncthreads();
+        mfma_phase_nc<TM, 2, kDnKs, 1, true>(acc, Hc[u], kLdH, 0, ring, dn_c(cc), kDnStride,
+                                             up_c(cc + 2), 0, lane);
+      }
+    }
+    // chunks 6 and 7
 #pragma unroll
     for (int mi = 0; mi < TM; ++mi)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) h2[u][mi][0][r] = 0.f;
-  mfma_phase_nc<TM, 1, kKs, 1, true>(h2[0], A, kLdA, 0, ring, up_c(0), 0, up_c(1), 0, lane);
-  // chunk cc: [up-projection cc+1 | GELU cc] -> barrier -> down-projection cc. Weight stream
-  // order: up 0, up 1, down 0, up 2, down 1, ..., up 7, down 6, down 7.
-#pragma unroll 1
-  for (int c = 0; c < kChunks - 2; c += 2) {
+      for (int r = 0; r < 16; ++r) h2[1][mi][0][r] = 0.f;
+    up_gelu_nc<true, TM, 2>(h2[1], h2[0], A, ring, up_c(7), dn_c(6), kDnStride,
+                            kGeluU * b_up[6 * kBH + hcol], Hc[0], hcol, lane);
+    __syncthreads();
+    mfma_phase_nc<TM, 2, kDnKs, 2, true>(acc, Hc[0], kLdH, 0, ring, dn_c(6), kDnStride, dn_c(7),
+                                         kDnStride, lane);
+    up_gelu_nc<false, TM, 2>(h2[0], h2[1], A, ring, up_c(7), dn_c(7), kDnStride,
+                             kGeluU * b_up[7 * kBH + hcol], Hc[1], hcol, lane);
+    __syncthreads();
+    mfma_phase_nc<TM, 2, kDnKs, 2, false>(acc, Hc[1], kLdH, 0, ring, dn_c(7), kDnStride, dn_c(7),
+                                          kDnStride, lane);
+  } else {
+    // FP8 operands for W_up and W_dn: the LayerNorm tile and the hidden chunks as e4m3 bytes
+    // (aliasing the BF16 tile and chunk buffers), the residual rows in W_dn's scaled domain
+    uint8_t* A8 = reinterpret_cast<uint8_t*>(A);
+    uint8_t* H8 = reinterpret_cast<uint8_t*>(&Hc[0][0]);
+    {
+      const float* mu = sl.mu[w];
+      const float* rs = sl.rs[w];
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int cc = c + u;
+      for (int nj = 0; nj < 2; ++nj) {
+        const int col = col0 + 32 * nj;
+        const float gv = g[col], sv = s[col], sd = f8.dn_scale[col];
+#pragma unroll
+        for (int mi = 0; mi < TM; ++mi)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const int row = acc_row(mi, r, lane);
+            A8[row * kLdA8 + col] = (uint8_t)to_fp8((acc[mi][nj][r] - mu[row]) * rs[row] * gv + sv);
+            acc[mi][nj][r] *= sd;
+          }
+      }
+    }
+    const int hcol = 32 * w + (lane & 31);
+    // up-projection fragments of the current chunk (column block 4 c + w, 4 K steps) and
+    // down-projection fragments (column blocks 2 w + nj, K steps 2 c + ks)
+    i32x8 fu[kKs8], fd[4];
+#pragma unroll
+    for (int ks = 0; ks < kKs8; ++ks) fu[ks] = f8.up[(w * kKs8 + ks) * 64 + lane];
+    __syncthreads();
+#pragma unroll 1
+    for (int c = 0; c < kChunks; ++c) {
+#pragma unroll
+      for (int nj = 0; nj < 2; ++nj)
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks)
+          fd[2 * nj + ks] = f8.dn[((2 * w + nj) * 16 + 2 * c + ks) * 64 + lane];
+      asm volatile("" ::: "memory");
+      f32x16 h[TM];
 #pragma unroll
       for (int mi = 0; mi < TM; ++mi)
 #pragma unroll
-        for (int r = 0; r < 16; ++r) h2[u ^ 1][mi][0][r] = 0.f;
-      up_gelu_nc<true, TM, 2>(h2[u ^ 1], h2[u], A, ring, up_c(cc + 1), dn_c(cc), kDnStride,
-                              kGeluU * b_up[cc * kBH + hcol], Hc[u], hcol, lane);
+        for (int r = 0; r < 16; ++r) h[mi][r] = 0.f;
+#pragma unroll
+      for (int ks = 0; ks < kKs8; ++ks)
+#pragma unroll
+        for (int mi = 0; mi < TM; ++mi)
+          h[mi] = mfma_f8(lds_frag8(A8, kLdA8, 32 * mi + (lane & 31), ks, lane), fu[ks], h[mi]);
+      if (c + 1 < kChunks) {
+#pragma unroll
+        for (int ks = 0; ks < kKs8; ++ks)
+          fu[ks] = f8.up[((4 * (c + 1) + w) * kKs8 + ks) * 64 + lane];
+      }
+      const float ui = f8.up_inv[c * kBH + hcol], bu = kGeluU * b_up[c * kBH + hcol];
+      uint8_t* hb = H8 + (c & 1) * (ROWS * kLdH8);
+#pragma unroll
+      for (int mi = 0; mi < TM; ++mi)
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+          hb[acc_row(mi, r, lane) * kLdH8 + hcol] = (uint8_t)to_fp8(gelu_as(h[mi][r] * ui, bu));
       __syncthreads();
-      mfma_phase_nc<TM, 2, kDnKs, 1, true>(acc, Hc[u], kLdH, 0, ring, dn_c(cc), kDnStride,
-                                           up_c(cc + 2), 0, lane);
+#pragma unroll
+      for (int ks = 0; ks < 2; ++ks) {
+        i32x8 a[TM];
+#pragma unroll
+        for (int mi = 0; mi < TM; ++mi) a[mi] = lds_frag8(hb, kLdH8, 32 * mi + (lane & 31), ks, lane);
+#pragma unroll
+        for (int nj = 0; nj < 2; ++nj)
+#pragma unroll
+          for (int mi = 0; mi < TM; ++mi) acc[mi][nj] = mfma_f8(a[mi], fd[2 * nj + ks], acc[mi][nj]);
+      }
+    }
+#pragma unroll
+    for (int nj = 0; nj < 2; ++nj) {
+      const float sdi = f8.dn_inv[col0 + 32 * nj];
+#pragma unroll
+      for (int mi = 0; mi < TM; ++mi)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[mi][nj][r] *= sdi;
     }
   }
-  // chunks 6 and 7
-#pragma unroll
-  for (int mi = 0; mi < TM; ++mi)
-#pragma unroll
-    for (int r = 0; r < 16; ++r) h2[1][mi][0][r] = 0.f;
-  up_gelu_nc<true, TM, 2>(h2[1], h2[0], A, ring, up_c(7), dn_c(6), kDnStride,
-                          kGeluU * b_up[6 * kBH + hcol], Hc[0], hcol, lane);
-  __syncthreads();
-  mfma_phase_nc<TM, 2, kDnKs, 2, true>(acc, Hc[0], kLdH, 0, ring, dn_c(6), kDnStride, dn_c(7),
-                                       kDnStride, lane);
-  up_gelu_nc<false, TM, 2>(h2[0], h2[1], A, ring, up_c(7), dn_c(7), kDnStride,
-                           kGeluU * b_up[7 * kBH + hcol], Hc[1], hcol, lane);
-  __syncthreads();
-  mfma_phase_nc<TM, 2, kDnKs, 2, false>(acc, Hc[1], kLdH, 0, ring, dn_c(7), kDnStride, dn_c(7),
-                                        kDnStride, lane);
 #pragma unroll
   for (int nj = 0; nj < 2; ++nj) {
     const float bv = b_dn[col0 + 32 * nj];
@@ -823,7 +966,7 @@ __global__ __launch_bounds__(kThreads4) __attribute__((amdgpu_waves_per_eu(2))) 
       }
     }
     __syncthreads();
-    const int64_t plane = (int64_t)gridDim.x * ROWS * kDh;
+    const int64_t plane = rm.Mp * kDh;
 #pragma unroll 1
     for (int slab = 0; slab < 3; ++slab) {
 #pragma unroll
@@ -882,17 +1025,27 @@ hipError_t launch_pack_frag(hipStream_t st, const float* W, int K, int N, void* 
 // CU and one's loads overlap the other's products) and 128-row tiles (twice the reuse of
 // each weight fragment); the autotuner picks one per token-count bucket.
 
+// Grid of a fused launch: the mapped tiles (64-row tiles only) or all of Mp.
+static bool fused_grid(int64_t Mp, int rows, const int32_t* tiles, int64_t n_tiles, unsigned* grid) {
+  if ((rows != 64 && rows != 128) || Mp % rows || (tiles && (rows != 64 || n_tiles > Mp / 64)))
+    return false;
+  *grid = (unsigned)(tiles ? n_tiles : Mp / rows);
+  return true;
+}
+
 hipError_t launch_fused_qkv(hipStream_t st, int64_t Mp, const float* H, const float* g,
                             const float* s, const void* Wf, const float* bias, void* qkv,
-                            int rows) {
-  if ((rows != 64 && rows != 128) || Mp % rows) return hipErrorInvalidValue;
-  if (Mp == 0) return hipSuccess;
+                            int rows, const int32_t* tiles, int64_t n_tiles) {
+  unsigned grid = 0;
+  if (!fused_grid(Mp, rows, tiles, n_tiles, &grid)) return hipErrorInvalidValue;
+  if (grid == 0) return hipSuccess;
+  const RowMap rm{tiles, Mp};
   if (rows == 64)
-    hipLaunchKernelGGL((k_fused_qkv<2, false>), dim3((unsigned)(Mp / 64)), dim3(kThreads), 0, st,
-                       H, g, s, (const u32x4*)Wf, bias, (bf16*)qkv, EmbedRows{});
+    hipLaunchKernelGGL((k_fused_qkv<2, false>), dim3(grid), dim3(kThreads), 0, st,
+                       H, g, s, (const u32x4*)Wf, bias, (bf16*)qkv, EmbedRows{}, rm);
   else
-    hipLaunchKernelGGL((k_fused_qkv<4, false>), dim3((unsigned)(Mp / 128)), dim3(kThreads), 0, st,
-                       H, g, s, (const u32x4*)Wf, bias, (bf16*)qkv, EmbedRows{});
+    hipLaunchKernelGGL((k_fused_qkv<4, false>), dim3(grid), dim3(kThreads), 0, st,
+                       H, g, s, (const u32x4*)Wf, bias, (bf16*)qkv, EmbedRows{}, rm);
   return hipGetLastError();
 }
 
@@ -904,28 +1057,32 @@ hipError_t launch_fused_embed_qkv(hipStream_t st, int64_t Mp, const float* xs, i
     return hipErrorInvalidValue;
   if (Mp == 0) return hipSuccess;
   const EmbedRows em{xs, T, temb, W_xin, H};
+  const RowMap rm{nullptr, Mp};
   if (rows == 64)
     hipLaunchKernelGGL((k_fused_qkv<2, true>), dim3((unsigned)(Mp / 64)), dim3(kThreads), 0, st,
-                       nullptr, g, s, (const u32x4*)Wf, bias, (bf16*)qkv, em);
+                       nullptr, g, s, (const u32x4*)Wf, bias, (bf16*)qkv, em, rm);
   else
     hipLaunchKernelGGL((k_fused_qkv<4, true>), dim3((unsigned)(Mp / 128)), dim3(kThreads), 0, st,
-                       nullptr, g, s, (const u32x4*)Wf, bias, (bf16*)qkv, em);
+                       nullptr, g, s, (const u32x4*)Wf, bias, (bf16*)qkv, em, rm);
   return hipGetLastError();
 }
 
 hipError_t launch_fused_oqc(hipStream_t st, int64_t Mp, const void* att, const void* Wf_o,
                             const float* b_o, float* H, const float* g, const float* s,
-                            const void* Wf_qc, const float* b_qc, void* qc, int rows) {
-  if ((rows != 64 && rows != 128) || Mp % rows) return hipErrorInvalidValue;
-  if (Mp == 0) return hipSuccess;
+                            const void* Wf_qc, const float* b_qc, void* qc, int rows,
+                            const int32_t* tiles, int64_t n_tiles) {
+  unsigned grid = 0;
+  if (!fused_grid(Mp, rows, tiles, n_tiles, &grid)) return hipErrorInvalidValue;
+  if (grid == 0) return hipSuccess;
+  const RowMap rm{tiles, Mp};
   if (rows == 64)
-    hipLaunchKernelGGL(k_fused_oqc<2>, dim3((unsigned)(Mp / 64)), dim3(kThreads), 0, st,
+    hipLaunchKernelGGL(k_fused_oqc<2>, dim3(grid), dim3(kThreads), 0, st,
                        (const bf16*)att, (const u32x4*)Wf_o, b_o, H, g, s, (const u32x4*)Wf_qc,
-                       b_qc, (bf16*)qc);
+                       b_qc, (bf16*)qc, rm);
   else
-    hipLaunchKernelGGL(k_fused_oqc<4>, dim3((unsigned)(Mp / 128)), dim3(kThreads), 0, st,
+    hipLaunchKernelGGL(k_fused_oqc<4>, dim3(grid), dim3(kThreads), 0, st,
                        (const bf16*)att, (const u32x4*)Wf_o, b_o, H, g, s, (const u32x4*)Wf_qc,
-                       b_qc, (bf16*)qc);
+                       b_qc, (bf16*)qc, rm);
   return hipGetLastError();
 }
 
@@ -935,31 +1092,98 @@ hipError_t launch_fused_mlp(hipStream_t st, int64_t Mp, const void* att, const v
                             const float* b_dn, float2* stats_out, const float* g1n,
                             const float* s1n, const void* Wf_qkv_n, const float* b_qkv_n,
                             void* qkv, const float* gf, const float* sf, const float* Wt_out,
-                            const float* b_out, const OdeArgs* head) {
-  if (Mp % 64) return hipErrorInvalidValue;
-  if (Mp == 0) return hipSuccess;
+                            const float* b_out, const OdeArgs* head, const Fp8Mlp* fp8,
+                            const int32_t* tiles, int64_t n_tiles) {
+  unsigned gsz = 0;
+  if (!fused_grid(Mp, 64, tiles, n_tiles, &gsz)) return hipErrorInvalidValue;
+  if (gsz == 0) return hipSuccess;
+  const RowMap rm{tiles, Mp};
   if (qkv && head) return hipErrorInvalidValue;
-  const dim3 grid((unsigned)(Mp / 64));
+  if (fp8 && (!fp8->up || !fp8->dn || !fp8->up_inv || !fp8->dn_scale || !fp8->dn_inv))
+    return hipErrorInvalidValue;
+  const Mlp8 f8 = fp8 ? Mlp8{(const i32x8*)fp8->up, (const i32x8*)fp8->dn, fp8->up_inv,
+                             fp8->dn_scale, fp8->dn_inv}
+                      : Mlp8{};
+  const dim3 grid(gsz);
+#define FMD_MLP_GO(TAIL, NQ, NH)                                                              \
+  do {                                                                                        \
+    if (fp8)                                                                                  \
+      hipLaunchKernelGGL((k_fused_mlp<2, TAIL, true>), grid, dim3(kThreads4), 0, st,          \
+                         (const bf16*)att, (const u32x4*)Wf_oc, b_oc, H, g, s,                \
+                         (const u32x4*)Wf_up, b_up, (const u32x4*)Wf_dn, b_dn, stats_out, NQ, \
+                         NH, f8, rm);                                                         \
+    else                                                                                      \
+      hipLaunchKernelGGL((k_fused_mlp<2, TAIL, false>), grid, dim3(kThreads4), 0, st,         \
+                         (const bf16*)att, (const u32x4*)Wf_oc, b_oc, H, g, s,                \
+                         (const u32x4*)Wf_up, b_up, (const u32x4*)Wf_dn, b_dn, stats_out, NQ, \
+                         NH, f8, rm);                                                         \
+  } while (0)
   if (qkv) {
     if (!g1n || !s1n || !Wf_qkv_n || !b_qkv_n) return hipErrorInvalidValue;
     const NextQkv nq{g1n, s1n, (const u32x4*)Wf_qkv_n, b_qkv_n, (bf16*)qkv};
-    hipLaunchKernelGGL((k_fused_mlp<2, kTailQkv>), grid, dim3(kThreads4), 0, st,
-                       (const bf16*)att, (const u32x4*)Wf_oc, b_oc, H, g, s,
-                       (const u32x4*)Wf_up, b_up, (const u32x4*)Wf_dn, b_dn, stats_out, nq,
-                       NextHead{});
+    FMD_MLP_GO(kTailQkv, nq, NextHead{});
   } else if (head) {
     if (!gf || !sf || !Wt_out || !b_out || head->nf != 9) return hipErrorInvalidValue;
     const NextHead nh{gf, sf, Wt_out, b_out, *head};
-    hipLaunchKernelGGL((k_fused_mlp<2, kTailHead>), grid, dim3(kThreads4), 0, st,
-                       (const bf16*)att, (const u32x4*)Wf_oc, b_oc, H, g, s,
-                       (const u32x4*)Wf_up, b_up, (const u32x4*)Wf_dn, b_dn, stats_out,
-                       NextQkv{}, nh);
+    FMD_MLP_GO(kTailHead, NextQkv{}, nh);
   } else {
-    hipLaunchKernelGGL((k_fused_mlp<2, kTailStats>), grid, dim3(kThreads4), 0, st,
-                       (const bf16*)att, (const u32x4*)Wf_oc, b_oc, H, g, s,
-                       (const u32x4*)Wf_up, b_up, (const u32x4*)Wf_dn, b_dn, stats_out,
-                       NextQkv{}, NextHead{});
+    FMD_MLP_GO(kTailStats, NextQkv{}, NextHead{});
   }
+#undef FMD_MLP_GO
+  return hipGetLastError();
+}
+
+// Per-column power-of-two scale of a K x N FP32 matrix for FP8 e4m3: s_n = 2^e with e the
+// largest integer such that max_k |W[k][n]| s_n <= 448 (s_n = 1 for a zero column); inv = 1/s.
+__global__ void k_fp8_col_scale(const float* __restrict__ W, int K, int N, float* __restrict__ scale,
+                                float* __restrict__ inv) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  float mx = 0.f;
+  for (int k = 0; k < K; ++k) mx = fmaxf(mx, fabsf(W[(int64_t)k * N + n]));
+  int e = 0;
+  if (mx > 0.f) {
+    e = (int)floorf(log2f(448.0f / mx));
+    while (ldexpf(mx, e) > 448.0f) --e;        // log2f may round up across a power of two
+    while (ldexpf(mx, e + 1) <= 448.0f) ++e;
+  }
+  scale[n] = ldexpf(1.0f, e);
+  inv[n] = ldexpf(1.0f, -e);
+}
+
+// FP8 fragments (layout of the Mlp8 comment) of W s_n.
+__global__ void k_pack_frag8(const float* __restrict__ W, int K, int N, const float* __restrict__ scale,
+                             i32x8* __restrict__ Wf) {
+  const int nks = K / 64;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)(N / 32) * nks * 64) return;
+  const int lane = (int)(e % 64);
+  const int ks = (int)((e / 64) % nks);
+  const int nb = (int)(e / (64 * nks));
+  const int n = nb * 32 + (lane & 31);
+  const float sc = scale[n];
+  i32x8 v;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    uint32_t word = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int k = ks * 64 + (lane >> 5) * 32 + 4 * q + b;
+      word |= to_fp8(W[(int64_t)k * N + n] * sc) << (8 * b);
+    }
+    v[q] = (int)word;
+  }
+  Wf[e] = v;
+}
+
+hipError_t launch_pack_frag8(hipStream_t st, const float* W, int K, int N, void* Wf, float* scale,
+                             float* inv) {
+  if (K % 64 || N % 32) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_fp8_col_scale, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, W, K, N,
+                     scale, inv);
+  const int64_t n = (int64_t)(N / 32) * (K / 64) * 64;
+  hipLaunchKernelGGL(k_pack_frag8, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, W, K, N,
+                     (const float*)scale, (i32x8*)Wf);
   return hipGetLastError();
 }
 

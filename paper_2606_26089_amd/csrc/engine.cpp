@@ -54,8 +54,10 @@ int check_cfg(const fmd_model_config* c) {
   if (c->t_embed_dim != 32) return fail(FMD_E_UNSUPPORTED, "t_embed_dim must be 32");
   if (c->f_truth != 9 || c->f_reco != 9) return fail(FMD_E_UNSUPPORTED, "f_truth and f_reco must be 9");
   if (c->n_max < 1 || c->n_max > 4096) return fail(FMD_E_UNSUPPORTED, "n_max must be in [1, 4096]");
-  if (c->precision != FMD_FP32 && c->precision != FMD_BF16)
+  if (c->precision != FMD_FP32 && c->precision != FMD_BF16 && c->precision != FMD_FP8)
     return fail(FMD_E_INVALID, "unknown precision %d", c->precision);
+  if (c->precision == FMD_FP8 && !fused_supported(c->d_model, c->n_heads, c->mlp_ratio))
+    return fail(FMD_E_UNSUPPORTED, "FP8 operands exist in the fused kernels only (d_model 256, 8 heads of 32)");
   return FMD_OK;
 }
 
@@ -91,7 +93,7 @@ size_t walk_params(const fmd_model_config& c, F&& f) {
   return o;
 }
 
-size_t elem_size(const fmd_model_config& c) { return c.precision == FMD_BF16 ? 2 : 4; }
+size_t elem_size(const fmd_model_config& c) { return c.precision == FMD_FP32 ? 4 : 2; }
 
 // ---------------------------------------------------------------------------------------
 // workspace
@@ -418,7 +420,7 @@ int resid_epi(const fmd_model* m) { return m->fuse_stats ? EPI_RESID_LN : EPI_RE
 // Attention query tiles the model's kernel takes (candidates of the autotuner) and the one
 // used for a padded token count: the tuned one, else the default.
 int attn_tiles(const fmd_model* m, int* tiles) {
-  return attention_query_tiles(m->cfg.precision == FMD_BF16,
+  return attention_query_tiles(m->cfg.precision != FMD_FP32,
                                m->cfg.d_model / std::max(m->cfg.n_heads, 1), tiles);
 }
 int attn_tile_for(const fmd_model* m, int64_t Tp) {
@@ -426,12 +428,13 @@ int attn_tile_for(const fmd_model* m, int64_t Tp) {
   const int n = attn_tiles(m, tiles);
   const int t = m->tune[TS_ATTN][bucket_of(Tp)];
   if (t >= 0 && t < n) return tiles[t];
-  return attention_query_tile(m->cfg.precision == FMD_BF16,
+  return attention_query_tile(m->cfg.precision != FMD_FP32,
                               m->cfg.d_model / std::max(m->cfg.n_heads, 1), m->cfg.n_heads);
 }
-// Row tile of the fused QKV / OQC kernels (candidate 0: 64 rows, 1: 128 rows).
-int fused_rows_for(const fmd_model* m, int slot, int64_t Tp) {
-  return m->tune[slot][bucket_of(Tp)] == 1 ? 128 : 64;
+// Row tile of the fused QKV / OQC kernels (candidate 0: 64 rows, 1: 128 rows); 64 when the
+// call runs a map of 64-row tiles.
+int fused_rows_for(const fmd_model* m, const Call& c, int slot) {
+  return !c.tiles && m->tune[slot][bucket_of(c.Tp)] == 1 ? 128 : 64;
 }
 
 // Launches the GEMM of one tuning slot with a given tiling on the live workspace.
@@ -642,7 +645,7 @@ int net_forward(fmd_model* m, Call& c, const float* t_ev) {
   // embedding formed in block 0's QKV kernel); the GEMM kernels otherwise
   const int fz = std::is_same<T, bf16>::value ? m->fused : 0;
   // (stage times only: calls with per-event times keep the embedding kernel)
-  const bool embed_in_qkv = (fz & FMD_FUSED_QKV) && (fz & FMD_FUSED_EMBED) && !t_ev;
+  const bool embed_in_qkv = (fz & FMD_FUSED_QKV) && (fz & FMD_FUSED_EMBED) && !t_ev && !c.tiles;
   if (!embed_in_qkv)
     FMD_TRY(timed(m, c.st, FMD_K_OTHER, 0, [&] {
       return launch_embed(c.st, w.xs, kStateLd, 9, c.T, t_ev ? w.tok_event : nullptr, w.temb,
@@ -658,13 +661,13 @@ int net_forward(fmd_model* m, Call& c, const float* t_ev) {
                       Td * (dd * 4 + kStateLd * 4) + (Td + dd) * 3 * dd * es, [&] {
           return launch_fused_embed_qkv(c.st, c.Tp, w.xs, kStateLd, 9, c.T, w.temb, m->W_xin,
                                         w.H, B.g1, B.s1, B.Fqkv, B.bqkv, w.qkv,
-                                        fused_rows_for(m, TS_FQKV, c.Tp));
+                                        fused_rows_for(m, c, TS_FQKV));
         }));
       else if (!qkv_ready)
         FMD_TRY(timed(m, c.st, FMD_K_GEMM_QKV, 2.0 * Td * dd * 3 * dd,
                       Td * dd * 4 + (Td + dd) * 3 * dd * es, [&] {
           return launch_fused_qkv(c.st, c.Tp, w.H, B.g1, B.s1, B.Fqkv, B.bqkv, w.qkv,
-                                  fused_rows_for(m, TS_FQKV, c.Tp));
+                                  fused_rows_for(m, c, TS_FQKV), c.tiles, c.n_tiles);
         }));
     } else {
       if (l > 0) FMD_TRY(row_stats(m, c));
@@ -681,7 +684,7 @@ int net_forward(fmd_model* m, Call& c, const float* t_ev) {
       FMD_TRY(timed(m, c.st, FMD_K_FUSED_OQC, 2.0 * Td * dd * dd * 2,
                     Td * dd * (es + 8 + es) + 2 * dd * dd * es, [&] {
         return launch_fused_oqc(c.st, c.Tp, w.att, B.Fo, B.bo, w.H, B.g2, B.s2, B.Fqc, B.bqc, w.qc,
-                                fused_rows_for(m, TS_FOQC, c.Tp));
+                                fused_rows_for(m, c, TS_FOQC), c.tiles, c.n_tiles);
       }));
     } else {
       FMD_TRY(timed(m, c.st, FMD_K_GEMM_PROJ, 2.0 * Td * d * d, (Td + d) * d * es + resid, [&] {
@@ -733,7 +736,8 @@ int net_forward(fmd_model* m, Call& c, const float* t_ev) {
                                 chain ? N->bqkv : nullptr, chain ? w.qkv : nullptr,
                                 fold ? m->g_f : nullptr, fold ? m->s_f : nullptr,
                                 fold ? m->Wout_pk : nullptr, fold ? m->bout_pk : nullptr,
-                                fold ? c.head : nullptr);
+                                fold ? c.head : nullptr, m->f8.empty() ? nullptr : &m->f8[l],
+                                c.tiles, c.n_tiles);
       }));
       qkv_ready = chain;
       c.head_done = fold;
@@ -970,7 +974,7 @@ int simulate_impl(fmd_model* m, const fmd_events_in* truth, const float* x0, uin
   c.Tp = round_up(c.T, kGemmBM);
   const hipStream_t caller = (hipStream_t)stream;
   FMD_TRY(enter_stream(m, caller, c));
-  const int st = m->kind == 0 && m->cfg.precision == FMD_BF16
+  const int st = m->kind == 0 && m->cfg.precision != FMD_FP32
                      ? simulate_body<bf16>(m, truth, x0, seed, sched, reco, c, reco_off)
                      : simulate_body<float>(m, truth, x0, seed, sched, reco, c, reco_off);
   const int st2 = leave_stream(m, caller);
@@ -1003,7 +1007,7 @@ int velocity_body(fmd_model* m, const fmd_events_in* truth, const float* x,
   }
   FMD_TRY(timed(m, c.st, FMD_K_OTHER, 0, [&] { return launch_load_state(c.st, xs, 9, c.T, w.x, w.xs, kStateLd); }));
   float* out = truth->on_device ? v : w.io;
-  if (m->cfg.precision == FMD_BF16) {
+  if (m->cfg.precision != FMD_FP32) {
     FMD_TRY(truth_cache<bf16>(m, c));
     FMD_TRY(autotune<bf16>(m, c));
     FMD_TRY(net_forward<bf16>(m, c, tev));
@@ -1061,18 +1065,23 @@ int fmd_model_create(const fmd_model_config* cfg, const float* params, size_t n_
   if (grow(m->bkv, (size_t)(L * 2 * d) * 4) != FMD_OK) return bail(FMD_E_NOMEM);
   if (grow(m->Wout_pk, (size_t)64 * d * 4) != FMD_OK) return bail(FMD_E_NOMEM);
   if (grow(m->bout_pk, (size_t)64 * 4) != FMD_OK) return bail(FMD_E_NOMEM);
-  m->fused_ok = cfg->precision == FMD_BF16 &&
+  m->fused_ok = cfg->precision != FMD_FP32 &&
                 fused_supported(cfg->d_model, cfg->n_heads, cfg->mlp_ratio);
-  m->kv_hm = cfg->precision == FMD_BF16 && cfg->d_model == 32 * cfg->n_heads;
+  m->kv_hm = cfg->precision != FMD_FP32 && cfg->d_model == 32 * cfg->n_heads;
   m->fused = m->fused_ok ? FMD_FUSED_ALL : 0;
   if (m->fused_ok && grow(m->frag, (size_t)(L * blk_elems) * 2) != FMD_OK) return bail(FMD_E_NOMEM);
+  // FP8 form, per block: e4m3 fragments of W_up and W_dn (4 d^2 bytes each), then the column
+  // scales s_up [4d], 1/s_up [4d], s_dn [d], 1/s_dn [d] (FP32)
+  const size_t f8_blk = 8 * d * d + (size_t)10 * d * 4;
+  if (cfg->precision == FMD_FP8 && grow(m->frag8, (size_t)L * f8_blk) != FMD_OK) return bail(FMD_E_NOMEM);
+  if (cfg->precision == FMD_FP8) m->f8.assign(L, Fp8Mlp{});
   m->blk.assign(L, DevBlock{});
   char* pk = (char*)m->packed;
   char* wkv = (char*)m->Wkv;
   int status = FMD_OK;
   auto pack = [&](size_t off, int64_t rows, int64_t cols, void* dst) {
     const float* W = m->params + off;
-    hipError_t e = cfg->precision == FMD_BF16
+    hipError_t e = cfg->precision != FMD_FP32
                        ? launch_pack_weight<bf16>(nullptr, W, (int)rows, (int)cols, (bf16*)dst)
                        : launch_pack_weight<float>(nullptr, W, (int)rows, (int)cols, (float*)dst);
     if (e != hipSuccess && status == FMD_OK) status = fail(FMD_E_DEVICE, "weight packing failed");
@@ -1137,11 +1146,30 @@ int fmd_model_create(const fmd_model_config* cfg, const float* params, size_t n_
         B->Wup = base + 6 * d * d * es;
         pack(off, rows, cols, B->Wup);
         pack_frag(off, rows, cols, l, 6 * d * d, &B->Fup);
+        if (cfg->precision == FMD_FP8) {
+          char* f = (char*)m->frag8 + (size_t)l * f8_blk;
+          float* sc = (float*)(f + 8 * d * d);
+          m->f8[l].up = f;
+          m->f8[l].up_inv = sc + 4 * d;
+          if (launch_pack_frag8(nullptr, p, (int)rows, (int)cols, f, sc, sc + 4 * d) != hipSuccess &&
+              status == FMD_OK)
+            status = fail(FMD_E_DEVICE, "FP8 weight packing failed");
+        }
         break;
       case P_W_DN:
         B->Wdn = base + 10 * d * d * es;
         pack(off, rows, cols, B->Wdn);
         pack_frag(off, rows, cols, l, 10 * d * d, &B->Fdn);
+        if (cfg->precision == FMD_FP8) {
+          char* f = (char*)m->frag8 + (size_t)l * f8_blk + 4 * d * d;
+          float* sc = (float*)((char*)m->frag8 + (size_t)l * f8_blk + 8 * d * d) + 8 * d;
+          m->f8[l].dn = f;
+          m->f8[l].dn_scale = sc;
+          m->f8[l].dn_inv = sc + d;
+          if (launch_pack_frag8(nullptr, p, (int)rows, (int)cols, f, sc, sc + d) != hipSuccess &&
+              status == FMD_OK)
+            status = fail(FMD_E_DEVICE, "FP8 weight packing failed");
+        }
         break;
       case P_W_KC: pack(off, rows, cols, wkv + (size_t)l * 2 * d * d * es); break;
       case P_W_VC: pack(off, rows, cols, wkv + ((size_t)l * 2 * d + d) * d * es); break;
@@ -1210,6 +1238,7 @@ int fmd_model_destroy(fmd_model* m) {
   if (m->params) (void)hipFree(m->params);
   if (m->packed) (void)hipFree(m->packed);
   if (m->frag) (void)hipFree(m->frag);
+  if (m->frag8) (void)hipFree(m->frag8);
   if (m->Wkv) (void)hipFree(m->Wkv);
   if (m->bkv) (void)hipFree(m->bkv);
   if (m->Wout_pk) (void)hipFree(m->Wout_pk);
@@ -1490,7 +1519,7 @@ const char* fmd_kernel_name(fmd_model* m, int32_t cls) {
                                            "other"};
   if (cls == FMD_K_GEMM_QKV && m && (m->fused & FMD_FUSED_QKV)) return "k_fused_qkv";
   if ((cls == FMD_K_ATTN_SELF || cls == FMD_K_ATTN_CROSS) && m && m->kind == 0 &&
-      m->cfg.precision == FMD_BF16 && m->cfg.d_model == 32 * m->cfg.n_heads)
+      m->cfg.precision != FMD_FP32 && m->cfg.d_model == 32 * m->cfg.n_heads)
     return cls == FMD_K_ATTN_SELF ? "k_attn32_self" : "k_attn32_cross";
   return cls >= 0 && cls < FMD_K_COUNT ? names[cls] : "";
 }
@@ -1507,6 +1536,8 @@ int fmd_fused_enable(fmd_model* m, int32_t mask) {
     return fail(FMD_E_INVALID, "fused mask %d not in [0, %d]", mask, (int)FMD_FUSED_ALL);
   if (mask && !m->fused_ok)
     return fail(FMD_E_UNSUPPORTED, "no fused kernels for this configuration (BF16, d_model 256 only)");
+  if (m->cfg.precision == FMD_FP8 && !(mask & FMD_FUSED_MLP))
+    return fail(FMD_E_UNSUPPORTED, "an FP8 model runs its MLP in the fused kernel");
   if (m->fused != mask) {
     m->fused = mask;
     m->tune_gen++;   // captured graphs hold the other kernel sequence
@@ -1542,7 +1573,7 @@ int fmd_tuning_table(fmd_model* m, char* buf, size_t cap, size_t* needed) {
   int tiles[4];
   attn_tiles(m, tiles);
   std::string js = "{\"precision\": \"";
-  js += m->cfg.precision == FMD_BF16 ? "bf16" : "fp32";
+  js += m->cfg.precision == FMD_FP8 ? "fp8" : m->cfg.precision == FMD_BF16 ? "bf16" : "fp32";
   js += "\", \"d_model\": " + std::to_string(m->cfg.d_model) + ", \"entries\": [";
   bool first = true;
   for (int sl = 0; sl < TS_COUNT; ++sl)

@@ -93,6 +93,8 @@ struct fmd_model {
   float* params = nullptr;         // flat FP32 copy on device
   void* packed = nullptr;          // packed matrices in the compute type
   void* frag = nullptr;            // fragment-layout BF16 matrices of the fused kernels
+  void* frag8 = nullptr;           // FP8 form: e4m3 fragments of W_up, W_dn and column scales
+  std::vector<fmd::Fp8Mlp> f8;     // FP8 form: per block pointers into frag8
   bool fused_ok = false;           // the fused block kernels exist for this configuration
   bool kv_hm = false;              // cross K/V cache head-major [L][2][heads][cap][dh]
   int fused = 0;                   // segments that use them (FMD_FUSED_* bits)

@@ -114,6 +114,10 @@ struct Call {
   // path); net_forward sets head_done when it did, and the caller then skips its head.
   const OdeArgs* head = nullptr;
   bool head_done = false;
+  // 64-row tiles the fused kernels run (device int32, n_tiles of them; null: all of Tp). The
+  // serving loop skips the tiles of gaps between resident requests this way.
+  const int32_t* tiles = nullptr;
+  int64_t n_tiles = 0;
 };
 
 

@@ -203,9 +203,10 @@ bool fused_supported(int d_model, int n_heads, int mlp_ratio);
 hipError_t launch_pack_frag(hipStream_t st, const float* W, int K, int N, void* Wf);
 // [Q | K | V] = LN(H; g, s) Wqkv + b, head-major: qkv [3][8 heads][Mp][32] (plane = Mp x 32).
 // rows: the workgroup's row tile, 64 or 128 (the autotuner's candidates; same results).
+// tiles (optional, device int32 [n_tiles]): run only these 64-row tiles (rows must be 64).
 hipError_t launch_fused_qkv(hipStream_t st, int64_t Mp, const float* H, const float* g,
                             const float* s, const void* Wf, const float* bias, void* qkv,
-                            int rows = 64);
+                            int rows = 64, const int32_t* tiles = nullptr, int64_t n_tiles = 0);
 // As launch_fused_qkv for block 0, with the input embedding formed in the kernel for a
 // stage time shared by every row: H rows [0, T) = temb[0..255] + xs[r][0..8] W_xin (the
 // order of launch_embed's d = 256 kernel, so H is the same; rows [T, Mp) are zero) are
@@ -218,12 +219,27 @@ hipError_t launch_fused_embed_qkv(hipStream_t st, int64_t Mp, const float* xs, i
 // attention output att is head-major [8 heads][Mp][32] as well. rows: 64 or 128.
 hipError_t launch_fused_oqc(hipStream_t st, int64_t Mp, const void* att, const void* Wf_o,
                             const float* b_o, float* H, const float* g, const float* s,
-                            const void* Wf_qc, const float* b_qc, void* qc, int rows = 64);
+                            const void* Wf_qc, const float* b_qc, void* qc, int rows = 64,
+                            const int32_t* tiles = nullptr, int64_t n_tiles = 0);
 // att (head-major [8 heads][Mp][32]): H += att Woc + b_oc;  H += GELU(LN(H; g, s) Wup + b_up) Wdn + b_dn;  stats_out = LN stats of
 // H. With qkv set, also the next block's [Q | K | V] = LN(H; g1n, s1n) Wqkv_n + b_qkv_n into
 // qkv, head-major like launch_fused_qkv (the next block then skips its QKV kernel). With head
 // set instead (the last block, 9 features), the output head LN_f(H; gf, sf) Wt_out^T + b_out
 // and the ODE update of *head, as launch_head256 does; H is then not written.
+// FP8 operands of the MLP's two projections (the FP8 precision form): FP8 e4m3 fragments of
+// W_up s_up and W_dn s_dn (launch_pack_frag8) with the power-of-two column scales.
+struct Fp8Mlp {
+  const void* up;          // [1024/32][256/64][64 lanes][32 bytes]
+  const void* dn;          // [256/32][1024/64][64 lanes][32 bytes]
+  const float* up_inv;     // 1 / s_up [1024]
+  const float* dn_scale;   // s_dn [256]
+  const float* dn_inv;     // 1 / s_dn [256]
+};
+// W: FP32 K x N -> FP8 e4m3 fragments of W diag(scale) [N/32][K/64][64 lanes][32 bytes], with
+// scale[n] the power of two that brings the column's largest magnitude into (224, 448] and
+// inv[n] = 1 / scale[n] (both written, device [N]). K % 64 == 0, N % 32 == 0.
+hipError_t launch_pack_frag8(hipStream_t st, const float* W, int K, int N, void* Wf, float* scale,
+                             float* inv);
 hipError_t launch_fused_mlp(hipStream_t st, int64_t Mp, const void* att, const void* Wf_oc,
                             const float* b_oc, float* H, const float* g, const float* s,
                             const void* Wf_up, const float* b_up, const void* Wf_dn,
@@ -232,7 +248,8 @@ hipError_t launch_fused_mlp(hipStream_t st, int64_t Mp, const void* att, const v
                             const float* b_qkv_n = nullptr, void* qkv = nullptr,
                             const float* gf = nullptr, const float* sf = nullptr,
                             const float* Wt_out = nullptr, const float* b_out = nullptr,
-                            const OdeArgs* head = nullptr);
+                            const OdeArgs* head = nullptr, const Fp8Mlp* fp8 = nullptr,
+                            const int32_t* tiles = nullptr, int64_t n_tiles = 0);
 
 // dst[i] = T(src[i]).
 template <typename T>

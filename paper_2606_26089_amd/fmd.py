@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(_HERE, "libfmdet.so")
 
 OK, PENDING = 0, 1
 E_INVALID, E_NOMEM, E_BUDGET, E_UNSUPPORTED, E_DEVICE, E_STATE = -1, -2, -3, -4, -5, -6
-FP32, BF16 = 0, 1
+FP32, BF16, FP8 = 0, 1, 2
 EULER, RK4, MIDPOINT = 0, 1, 2
 (K_GEMM_QKV, K_GEMM_PROJ, K_GEMM_QC, K_GEMM_UP, K_GEMM_DOWN, K_FUSED_OQC, K_FUSED_MLP,
  K_ATTN_SELF, K_ATTN_CROSS, K_OTHER) = range(10)
@@ -62,7 +62,7 @@ class RequestStats(ctypes.Structure):
 class ServerInfo(ctypes.Structure):
     _fields_ = [(n, c_int64) for n in ("pool_tokens", "bytes_per_token", "queued_requests",
                                         "resident_requests", "resident_tokens", "iterations",
-                                        "rows_processed", "busy_ns")]
+                                        "rows_processed", "busy_ns", "rows_live")]
 
 
 class MultiplicityLaw(ctypes.Structure):

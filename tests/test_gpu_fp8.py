@@ -1,0 +1,96 @@
+"""FP8 operands for the MLP projections (GPU): the BF16 form with W_up / W_dn and their inputs
+rounded to e4m3 (power-of-two column scales on the weights, FP32 accumulation). Checked
+against the FP64 oracle at the FP8 tolerance, for the velocity field and for whole sampling
+runs on ragged events spanning several tiles, on the full base workload's first 256 events
+(normwise error and the pT / eta response), and for the exact invariances (an event alone
+equals the event in a batch; graph replay equals eager launches)."""
+
+import dataclasses
+import os
+
+import numpy as np
+import pytest
+
+from oracle import net, sample
+from tests._gpu import fmd_lib, torch_cuda
+from workload import configs, errors, events, params
+
+pytestmark = pytest.mark.gpu
+
+CFG = dataclasses.replace(configs.BASE_MODEL.with_precision(configs.FP8), n_max=1000)
+# normwise error bar of the FP8 form per output feature (derivation in the design notes)
+TOL_FP8 = 8e-2
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "oracle_base_rk4x16_first256.npz")
+
+
+@pytest.fixture(scope="module")
+def env():
+    return torch_cuda(), fmd_lib()
+
+
+def dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def test_fp8_velocity_and_sampling_match_the_oracle(env):
+    torch, fmd = env
+    sizes = [1, 64, 65, 200, 0, 129, 37]
+    off = np.r_[0, np.cumsum(sizes)].astype(np.int64)
+    feat = events.particles(np.random.default_rng(81), int(off[-1]))
+    x = np.random.default_rng(82).standard_normal((off[-1], 9)).astype(np.float32)
+    t = np.linspace(0.05, 0.95, len(sizes)).astype(np.float32)
+    flat = params.draw(CFG, seed=0, perturbed=True)
+    m = fmd.Model(CFG, flat)
+    assert m.tuning_table()["precision"] == "fp8"
+    v = m.velocity(off, dev(torch, feat), dev(torch, x), dev(torch, t)).cpu().numpy()
+    sched = configs.Schedule(configs.RK4, 2)
+    out = m.simulate(off, dev(torch, feat), 3, sched).cpu().numpy()
+    m.close()
+    P = net.unpack(flat, CFG)
+    ref = np.concatenate([net.velocity(P, feat[off[e]:off[e + 1]], x[off[e]:off[e + 1]], float(t[e]))
+                          for e in range(len(sizes)) if sizes[e]])
+    ev = errors.normwise_rel_err(v, ref).max()
+    ref_s = sample.simulate(flat, CFG, off, feat, sched, seed=3)
+    es = errors.normwise_rel_err(out, ref_s).max()
+    print(f"FP8 velocity error {ev:.3e}, sampling error {es:.3e}")
+    assert ev < TOL_FP8 and es < TOL_FP8
+
+
+def test_fp8_event_alone_equals_event_in_batch_and_graphs(env):
+    torch, fmd = env
+    flat = params.draw(CFG, seed=0)
+    sizes = [150, 3, 64, 90]
+    off = np.r_[0, np.cumsum(sizes)].astype(np.int64)
+    feat = events.particles(np.random.default_rng(83), int(off[-1]))
+    sched = configs.Schedule(configs.EULER, 3)
+    m = fmd.Model(CFG, flat)
+    batch = m.simulate(off, dev(torch, feat), 7, sched).cpu().numpy()
+    m.graphs_enable(False)
+    eager = m.simulate(off, dev(torch, feat), 7, sched).cpu().numpy()
+    alone = m.simulate(off[:2] - off[0], dev(torch, feat[: sizes[0]]), 7, sched).cpu().numpy()
+    with pytest.raises(fmd.FmdError):
+        m.fused_enable(fmd.FUSED_QKV)        # the FP8 MLP exists in the fused kernel only
+    m.close()
+    assert np.array_equal(batch, eager)
+    assert np.array_equal(batch[: sizes[0]], alone)
+
+
+def test_fp8_base_workload_first_256_events_against_golden(env):
+    torch, fmd = env
+    w = configs.BASE_BF16
+    off, feat = events.for_workload(w)
+    g = np.load(GOLDEN)
+    n = len(g["offsets"]) - 1
+    assert np.array_equal(g["offsets"], off[:n + 1])
+    cfg = w.model.with_precision(configs.FP8)
+    m = fmd.Model(cfg, params.draw(cfg, w.weight_seed))
+    out = m.simulate(off, dev(torch, feat), w.noise_seed, w.schedule).cpu().numpy()
+    m.close()
+    rows = int(off[n])
+    err = errors.normwise_rel_err(out[:rows], g["reco"]).max()
+    resp = errors.response(out[:rows], feat[:rows])
+    resp_ref = errors.response(g["reco"], feat[:rows])
+    print(f"FP8 base workload: normwise {err:.3e}, response {resp}, oracle {resp_ref}")
+    assert np.isfinite(out).all()
+    assert err < TOL_FP8
+    assert errors.response_agrees(resp, resp_ref, 0.03)

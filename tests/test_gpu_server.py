@@ -155,7 +155,8 @@ def test_tight_budget_queues_requests_and_rejects_oversize(env):
     probe.close()
     reqs = [(off, feat, s, sch) for off, feat, s, sch in _requests(8, seed=9)]
     biggest = max(int(r[0][-1]) for r in reqs)
-    budget = (biggest + 256 + 8) * bpt            # one request at a time, at most
+    # one request at a time, at most (pool ranges are whole 64-row tiles)
+    budget = (-(-biggest // 64) * 64 + 256 + 8) * bpt
     alone = _alone(fmd, flat, reqs)
     srv = fmd.Server(m, hbm_budget_bytes=budget)
     assert srv.info()["pool_tokens"] >= biggest

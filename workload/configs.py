@@ -12,7 +12,7 @@ T_EMBED = 32        # sinusoidal time-embedding width
 MLP_RATIO = 4
 
 EULER, RK4, MIDPOINT = 0, 1, 2
-FP32, BF16 = 0, 1
+FP32, BF16, FP8 = 0, 1, 2
 
 
 @dataclass(frozen=True)
