@@ -139,6 +139,11 @@ int fmd_linear_field_create(double alpha, double beta, fmd_model** out);
  * r = sqrt(-2 ln u_a): z_a = r cos(2 pi u_b), z_b = r sin(2 pi u_b).
  * e is the event's index within this call, so an event's result does not depend on the
  * other events of the call.
+ * With device input and output the call only enqueues work: it does not wait for earlier
+ * work on the stream (its host-built arrays go through two pinned staging sets used by
+ * alternate calls, so it waits at most for the uploads of the call two calls back). The
+ * first call whose padded size falls in a new power-of-two bucket also times the
+ * autotuner's candidates, and waits for them.
  * Errors: FMD_E_INVALID (null pointers, bad offsets, n_steps < 1, unknown scheme,
  * t1 == t0); FMD_E_UNSUPPORTED (an event with more than n_max particles). */
 int fmd_simulate(fmd_model* m, const fmd_events_in* truth, uint64_t seed,
@@ -338,13 +343,15 @@ int fmd_fused_enable(fmd_model* m, int32_t mask);
  * results. */
 int fmd_autotune_enable(fmd_model* m, int32_t enable);
 
-/* On the fused BF16 path (d = 256, heads of 32) the autotuner also chooses, per token bucket,
- * the attention query tile (work items of 64 or 128 queries of one event and head) and the
- * row tile of block 0's fused QKV kernel and of the OQC kernel (64 or 128 rows). These too
- * change only the speed: every candidate gives bitwise-identical results.
+/* On the BF16 path with heads of 32 the autotuner also chooses, per token bucket, the
+ * attention form (candidate 0: work items of 64 queries of one event, one workgroup per item
+ * and head; 1: items of 128 queries; 2: items of 64 queries, one wave per item and head), and
+ * on the fused path (d = 256) the row tile of block 0's fused QKV kernel and of the OQC kernel
+ * (candidate 0: 64 rows, 1: 128 rows). These too change only the speed: every candidate gives
+ * bitwise-identical results.
  * fmd_tuning_set fixes the choice of one of these sites for the padded token counts in
  * [2^tokens_log2, 2^(tokens_log2 + 1)) (rows padded to a multiple of 256), e.g. to reuse a
- * table measured earlier or to compare candidates; candidate indexes are 0 (64) and 1 (128).
+ * table measured earlier or to compare candidates.
  * Errors: FMD_E_INVALID for a null model, another site, a bucket outside [0, 40) or a
  * candidate the model's kernels do not offer. */
 enum { FMD_TUNE_ATTN_QUERY_TILE = 5, FMD_TUNE_FUSED_QKV = 6, FMD_TUNE_FUSED_OQC = 7 };

@@ -103,9 +103,13 @@ void free_ws(Workspace& w) {
                  w.temb, w.tev, w.stats, w.tok_event, w.off, w.work, w.desc, w.ctr};
   for (void* p : dev)
     if (p) (void)hipFree(p);
-  if (w.h_desc) (void)hipHostFree(w.h_desc);
-  if (w.h_off) (void)hipHostFree(w.h_off);
-  if (w.h_work) (void)hipHostFree(w.h_work);
+  for (auto& h : w.hs) {
+    if (h.live) (void)hipEventSynchronize(h.ev);
+    if (h.ev) (void)hipEventDestroy(h.ev);
+    if (h.desc) (void)hipHostFree(h.desc);
+    if (h.off) (void)hipHostFree(h.off);
+    if (h.work) (void)hipHostFree(h.work);
+  }
   w = Workspace();
 }
 
@@ -161,20 +165,41 @@ int ensure_ws_alloc(fmd_model* m, int64_t T, int64_t E, int64_t items, bool* gre
     w.cap_ev = cap;
     *grew = true;
   }
-  if (E + 1 > w.h_cap_ev) {
-    FMD_TRY(grow_host(w.h_off, (size_t)(E + 1) * 8));
-    w.h_cap_ev = E + 1;
-  }
   if (items > w.cap_items) {
     const int64_t cap = std::max(items, w.cap_items + w.cap_items / 4);
     FMD_TRY(grow(w.work, (size_t)cap * sizeof(AttnItem)));
     w.cap_items = cap;
     *grew = true;
   }
-  if (items > w.h_cap_items) {
-    FMD_TRY(grow_host(w.h_work, (size_t)std::max<int64_t>(items, 1) * sizeof(AttnItem)));
-    w.h_cap_items = items;
+  return FMD_OK;
+}
+
+// Switches to the other pinned staging set and makes it writable (waits for the uploads of
+// the call that used it last) with room for E events and `items` work items.
+int next_host_stage(Workspace& w, int64_t E, int64_t items) {
+  w.cur ^= 1;
+  Workspace::HostStage& h = w.hs[w.cur];
+  if (!h.ev) HIP_TRY(hipEventCreateWithFlags(&h.ev, hipEventDisableTiming));
+  if (h.live) {
+    HIP_TRY(hipEventSynchronize(h.ev));
+    h.live = false;
   }
+  if (E + 1 > h.cap_ev) {
+    FMD_TRY(grow_host(h.off, (size_t)(E + 1) * 8));
+    h.cap_ev = E + 1;
+  }
+  if (items > h.cap_items) {
+    FMD_TRY(grow_host(h.work, (size_t)std::max<int64_t>(items, 1) * sizeof(AttnItem)));
+    h.cap_items = std::max<int64_t>(items, 1);
+  }
+  return FMD_OK;
+}
+
+// The uploads from the current set are enqueued on st: record its event after them.
+int mark_host_stage(Workspace& w, hipStream_t st) {
+  Workspace::HostStage& h = w.hs[w.cur];
+  HIP_TRY(hipEventRecord(h.ev, st));
+  h.live = true;
   return FMD_OK;
 }
 
@@ -266,7 +291,8 @@ int stage_events(fmd_model* m, const fmd_events_in* ev, Call& c, const int64_t* 
   int tiles[4];
   const int n_tiles = attn_tiles(m, tiles);
   std::vector<int64_t> ids((size_t)E);
-  auto count_items = [&](int qt) {
+  auto count_items = [&](int code) {
+    const int qt = attn_items_qt(code);
     int64_t k = 0;
     for (int64_t e = 0; e < E; ++e) k += (roff[e + 1] - roff[e] + qt - 1) / qt;
     return k;
@@ -282,8 +308,9 @@ int stage_events(fmd_model* m, const fmd_events_in* ev, Call& c, const int64_t* 
   // capacity for the smallest candidate tile (the most items)
   const int64_t cap_items = count_items(tiles[0]) * (reco_off ? 2 : 1);
   FMD_TRY(ensure_ws(m, std::max(c.T, Tt), E, cap_items));
-  // The pinned staging buffers may still feed the previous call's copies.
-  HIP_TRY(hipStreamSynchronize(c.st));
+  // the pinned staging set of this call (the other set may still feed the last call's copies)
+  FMD_TRY(next_host_stage(w, E, cap_items));
+  Workspace::HostStage& hs = w.hs[w.cur];
   const int b = bucket_of(c.Tp);
   if (n_tiles > 1 && m->autotune && m->kind == 0 && m->tune[TS_ATTN][b] < 0) {
     // the attention query tile: time the self-attention with each candidate's work list on
@@ -297,11 +324,11 @@ int stage_events(fmd_model* m, const fmd_events_in* ev, Call& c, const int64_t* 
     for (int k = 0; k < n_tiles && status == FMD_OK; ++k) {
       const int64_t nk = count_items(tiles[k]);
       AttnBins bk{};
-      if (build_attention_work(roff, roff, ids.data(), E, tiles[k], w.h_work, &bk) != nk) {
+      if (build_attention_work(roff, roff, ids.data(), E, attn_items_qt(tiles[k]), hs.work, &bk) != nk) {
         status = fail(FMD_E_INVALID, "token rows beyond 2^31");
         break;
       }
-      if (hipMemcpyAsync(w.work, w.h_work, (size_t)nk * sizeof(AttnItem), hipMemcpyHostToDevice, c.st) !=
+      if (hipMemcpyAsync(w.work, hs.work, (size_t)nk * sizeof(AttnItem), hipMemcpyHostToDevice, c.st) !=
               hipSuccess ||
           hipStreamSynchronize(c.st) != hipSuccess) {
         status = fail(FMD_E_DEVICE, "autotune upload failed");
@@ -329,8 +356,8 @@ int stage_events(fmd_model* m, const fmd_events_in* ev, Call& c, const int64_t* 
   c.qt = qt;
   c.items = items;
   const int64_t all_items = reco_off ? 2 * items : items;
-  std::memcpy(w.h_off, roff, (size_t)(E + 1) * 8);
-  if (build_attention_work(w.h_off, w.h_off, ids.data(), E, qt, w.h_work, &c.bins) != items)
+  std::memcpy(hs.off, roff, (size_t)(E + 1) * 8);
+  if (build_attention_work(hs.off, hs.off, ids.data(), E, attn_items_qt(qt), hs.work, &c.bins) != items)
     return fail(FMD_E_INVALID, "token rows beyond 2^31");
   same_truth(c);
   if (reco_off) {
@@ -338,14 +365,15 @@ int stage_events(fmd_model* m, const fmd_events_in* ev, Call& c, const int64_t* 
     c.Ttp = round_up(std::max<int64_t>(Tt, 1), kGemmBM);
     c.work_x = items;
     c.sum_nx = sx;
-    if (build_attention_work(w.h_off, ev->offsets, ids.data(), E, qt, w.h_work + items,
+    if (build_attention_work(hs.off, ev->offsets, ids.data(), E, attn_items_qt(qt), hs.work + items,
                              &c.bins_x) != items)
       return fail(FMD_E_INVALID, "token rows beyond 2^31");
   }
-  HIP_TRY(hipMemcpyAsync(w.off, w.h_off, (size_t)(E + 1) * 8, hipMemcpyHostToDevice, c.st));
+  HIP_TRY(hipMemcpyAsync(w.off, hs.off, (size_t)(E + 1) * 8, hipMemcpyHostToDevice, c.st));
   if (all_items)
-    HIP_TRY(hipMemcpyAsync(w.work, w.h_work, (size_t)all_items * sizeof(AttnItem),
+    HIP_TRY(hipMemcpyAsync(w.work, hs.work, (size_t)all_items * sizeof(AttnItem),
                            hipMemcpyHostToDevice, c.st));
+  FMD_TRY(mark_host_stage(w, c.st));
   FMD_TRY(timed(m, c.st, FMD_K_OTHER, 0, [&] { return launch_token_map(c.st, w.off, E, c.T, w.tok_event); }));
   if (ev->on_device) {
     c.u = ev->feat;
@@ -817,17 +845,22 @@ StageDesc stage_desc(const fmd_schedule& s, int i) {
 // Uploads the stage table of a schedule: stage i = (t, h, update mode, write output).
 int upload_stages(fmd_model* m, Call& c, const fmd_schedule* s, int* n_stages) {
   Workspace& w = m->ws;
+  Workspace::HostStage& hs = w.hs[w.cur];   // the call's set (made writable by stage_events)
   const int K = s->n_steps, S = stages_per_step(s->scheme);
   const int n = K * S;
   if (n > w.cap_desc) {
     FMD_TRY(grow(w.desc, (size_t)n * sizeof(StageDesc)));
-    FMD_TRY(grow_host(w.h_desc, (size_t)n * sizeof(StageDesc)));
     HIP_TRY(hipDeviceSynchronize());
     w.cap_desc = n;
     w.generation++;
   }
-  for (int i = 0; i < n; ++i) w.h_desc[i] = stage_desc(*s, i);
-  HIP_TRY(hipMemcpyAsync(w.desc, w.h_desc, (size_t)n * sizeof(StageDesc), hipMemcpyHostToDevice, c.st));
+  if (n > hs.cap_desc) {
+    FMD_TRY(grow_host(hs.desc, (size_t)n * sizeof(StageDesc)));
+    hs.cap_desc = n;
+  }
+  for (int i = 0; i < n; ++i) hs.desc[i] = stage_desc(*s, i);
+  HIP_TRY(hipMemcpyAsync(w.desc, hs.desc, (size_t)n * sizeof(StageDesc), hipMemcpyHostToDevice, c.st));
+  FMD_TRY(mark_host_stage(w, c.st));
   FMD_TRY(timed(m, c.st, FMD_K_OTHER, 0, [&] { return launch_set_counter(c.st, w.ctr, 0); }));
   *n_stages = n;
   return FMD_OK;
@@ -1584,8 +1617,9 @@ int fmd_tuning_table(fmd_model* m, char* buf, size_t cap, size_t* needed) {
       TileDims t{};
       if (sl < TS_GEMM)
         t = tile_dims(m->tune[sl][b]);
-      else if (sl == TS_ATTN)
-        t = TileDims{tiles[m->tune[sl][b]], 128, m->cfg.d_model / m->cfg.n_heads, 256};
+      else if (sl == TS_ATTN)   // threads: 64 for the form with one wave per (item, head)
+        t = TileDims{attn_items_qt(tiles[m->tune[sl][b]]), 128, m->cfg.d_model / m->cfg.n_heads,
+                     (tiles[m->tune[sl][b]] & kAttnWaveForm) ? 64 : 256};
       else
         t = TileDims{64 << m->tune[sl][b], m->cfg.d_model, 16, 512};
       char e[256];

@@ -43,10 +43,19 @@ struct Workspace {
   AttnItem* work = nullptr;        // attention work list
   StageDesc* desc = nullptr;       // [stages] stage table of the call
   int32_t* ctr = nullptr;          // current stage index (device)
-  int64_t* h_off = nullptr;        // pinned staging
-  AttnItem* h_work = nullptr;
-  StageDesc* h_desc = nullptr;
-  int64_t h_cap_ev = 0, h_cap_items = 0;
+  // Pinned staging of the host-built arrays a call uploads (offsets, attention work lists,
+  // stage table), two sets used by alternate calls. A set's event is recorded after the
+  // copies that read it; a call waits on it before rewriting the set, so it only waits for
+  // the uploads of the call two calls back, never for the device work of the last one.
+  struct HostStage {
+    int64_t* off = nullptr;
+    AttnItem* work = nullptr;
+    StageDesc* desc = nullptr;
+    int64_t cap_ev = 0, cap_items = 0, cap_desc = 0;
+    hipEvent_t ev = nullptr;
+    bool live = false;             // ev recorded and not yet waited for
+  } hs[2];
+  int cur = 0;                     // set of the current call
   int cap_desc = 0;
   uint64_t generation = 0;         // bumped whenever a buffer is reallocated
 };
