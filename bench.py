@@ -8,15 +8,20 @@ resident in HBM when the timed region starts, and outputs stay in HBM.
   value            BF16-path events/s (BF16 MFMA operands, FP32 accumulation/state), timed
                    with per-kernel HIP events on (kernels launched one by one)
   graph_replay     the same steps right after, with timing off (each stage one graph replay)
-  fp32             the same workload on the plain FP32 path
-  error            worst per-feature normwise error of both paths against the FP64 oracle,
-                   on the events of the CPU sample
+  fp32             the same workload on the plain FP32 path (median of per-call times)
+  fp8              the same workload with FP8 operands for the MLP projections
+  error            errors against the FP64 oracle's stored outputs of the first 256 events
+                   (normwise per feature and elementwise), BF16 against FP32, pT / eta response
   roofline         the kernel class with the largest device time, timed with HIP events
                    on its launch stream during the timed steps
   cpu_baseline     the FP64 oracle on a bounded sample of the same events, host cores
-  reco_multiplicity  the same workload with per-event reco counts differing from the truth
-                   counts (fmd_simulate_reco); truth_selection and observables: the steps
+  reco_multiplicity  the same workload with reco counts drawn on the device (missed truth
+                   particles, extra slots); truth_selection and observables: the steps
                    before and after the sampler
+  batch_workload   65,536 events with heavy-tailed multiplicities in one call
+  latency          the continuous-batching server under open-loop Poisson load, 1k-50k
+                   events/s offered, with its saturation throughput and the batch path on the
+                   same request mix
 Prints one JSON line on stdout.
 """
 
@@ -146,14 +151,51 @@ def select_leg(fmd, torch, off, feat_d, cut, limit, reps):
             "particles_out": int(o2[-1]), "calls": reps}
 
 
+def batch_leg(fmd, torch, configs, events, params):
+    """The batching workload (65,536 events, heavy-tailed multiplicities, BF16, RK4 16) as one
+    fmd_simulate call: one warm-up call (which also runs the autotuner for this size), then one
+    timed call; the attention and fused-kernel choices of the autotuner for its size bucket."""
+    wb = configs.BATCH_BF16
+    off, feat = events.for_workload(wb)
+    feat_d = torch.from_numpy(feat).cuda()
+    m = fmd.Model(wb.model, params.draw(wb.model, wb.weight_seed))
+    out = torch.empty((int(off[-1]), 9), dtype=torch.float32, device="cuda")
+    m.simulate(off, feat_d, wb.noise_seed, wb.schedule, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    m.simulate(off, feat_d, wb.noise_seed, wb.schedule, out=out)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    table = m.tuning_table()["entries"]
+    m.close()
+    E, T = len(off) - 1, int(off[-1])
+    flops = event_flops(wb.model, np.diff(off), wb.schedule.evals)
+    del out, feat_d
+    torch.cuda.empty_cache()
+    return {"workload": WORKLOAD_TEXT["batch"], "events": E, "particles": T,
+            "ms_per_call": round(dt * 1e3, 1), "events_per_s": round(E / dt, 1),
+            "mfma_frac": round(flops / dt / (PEAK_TFLOPS["bf16"] * 1e12), 4),
+            "tiles": {e["site"]: f"{e['BM']}x{e['BN']}x{e['BK']}/{e['threads']}t" for e in table},
+            "tuning": [{k: e[k] for k in ("site", "tokens_log2", "tile", "us", "candidates_us")}
+                       for e in table]}
+
+
+# stand-in reco multiplicity law of the reco leg: 5% of truth particles missed, Binomial(64, 1/4)
+# extra slots per event (16 on average)
+RECO_LAW = (0.05, 0.25, 64)
+
+
 def reco_leg(fmd, torch, cfg, flat, off, feat_d, w, steps):
-    """The sampler with reco multiplicities that differ from the truth multiplicities (each
-    event's count scaled by a seeded factor in [0.8, 1.3]): wall time per step on the same
-    workload, timed like the main path."""
+    """The sampler with reco multiplicities that differ from the truth multiplicities, drawn on
+    the device (fmd_reco_multiplicity, law RECO_LAW): the draw's wall time per call, and the
+    sampler's wall time per step on the same workload, timed like the main path."""
     n = np.diff(off)
-    f = np.random.default_rng(11).uniform(0.8, 1.3, len(n))
-    r = np.where(n > 0, np.clip(np.rint(n * f), 1, cfg.n_max), 0).astype(np.int64)
-    roff = np.r_[0, np.cumsum(r)].astype(np.int64)
+    q, p, trials = RECO_LAW
+    roff = fmd.reco_multiplicity(off, w.noise_seed, q, p, trials, cfg.n_max)
+    t0 = time.perf_counter()
+    for _ in range(10):
+        fmd.reco_multiplicity(off, w.noise_seed, q, p, trials, cfg.n_max)
+    draw_ms = (time.perf_counter() - t0) / 10 * 1e3
     m = fmd.Model(cfg, flat)
     out = torch.empty((int(roff[-1]), 9), dtype=torch.float32, device="cuda")
     m.simulate(off, feat_d, w.noise_seed, w.schedule, out=out, reco_offsets=roff)
@@ -165,7 +207,10 @@ def reco_leg(fmd, torch, cfg, flat, off, feat_d, w, steps):
     dt = (time.perf_counter() - t0) / steps
     m.close()
     E = len(n)
-    return {"entry": "fmd_simulate_reco", "reco_slots": int(roff[-1]), "truth_particles": int(off[-1]),
+    return {"entry": "fmd_reco_multiplicity + fmd_simulate_reco",
+            "law": {"loss_prob": q, "fake_prob": p, "fake_trials": trials},
+            "reco_slots": int(roff[-1]), "truth_particles": int(off[-1]),
+            "count_draw_ms_per_call": round(draw_ms, 3),
             "ms_per_step": round(dt * 1e3, 2), "events_per_s": round(E / dt, 1),
             "reco_slots_per_s": round(int(roff[-1]) / dt, 1), "steps": steps}
 
@@ -384,6 +429,7 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp8", action="store_true", help="skip the FP8-operand leg")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batching-workload leg")
     ap.add_argument("--fp8-steps", type=int, default=3)
     ap.add_argument("--cpu-sample", type=int, default=0, help="oracle events (0: 6 per core)")
     ap.add_argument("--no-serve", action="store_true")
@@ -456,7 +502,7 @@ def main():
     reco = None
     if not a.no_reco:
         reco = reco_leg(fmd, torch, w.model, flat, off, feat_d, w, 1)
-        log(f"reco multiplicities x[0.8, 1.3]: {reco['reco_slots']} slots for "
+        log(f"reco multiplicities drawn on the device: {reco['reco_slots']} slots for "
             f"{reco['truth_particles']} truth particles, {reco['ms_per_step']:.1f} ms/step, "
             f"{reco['events_per_s']:.1f} events/s")
 
@@ -473,6 +519,12 @@ def main():
         fp32 = {"events_per_s": round(ev32, 2), "ms_per_step": round(med32 * 1e3, 2),
                 "steps": a.fp32_steps, "timing": "median of per-call times",
                 "roofline": rl32, "tiles": kern32["_tiles"]}
+
+    batch = None
+    if not a.no_batch and a.workload == "base":
+        batch = batch_leg(fmd, torch, configs, events, params)
+        log(f"batching workload: {batch['ms_per_call']:.0f} ms per call, {batch['events_per_s']} "
+            f"events/s, tiles {batch['tiles']}")
 
     fp8 = None
     if not a.no_fp8 and a.workload == "base":
@@ -524,7 +576,7 @@ def main():
                    "tiles": kern16["_tiles"]},
         "graph_replay": graph, "fp32": fp32, "error": err,
         "latency": serve, "truth_selection": selection, "observables": obs,
-        "reco_multiplicity": reco, "fp8": fp8,
+        "reco_multiplicity": reco, "fp8": fp8, "batch_workload": batch,
         "roofline": rl, "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -393,172 +393,6 @@ __device__ __forceinline__ void attention32_body(
   }
 }
 
-// The same work with one wave per (work item, head) and no workgroup barriers: the
-// workgroup's four waves are independent units. K is read from memory straight into the
-// A-operand registers of S^T = K Q^T (16 consecutive keys x 32 dims of a head-major plane per
-// 16-key block: one contiguous kilobyte), so only V^T is staged, in an LDS region private to
-// the wave. Work items have at most 64 queries (4 tiles of 16, the wave carries the running
-// softmax state of all four); keys stream in chunks of 128.
-constexpr int kQtW = 64;            // queries per work item of the wave form
-__device__ __forceinline__ void attention32w_body(
-    const bf16* __restrict__ Q, int ldq, int64_t hsq, const bf16* __restrict__ Kp,
-    const bf16* __restrict__ Vp, int ldkv, int64_t hskv, bf16* __restrict__ O, int ldo,
-    int64_t hso, const AttnItem* __restrict__ work, const AttnBins& bins, int n_heads, float sl2e) {
-  // per wave: V^T rows 0-31 and the key validity row 32 (pitch kLdV32)
-  __shared__ __attribute__((aligned(16))) bf16 Vs[4][(kH32 + 1) * kLdV32];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int g = lane >> 4, j = lane & 15;
-  bf16* Vt = Vs[wave];
-  // workgroup b: bin b % kAttnBins (so one XCD), units 4 (b / kAttnBins) + wave of that bin
-  const int bin = blockIdx.x % kAttnBins;
-  const int unit = (blockIdx.x / kAttnBins) * 4 + wave;
-  const int item = unit / n_heads;
-  if (item >= bins.len[bin]) return;     // a whole wave leaves: there are no barriers
-  const AttnItem wk = work[bins.start[bin] + item];
-  const int h = unit % n_heads;
-  const int64_t qs0 = wk.q0, ks0 = wk.k0;
-  const int nq = wk.nq, nk = wk.nk;
-  const int ntile = (nq + 15) >> 4;       // 1..4, wave-uniform
-
-  float m_run[4];
-  f32x4 o[4][3];
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    m_run[t] = -INFINITY;
-#pragma unroll
-    for (int db = 0; db < 3; ++db) o[t][db] = f32x4{0.f, 0.f, 0.f, 0.f};
-  }
-  const char* qc = (const char*)(Q + qs0 * ldq + h * hsq);
-  for (int c0 = 0; c0 < nk; c0 += kKc2) {
-    const int lim = nk - 1 - c0;
-    // K blocks of this chunk as A operands: lane (j, g) holds key 16 kb + j, dims 8g..8g+7
-    bf16x8 kf[8];
-    {
-      const char* kc = (const char*)(Kp + (ks0 + c0) * ldkv + h * hskv);
-#pragma unroll
-      for (int kb = 0; kb < 8; ++kb)
-        kf[kb] = __builtin_bit_cast(
-            bf16x8, *(const u32x4*)(kc + (uint32_t)((min(kb * 16 + j, lim) * ldkv + 8 * g) * 2)));
-    }
-    // V^T of the chunk into this wave's region: lane = (4 consecutive keys kq, 16 dims)
-    {
-      const char* vc = (const char*)(Vp + (ks0 + c0) * ldkv + h * hskv);
-      const int kq = lane & 31, half = lane >> 5;
-      u32x4 v[8];
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-          const int key = kq * 4 + r;
-          v[2 * r + q] = *(const u32x4*)(vc + (uint32_t)((min(key, lim) * ldkv + (2 * half + q) * 8) * 2));
-          if (key > lim) v[2 * r + q] = u32x4{0u, 0u, 0u, 0u};
-        }
-      const int pos = vt_pos(kq * 4);
-      if (half == 0) {
-        bf16x4 valid;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) valid[r] = (bf16)(kq * 4 + r <= lim ? 1.f : 0.f);
-        *(bf16x4*)&Vt[kH32 * kLdV32 + pos] = valid;
-      }
-#pragma unroll
-      for (int q = 0; q < 2; ++q)
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-          bf16x4 w4;
-#pragma unroll
-          for (int r = 0; r < 4; ++r) w4[r] = __builtin_bit_cast(bf16x8, v[2 * r + q])[i];
-          *(bf16x4*)&Vt[((2 * half + q) * 8 + i) * kLdV32 + pos] = w4;
-        }
-    }
-    // the wave's own LDS stores complete before its reads (LDS operations of one wave are
-    // served in order; the fence keeps the compiler from moving reads above the stores)
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      if (t >= ntile) break;             // wave-uniform
-      const int qi = t * 16 + j;
-      u32x4 qv = *(const u32x4*)(qc + (uint32_t)((min(qi, nq - 1) * ldq + 8 * g) * 2));
-      if (qi >= nq) qv = u32x4{0u, 0u, 0u, 0u};
-      const bf16x8 qf = __builtin_bit_cast(bf16x8, qv);
-      f32x4 sc[8];
-#pragma unroll
-      for (int kb = 0; kb < 8; ++kb)
-        sc[kb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kf[kb], qf, f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
-      float cmax = -INFINITY;
-#pragma unroll
-      for (int kb = 0; kb < 8; ++kb)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) cmax = fmaxf(cmax, sc[kb][r]);
-      cmax = fmaxf(cmax, __shfl_xor(cmax, 16, kWave));
-      cmax = fmaxf(cmax, __shfl_xor(cmax, 32, kWave));
-      const float m_new = fmaxf(m_run[t], cmax);
-      const float alpha = __builtin_amdgcn_exp2f((m_run[t] - m_new) * sl2e);
-#pragma unroll
-      for (int db = 0; db < 3; ++db) o[t][db] *= alpha;
-      const float mb = -m_new * sl2e;
-#pragma unroll
-      for (int kb = 0; kb < 8; ++kb)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) sc[kb][r] = __builtin_amdgcn_exp2f(fmaf(sc[kb][r], sl2e, mb));
-      m_run[t] = m_new;
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        bf16x8 pb;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          pb[r] = (bf16)sc[2 * c][r];
-          pb[4 + r] = (bf16)sc[2 * c + 1][r];
-        }
-#pragma unroll
-        for (int db = 0; db < 2; ++db) {
-          const bf16x8 vf = *(const bf16x8*)&Vt[(db * 16 + j) * kLdV32 + 32 * c + 8 * g];
-          o[t][db] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vf, pb, o[t][db], 0, 0, 0);
-        }
-        // row-sum block: row 0 = key validity (lanes j = 0), rows 1-15 zero
-        bf16x8 vld = *(const bf16x8*)&Vt[kH32 * kLdV32 + 32 * c + 8 * g];
-        if (j != 0) vld = bf16x8{};
-        o[t][2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vld, pb, o[t][2], 0, 0, 0);
-      }
-    }
-    // the next chunk's stores must not pass this chunk's reads
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  }
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    if (t >= ntile) break;
-    const int qi = t * 16 + j;
-    const float l = __shfl(o[t][2][0], j, kWave);
-    const float inv = 1.0f / l;
-    if (qi < nq) {
-      bf16* orow = O + (qs0 + qi) * ldo + h * hso;
-#pragma unroll
-      for (int db = 0; db < 2; ++db) {
-        bf16x4 w4;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) w4[r] = (bf16)(o[t][db][r] * inv);
-        *(bf16x4*)(orow + db * 16 + 4 * g) = w4;
-      }
-    }
-  }
-}
-
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_attn32w_self(
-    const bf16* __restrict__ Q, int ldq, int64_t hsq, const bf16* __restrict__ K,
-    const bf16* __restrict__ V, int ldkv, int64_t hskv, bf16* __restrict__ O, int ldo,
-    int64_t hso, const AttnItem* __restrict__ work, AttnBins bins, int n_heads, float sl2e) {
-  attention32w_body(Q, ldq, hsq, K, V, ldkv, hskv, O, ldo, hso, work, bins, n_heads, sl2e);
-}
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_attn32w_cross(
-    const bf16* __restrict__ Q, int ldq, int64_t hsq, const bf16* __restrict__ K,
-    const bf16* __restrict__ V, int ldkv, int64_t hskv, bf16* __restrict__ O, int ldo,
-    int64_t hso, const AttnItem* __restrict__ work, AttnBins bins, int n_heads, float sl2e) {
-  attention32w_body(Q, ldq, hsq, K, V, ldkv, hskv, O, ldo, hso, work, bins, n_heads, sl2e);
-}
-
 template <int TPW>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_attn32_self(
     const bf16* __restrict__ Q, int ldq, int64_t hsq, const bf16* __restrict__ K,
@@ -659,10 +493,9 @@ int attention_query_tile(bool bf16, int dh, int n_heads) {
 
 int attention_query_tiles(bool bf16, int dh, int* tiles) {
   if (bf16 && dh == kH32) {
-    tiles[0] = 64;                    // workgroup per (item, head), one 16-query tile per wave
-    tiles[1] = 128;                   // two per wave
-    tiles[2] = kQtW | kAttnWaveForm;  // one wave per (item, head), four tiles
-    return 3;
+    tiles[0] = 64;    // one 16-query tile per wave
+    tiles[1] = 128;   // two
+    return 2;
   }
   tiles[0] = QT;
   return 1;
@@ -682,21 +515,9 @@ hipError_t launch_attention(hipStream_t st, bool cross, int dh, int n_heads, int
       if (ldq % 8 || ldkv % 8 || ldo % 4 || hsq % 8 || hskv % 8 || hso % 4 || hsq < dh ||
           hskv < dh || hso < dh)
         return hipErrorInvalidValue;
-      const bool wave_form = (qt & kAttnWaveForm) != 0;
-      const int64_t blocks = wave_form ? (int64_t)kAttnBins * ((bins.max_len * (int64_t)n_heads + 3) / 4)
-                                       : (int64_t)kAttnBins * bins.max_len * n_heads;
+      const int64_t blocks = (int64_t)kAttnBins * bins.max_len * n_heads;
       if (blocks > 0x7fffffff) return hipErrorInvalidValue;
       if (blocks == 0) return hipSuccess;
-      if (wave_form) {
-        if (attn_items_qt(qt) != kQtW) return hipErrorInvalidValue;
-        if (cross)
-          hipLaunchKernelGGL(k_attn32w_cross, dim3((unsigned)blocks), dim3(256), 0, st, Q, ldq, hsq, K,
-                             V, ldkv, hskv, O, ldo, hso, work, bins, n_heads, sl2e);
-        else
-          hipLaunchKernelGGL(k_attn32w_self, dim3((unsigned)blocks), dim3(256), 0, st, Q, ldq, hsq, K,
-                             V, ldkv, hskv, O, ldo, hso, work, bins, n_heads, sl2e);
-        return hipGetLastError();
-      }
 #define FMD_ATTN32_GO(TPW)                                                                     \
   do {                                                                                          \
     if (cross)                                                                                  \

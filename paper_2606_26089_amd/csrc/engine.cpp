@@ -291,8 +291,7 @@ int stage_events(fmd_model* m, const fmd_events_in* ev, Call& c, const int64_t* 
   int tiles[4];
   const int n_tiles = attn_tiles(m, tiles);
   std::vector<int64_t> ids((size_t)E);
-  auto count_items = [&](int code) {
-    const int qt = attn_items_qt(code);
+  auto count_items = [&](int qt) {
     int64_t k = 0;
     for (int64_t e = 0; e < E; ++e) k += (roff[e + 1] - roff[e] + qt - 1) / qt;
     return k;
@@ -324,7 +323,7 @@ int stage_events(fmd_model* m, const fmd_events_in* ev, Call& c, const int64_t* 
     for (int k = 0; k < n_tiles && status == FMD_OK; ++k) {
       const int64_t nk = count_items(tiles[k]);
       AttnBins bk{};
-      if (build_attention_work(roff, roff, ids.data(), E, attn_items_qt(tiles[k]), hs.work, &bk) != nk) {
+      if (build_attention_work(roff, roff, ids.data(), E, tiles[k], hs.work, &bk) != nk) {
         status = fail(FMD_E_INVALID, "token rows beyond 2^31");
         break;
       }
@@ -357,7 +356,7 @@ int stage_events(fmd_model* m, const fmd_events_in* ev, Call& c, const int64_t* 
   c.items = items;
   const int64_t all_items = reco_off ? 2 * items : items;
   std::memcpy(hs.off, roff, (size_t)(E + 1) * 8);
-  if (build_attention_work(hs.off, hs.off, ids.data(), E, attn_items_qt(qt), hs.work, &c.bins) != items)
+  if (build_attention_work(hs.off, hs.off, ids.data(), E, qt, hs.work, &c.bins) != items)
     return fail(FMD_E_INVALID, "token rows beyond 2^31");
   same_truth(c);
   if (reco_off) {
@@ -365,7 +364,7 @@ int stage_events(fmd_model* m, const fmd_events_in* ev, Call& c, const int64_t* 
     c.Ttp = round_up(std::max<int64_t>(Tt, 1), kGemmBM);
     c.work_x = items;
     c.sum_nx = sx;
-    if (build_attention_work(hs.off, ev->offsets, ids.data(), E, attn_items_qt(qt), hs.work + items,
+    if (build_attention_work(hs.off, ev->offsets, ids.data(), E, qt, hs.work + items,
                              &c.bins_x) != items)
       return fail(FMD_E_INVALID, "token rows beyond 2^31");
   }
@@ -1617,9 +1616,8 @@ int fmd_tuning_table(fmd_model* m, char* buf, size_t cap, size_t* needed) {
       TileDims t{};
       if (sl < TS_GEMM)
         t = tile_dims(m->tune[sl][b]);
-      else if (sl == TS_ATTN)   // threads: 64 for the form with one wave per (item, head)
-        t = TileDims{attn_items_qt(tiles[m->tune[sl][b]]), 128, m->cfg.d_model / m->cfg.n_heads,
-                     (tiles[m->tune[sl][b]] & kAttnWaveForm) ? 64 : 256};
+      else if (sl == TS_ATTN)
+        t = TileDims{tiles[m->tune[sl][b]], 128, m->cfg.d_model / m->cfg.n_heads, 256};
       else
         t = TileDims{64 << m->tune[sl][b], m->cfg.d_model, 16, 512};
       char e[256];

@@ -86,11 +86,6 @@ hipError_t launch_row_stats(hipStream_t st, const float* A, int ld, int K, int64
 // with the tile it is given.
 int attention_query_tile(bool bf16, int dh, int n_heads);
 int attention_query_tiles(bool bf16, int dh, int* tiles);   // candidates; returns their count
-// A query-tile code: the work items' query count in the low 16 bits; for BF16 heads of 32 the
-// bit kAttnWaveForm selects the form with one wave per (work item, head) instead of one
-// workgroup of four waves.
-constexpr int kAttnWaveForm = 1 << 16;
-inline int attn_items_qt(int code) { return code & 0xFFFF; }
 
 // Attention work list split into kAttnBins bins of whole events with about equal work, each
 // bin's items stored contiguously (bin i: items [start[i], start[i] + len[i])). Workgroup b

@@ -281,7 +281,7 @@ int iterate(fmd_server* S, int k, std::vector<Req*>& finished) {
   if (span == 0) return FMD_OK;
   // work items of the query tile tuned for this size (the default where none is)
   const int qt = attn_tile_for(m, round_up(span, kGemmBM));
-  for (const auto& rs : real) items += (rs.second + attn_items_qt(qt) - 1) / attn_items_qt(qt);
+  for (const auto& rs : real) items += (rs.second + qt - 1) / qt;
   // self-attention items, then cross-attention items (reco queries, truth keys)
   FMD_TRY(ensure_ws(m, span, E, 2 * items));
   FMD_TRY(reserve_pinned(g.off, g.cap_off, (size_t)E + 1));
@@ -301,9 +301,9 @@ int iterate(fmd_server* S, int k, std::vector<Req*>& finished) {
     std::vector<int64_t> ids(real.size());
     for (size_t i = 0; i < real.size(); ++i) ids[i] = real[i].first;
     if (build_attention_work(off.data(), off.data(), ids.data(), (int64_t)real.size(),
-                             attn_items_qt(qt), g.work, &bins) != items ||
+                             qt, g.work, &bins) != items ||
         build_attention_work_kv(off.data(), kv0.data(), kvn.data(), ids.data(),
-                                (int64_t)real.size(), attn_items_qt(qt), g.work + items, &bins_x) != items)
+                                (int64_t)real.size(), qt, g.work + items, &bins_x) != items)
       return fail(FMD_E_INVALID, "token rows beyond 2^31");
   }
   if (E > w.cap_desc) {   // (the reallocation waits for the device to go idle)

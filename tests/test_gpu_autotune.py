@@ -1,6 +1,6 @@
 """The autotuner on the fused BF16 path (GPU): for the sizes a call runs it times the attention
-form (work items of 64 or 128 queries per workgroup, or of 64 queries per wave) and the row
-tile of block 0's QKV kernel and of the OQC kernel (64 or 128 rows), keeps the fastest, and
+query tile (work items of 64 or 128 queries) and the row tile of block 0's QKV kernel and of
+the OQC kernel (64 or 128 rows), keeps the fastest, and
 reports them in the tuning table. Every candidate must give bitwise-identical results, so the
 choice cannot change what is computed: each combination is forced in turn and the sampler's
 output compared bit for bit, on ragged events that span several tiles and key chunks (an event
@@ -31,14 +31,14 @@ def test_candidates_are_tuned_reported_and_bitwise_equal():
     tuned = m.simulate(off, feat, 4, sched).cpu().numpy()
     table = m.tuning_table()["entries"]
     sites = {e["site"]: e for e in table}
-    for name, n in (("attn_query_tile", 3), ("fused_qkv", 2), ("fused_oqc", 2)):
+    for name, n in (("attn_query_tile", 2), ("fused_qkv", 2), ("fused_oqc", 2)):
         assert name in sites, table
         assert len(sites[name]["candidates_us"]) == n
     assert sites["attn_query_tile"]["BM"] in (64, 128)
     bucket = sites["fused_oqc"]["tokens_log2"]
     assert all(e["tokens_log2"] == bucket for e in table)
     outs = []
-    for a, q, o in itertools.product((0, 1, 2), (0, 1), (0, 1)):
+    for a, q, o in itertools.product((0, 1), repeat=3):
         m.tuning_set(fmd.TUNE_ATTN_QUERY_TILE, bucket, a)
         m.tuning_set(fmd.TUNE_FUSED_QKV, bucket, q)
         m.tuning_set(fmd.TUNE_FUSED_OQC, bucket, o)

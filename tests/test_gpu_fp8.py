@@ -18,8 +18,16 @@ from workload import configs, errors, events, params
 pytestmark = pytest.mark.gpu
 
 CFG = dataclasses.replace(configs.BASE_MODEL.with_precision(configs.FP8), n_max=1000)
-# normwise error bar of the FP8 form per output feature (derivation in the design notes)
+CFG_BF16 = dataclasses.replace(configs.BASE_MODEL.with_precision(configs.BF16), n_max=1000)
+# The FP8 form's error is predicted at 12.1 times the BF16 form's (e4m3 against BF16 unit
+# roundoff on the MLP projections, 16 of the 28 d^2 multiply-adds of a block, errors adding
+# in quadrature by work share). Sampling runs on ragged events: normwise bar 8e-2 per output
+# feature (2.5x that prediction on the base workload). One velocity evaluation of a network
+# with perturbed biases and gains, where nothing averages: the BF16 bar (2e-2) scaled by the
+# predicted factor, and the measured FP8 / BF16 ratio on the same inputs within twice it.
 TOL_FP8 = 8e-2
+FP8_OVER_BF16 = 12.1
+TOL_FP8_VELOCITY = FP8_OVER_BF16 * 2e-2
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "oracle_base_rk4x16_first256.npz")
 
 
@@ -42,18 +50,25 @@ def test_fp8_velocity_and_sampling_match_the_oracle(env):
     flat = params.draw(CFG, seed=0, perturbed=True)
     m = fmd.Model(CFG, flat)
     assert m.tuning_table()["precision"] == "fp8"
-    v = m.velocity(off, dev(torch, feat), dev(torch, x), dev(torch, t)).cpu().numpy()
+    args = (off, dev(torch, feat), dev(torch, x), dev(torch, t))
+    v = m.velocity(*args).cpu().numpy()
     sched = configs.Schedule(configs.RK4, 2)
     out = m.simulate(off, dev(torch, feat), 3, sched).cpu().numpy()
     m.close()
+    m16 = fmd.Model(CFG_BF16, flat)
+    v16 = m16.velocity(*args).cpu().numpy()
+    m16.close()
     P = net.unpack(flat, CFG)
     ref = np.concatenate([net.velocity(P, feat[off[e]:off[e + 1]], x[off[e]:off[e + 1]], float(t[e]))
                           for e in range(len(sizes)) if sizes[e]])
     ev = errors.normwise_rel_err(v, ref).max()
+    ev16 = errors.normwise_rel_err(v16, ref).max()
     ref_s = sample.simulate(flat, CFG, off, feat, sched, seed=3)
     es = errors.normwise_rel_err(out, ref_s).max()
-    print(f"FP8 velocity error {ev:.3e}, sampling error {es:.3e}")
-    assert ev < TOL_FP8 and es < TOL_FP8
+    print(f"FP8 velocity error {ev:.3e} (BF16 {ev16:.3e}, ratio {ev / ev16:.1f}), "
+          f"sampling error {es:.3e}")
+    assert ev < TOL_FP8_VELOCITY and ev < 2 * FP8_OVER_BF16 * ev16
+    assert es < TOL_FP8
 
 
 def test_fp8_event_alone_equals_event_in_batch_and_graphs(env):
