@@ -51,7 +51,11 @@ int grow(P*& p, size_t bytes) {
     p = nullptr;
     return fail(FMD_E_NOMEM, "device allocation of %zu bytes failed", bytes);
   }
+  // The zero fill runs on the null stream, which the library's non-blocking streams do not
+  // wait for: finish it here, or an upload enqueued on such a stream right after the growth
+  // can land first and be wiped.
   if (hipMemset(p, 0, bytes) != hipSuccess) return fail(FMD_E_DEVICE, "hipMemset failed");
+  if (hipDeviceSynchronize() != hipSuccess) return fail(FMD_E_DEVICE, "hipDeviceSynchronize failed");
   return FMD_OK;
 }
 
