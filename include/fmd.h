@@ -344,7 +344,8 @@ int fmd_fused_enable(fmd_model* m, int32_t mask);
 int fmd_autotune_enable(fmd_model* m, int32_t enable);
 
 /* On the BF16 path with heads of 32 the autotuner also chooses, per token bucket, the
- * attention query tile (candidate 0: work items of 64 queries of one event, 1: of 128), and
+ * attention query tile (candidate 0: work items of 64 queries of one event, 1: of 128, 2: of
+ * 192), and
  * on the fused path (d = 256) the row tile of block 0's fused QKV kernel and of the OQC kernel
  * (candidate 0: 64 rows, 1: 128 rows). These too change only the speed: every candidate gives
  * bitwise-identical results.

@@ -495,7 +495,8 @@ int attention_query_tiles(bool bf16, int dh, int* tiles) {
   if (bf16 && dh == kH32) {
     tiles[0] = 64;    // one 16-query tile per wave
     tiles[1] = 128;   // two
-    return 2;
+    tiles[2] = 192;   // three: events of up to 192 slots in one item (one workgroup per head)
+    return 3;
   }
   tiles[0] = QT;
   return 1;
@@ -531,6 +532,8 @@ hipError_t launch_attention(hipStream_t st, bool cross, int dh, int n_heads, int
         FMD_ATTN32_GO(1);
       else if (qt == 128)
         FMD_ATTN32_GO(2);
+      else if (qt == 192)
+        FMD_ATTN32_GO(3);
       else
         return hipErrorInvalidValue;
 #undef FMD_ATTN32_GO

@@ -81,7 +81,7 @@ hipError_t launch_row_stats(hipStream_t st, const float* A, int ld, int K, int64
                             float2* stats);
 
 // Queries per attention work item (event, query tile) for a precision and head shape, by
-// default; BF16 with heads of 32 also accepts the tiles of attention_query_tiles (64 and 128),
+// default; BF16 with heads of 32 also accepts the tiles of attention_query_tiles (64, 128, 192),
 // among which the autotuner chooses. The work lists passed to launch_attention are built
 // with the tile it is given.
 int attention_query_tile(bool bf16, int dh, int n_heads);

@@ -338,7 +338,8 @@ class Model:
 
     def tuning_set(self, site, tokens_log2, candidate):
         """Fixes the autotuner's choice for a fused-path site (TUNE_ATTN_QUERY_TILE,
-        TUNE_FUSED_QKV, TUNE_FUSED_OQC) and a log2 token bucket: candidate 0 (64) or 1 (128)."""
+        TUNE_FUSED_QKV, TUNE_FUSED_OQC) and a log2 token bucket: candidate 0 (64) or 1 (128);
+        the attention site also has 2 (192 queries per work item)."""
         _check(lib().fmd_tuning_set(self._h, int(site), int(tokens_log2), int(candidate)))
 
     def kernel_name(self, cls):

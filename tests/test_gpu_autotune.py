@@ -1,5 +1,5 @@
 """The autotuner on the fused BF16 path (GPU): for the sizes a call runs it times the attention
-query tile (work items of 64 or 128 queries) and the row tile of block 0's QKV kernel and of
+query tile (work items of 64, 128 or 192 queries) and the row tile of block 0's QKV kernel and of
 the OQC kernel (64 or 128 rows), keeps the fastest, and
 reports them in the tuning table. Every candidate must give bitwise-identical results, so the
 choice cannot change what is computed: each combination is forced in turn and the sampler's
@@ -31,20 +31,22 @@ def test_candidates_are_tuned_reported_and_bitwise_equal():
     tuned = m.simulate(off, feat, 4, sched).cpu().numpy()
     table = m.tuning_table()["entries"]
     sites = {e["site"]: e for e in table}
-    for name, n in (("attn_query_tile", 2), ("fused_qkv", 2), ("fused_oqc", 2)):
+    for name, n in (("attn_query_tile", 3), ("fused_qkv", 2), ("fused_oqc", 2)):
         assert name in sites, table
         assert len(sites[name]["candidates_us"]) == n
-    assert sites["attn_query_tile"]["BM"] in (64, 128)
+    assert sites["attn_query_tile"]["BM"] in (64, 128, 192)
     bucket = sites["fused_oqc"]["tokens_log2"]
     assert all(e["tokens_log2"] == bucket for e in table)
     outs = []
-    for a, q, o in itertools.product((0, 1), repeat=3):
+    for a, q, o in itertools.product((0, 1, 2), (0, 1), (0, 1)):
         m.tuning_set(fmd.TUNE_ATTN_QUERY_TILE, bucket, a)
         m.tuning_set(fmd.TUNE_FUSED_QKV, bucket, q)
         m.tuning_set(fmd.TUNE_FUSED_OQC, bucket, o)
         outs.append(((a, q, o), m.simulate(off, feat, 4, sched).cpu().numpy()))
     with pytest.raises(fmd.FmdError):
         m.tuning_set(fmd.TUNE_FUSED_OQC, bucket, 2)
+    with pytest.raises(fmd.FmdError):
+        m.tuning_set(fmd.TUNE_ATTN_QUERY_TILE, bucket, 3)
     with pytest.raises(fmd.FmdError):
         m.tuning_set(0, bucket, 0)           # GEMM sites are not set this way
     m.close()
