@@ -343,6 +343,9 @@ __device__ __forceinline__ float gelu_as(float a, float bu) {
 // 2w and 2w + 1 (64 columns) of all rows and hidden column block w of every chunk.
 constexpr int kWaves4 = 4;
 constexpr int kThreads4 = 64 * kWaves4;
+// sched_barrier mask: instructions of these kinds may be scheduled across it (VALU 0x2,
+// SALU 0x4, LDS reads 0x100); vector-memory loads and MFMAs may not
+constexpr int kKeepLoadsAndMfma = 0x2 | 0x4 | 0x100;
 
 // Fragment t of a weight stream over NC column blocks taken together: K step t / NC of
 // column block t % NC (blocks cstride fragments-of-64-lanes apart).
@@ -388,6 +391,10 @@ __device__ __forceinline__ void mfma_phase_nc(f32x16 (&acc)[TM][NC], const bf16*
       for (int mi = 0; mi < TM; ++mi)
         acc[mi][nj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[mi], b, acc[mi][nj], 0, 0, 0);
     }
+    // keeps the weight loads and the MFMAs of this K step in it (LDS reads and plain
+    // arithmetic may still move): the refill above stays kRing fragments ahead of its use
+    // instead of being sunk next to it, which exposed the L2 latency at every K step
+    __builtin_amdgcn_sched_barrier(kKeepLoadsAndMfma);
   }
 }
 
@@ -728,6 +735,9 @@ __global__ __launch_bounds__(kThreads4) __attribute__((amdgpu_waves_per_eu(2))) 
   const u32x4* woc = Wf_oc + 2 * w * kOcStride;
   auto up_c = [&](int c) { return Wf_up + (4 * c + w) * kKs * 64; };
   auto dn_c = [&](int c) { return Wf_dn + 2 * w * kDnStride + c * kDnKs * 64; };
+  // slab sl of the next block's W_qkv: column blocks 8 sl + 2w, 8 sl + 2w + 1
+  auto qkv_c = [&](int slab) { return nq.Wf + (8 * slab + 2 * w) * kOcStride; };
+  float gq[2], sq[2], bq[2];   // next block's LN1 gain / shift and Q bias (BF16, chained)
   u32x4 ring[kRing];
   ring_fill_nc<2>(ring, woc, kOcStride, lane);
   // head-major attention output [8 heads][Mp][32]
@@ -743,17 +753,23 @@ __global__ __launch_bounds__(kThreads4) __attribute__((amdgpu_waves_per_eu(2))) 
       for (int r = 0; r < 16; ++r) acc[mi][nj][r] = __builtin_nontemporal_load(io.at(mi, r)) + bv;
   }
   __syncthreads();
-  mfma_phase_nc<TM, 2, kKs, 1, false>(acc, A, kLdA, 0, ring, woc, kOcStride, woc, 0, lane);
+  float g3[2], s3[2], bd[2];
+#pragma unroll
+  for (int nj = 0; nj < 2; ++nj) {
+    g3[nj] = g[col0 + 32 * nj];
+    s3[nj] = s[col0 + 32 * nj];
+    if constexpr (QKV && !F8) bd[nj] = b_dn[col0 + 32 * nj];
+  }
+  mfma_phase_nc<TM, 2, kKs, 1, !F8>(acc, A, kLdA, 0, ring, woc, kOcStride, up_c(0), 0, lane);
   row_stats_nc(acc, sl, nullptr, m0, lane, w);   // barriers: A reads done
   if constexpr (!F8) {
-    ring_fill_nc<1>(ring, up_c(0), 0, lane);
     {
       const float* mu = sl.mu[w];
       const float* rs = sl.rs[w];
 #pragma unroll
       for (int nj = 0; nj < 2; ++nj) {
         const int col = col0 + 32 * nj;
-        const float gv = g[col], sv = s[col];
+        const float gv = g3[nj], sv = s3[nj];
 #pragma unroll
         for (int mi = 0; mi < TM; ++mi)
 #pragma unroll
@@ -772,6 +788,8 @@ __global__ __launch_bounds__(kThreads4) __attribute__((amdgpu_waves_per_eu(2))) 
       for (int mi = 0; mi < TM; ++mi)
 #pragma unroll
         for (int r = 0; r < 16; ++r) h2[u][mi][0][r] = 0.f;
+    float bu = b_up[hcol];   // chunk biases one chunk ahead: issued before the chunk's
+                             // weight loads, so their wait does not drain the ring
     mfma_phase_nc<TM, 1, kKs, 1, true>(h2[0], A, kLdA, 0, ring, up_c(0), 0, up_c(1), 0, lane);
     // chunk cc: [up-projection cc+1 | GELU cc] -> barrier -> down-projection cc. Weight stream
     // order: up 0, up 1, down 0, up 2, down 1, ..., up 7, down 6, down 7.
@@ -784,8 +802,10 @@ __global__ __launch_bounds__(kThreads4) __attribute__((amdgpu_waves_per_eu(2))) 
         for (int mi = 0; mi < TM; ++mi)
 #pragma unroll
           for (int r = 0; r < 16; ++r) h2[u ^ 1][mi][0][r] = 0.f;
+        const float bun = b_up[(cc + 1) * kBH + hcol];
         up_gelu_nc<true, TM, 2>(h2[u ^ 1], h2[u], A, ring, up_c(cc + 1), dn_c(cc), kDnStride,
-                                kGeluU * b_up[cc * kBH + hcol], Hc[u], hcol, lane);
+                                kGeluU * bu, Hc[u], hcol, lane);
+        bu = bun;
         __syncthreads();
         mfma_phase_nc<TM, 2, kDnKs, 1, true>(acc, Hc[u], kLdH, 0, ring, dn_c(cc), kDnStride,
                                              up_c(cc + 2), 0, lane);
@@ -796,16 +816,25 @@ __global__ __launch_bounds__(kThreads4) __attribute__((amdgpu_waves_per_eu(2))) 
     for (int mi = 0; mi < TM; ++mi)
 #pragma unroll
       for (int r = 0; r < 16; ++r) h2[1][mi][0][r] = 0.f;
+    const float bu7 = b_up[7 * kBH + hcol];
     up_gelu_nc<true, TM, 2>(h2[1], h2[0], A, ring, up_c(7), dn_c(6), kDnStride,
-                            kGeluU * b_up[6 * kBH + hcol], Hc[0], hcol, lane);
+                            kGeluU * bu, Hc[0], hcol, lane);
     __syncthreads();
     mfma_phase_nc<TM, 2, kDnKs, 2, true>(acc, Hc[0], kLdH, 0, ring, dn_c(6), kDnStride, dn_c(7),
                                          kDnStride, lane);
     up_gelu_nc<false, TM, 2>(h2[0], h2[1], A, ring, up_c(7), dn_c(7), kDnStride,
-                             kGeluU * b_up[7 * kBH + hcol], Hc[1], hcol, lane);
+                             kGeluU * bu7, Hc[1], hcol, lane);
     __syncthreads();
-    mfma_phase_nc<TM, 2, kDnKs, 2, false>(acc, Hc[1], kLdH, 0, ring, dn_c(7), kDnStride, dn_c(7),
-                                          kDnStride, lane);
+    if constexpr (QKV) {
+#pragma unroll
+      for (int nj = 0; nj < 2; ++nj) {
+        gq[nj] = nq.g[col0 + 32 * nj];
+        sq[nj] = nq.s[col0 + 32 * nj];
+        bq[nj] = nq.bias[col0 + 32 * nj];
+      }
+    }
+    mfma_phase_nc<TM, 2, kDnKs, 2, QKV>(acc, Hc[1], kLdH, 0, ring, dn_c(7), kDnStride,
+                                        QKV ? qkv_c(0) : dn_c(7), QKV ? kOcStride : kDnStride, lane);
   } else {
     // FP8 operands for W_up and W_dn: the LayerNorm tile and the hidden chunks as e4m3 bytes
     // (aliasing the BF16 tile and chunk buffers), the residual rows in W_dn's scaled domain
@@ -817,7 +846,7 @@ __global__ __launch_bounds__(kThreads4) __attribute__((amdgpu_waves_per_eu(2))) 
 #pragma unroll
       for (int nj = 0; nj < 2; ++nj) {
         const int col = col0 + 32 * nj;
-        const float gv = g[col], sv = s[col], sd = f8.dn_scale[col];
+        const float gv = g3[nj], sv = s3[nj], sd = f8.dn_scale[col];
 #pragma unroll
         for (int mi = 0; mi < TM; ++mi)
 #pragma unroll
@@ -888,7 +917,7 @@ __global__ __launch_bounds__(kThreads4) __attribute__((amdgpu_waves_per_eu(2))) 
   }
 #pragma unroll
   for (int nj = 0; nj < 2; ++nj) {
-    const float bv = b_dn[col0 + 32 * nj];
+    const float bv = QKV && !F8 ? bd[nj] : b_dn[col0 + 32 * nj];
     const RowIo<float, kD> io(H, m0, col0 + 32 * nj, lane);
 #pragma unroll
     for (int mi = 0; mi < TM; ++mi)
@@ -951,9 +980,7 @@ __global__ __launch_bounds__(kThreads4) __attribute__((amdgpu_waves_per_eu(2))) 
       }
     }
   } else {
-    // slab sl of the next block's W_qkv: column blocks 8 sl + 2w, 8 sl + 2w + 1
-    auto qkv_c = [&](int slab) { return nq.Wf + (8 * slab + 2 * w) * kOcStride; };
-    ring_fill_nc<2>(ring, qkv_c(0), kOcStride, lane);
+    if constexpr (F8) ring_fill_nc<2>(ring, qkv_c(0), kOcStride, lane);
     row_stats_nc(acc, sl, stats_out, m0, lane, w);   // barriers: every wave is past its
     {                                                // last read of the LN3 tile A
       const float* mu = sl.mu[w];
@@ -961,7 +988,7 @@ __global__ __launch_bounds__(kThreads4) __attribute__((amdgpu_waves_per_eu(2))) 
 #pragma unroll
       for (int nj = 0; nj < 2; ++nj) {
         const int col = col0 + 32 * nj;
-        const float gv = nq.g[col], sv = nq.s[col];
+        const float gv = F8 ? nq.g[col] : gq[nj], sv = F8 ? nq.s[col] : sq[nj];
 #pragma unroll
         for (int mi = 0; mi < TM; ++mi)
 #pragma unroll
@@ -973,15 +1000,19 @@ __global__ __launch_bounds__(kThreads4) __attribute__((amdgpu_waves_per_eu(2))) 
     }
     __syncthreads();
     const int64_t plane = rm.Mp * kDh;
+    float bcur[2];
+#pragma unroll
+    for (int nj = 0; nj < 2; ++nj) bcur[nj] = F8 ? nq.bias[col0 + 32 * nj] : bq[nj];
 #pragma unroll 1
     for (int slab = 0; slab < 3; ++slab) {
+      float bnext[2];
 #pragma unroll
       for (int nj = 0; nj < 2; ++nj) {
-        const float bv = nq.bias[slab * kD + col0 + 32 * nj];
 #pragma unroll
         for (int mi = 0; mi < TM; ++mi)
 #pragma unroll
-          for (int r = 0; r < 16; ++r) acc[mi][nj][r] = bv;
+          for (int r = 0; r < 16; ++r) acc[mi][nj][r] = bcur[nj];
+        bnext[nj] = nq.bias[(slab < 2 ? slab + 1 : slab) * kD + col0 + 32 * nj];
       }
       mfma_phase_nc<TM, 2, kKs, 2, true>(acc, A, kLdA, 0, ring, qkv_c(slab), kOcStride,
                                          qkv_c(slab < 2 ? slab + 1 : slab), kOcStride, lane);
@@ -995,6 +1026,8 @@ __global__ __launch_bounds__(kThreads4) __attribute__((amdgpu_waves_per_eu(2))) 
 #pragma unroll
           for (int r = 0; r < 16; ++r) __builtin_nontemporal_store((bf16)acc[mi][nj][r], io.at(mi, r));
       }
+#pragma unroll
+      for (int nj = 0; nj < 2; ++nj) bcur[nj] = bnext[nj];
     }
   }
 }
