@@ -402,12 +402,25 @@ __device__ __forceinline__ void mfma_phase_nc(f32x16 (&acc)[TM][NC], const bf16*
 // column block, 16 K steps) software-pipelined with the GELU of the previous chunk's
 // products h2 (two values per K step, bias term bv = bias x kGeluU, BF16 into the hidden
 // tile hb at column hcol); the prefetch past the end reads the next phase's stream (NCN blocks).
-template <bool UP, int TA, int NCN>
+// GELU of P values of h2 starting at value v0 (value v: row block v / 16, register v % 16),
+// bias term bv = bias x kGeluU, written as BF16 into the hidden tile hb at column hcol
+template <int TA, int P>
+__device__ __forceinline__ void gelu_vals(const f32x16 (&h2)[TA][1], int v0, float bv,
+                                          bf16* __restrict__ hb, int hcol, int lane) {
+#pragma unroll
+  for (int q = 0; q < P; ++q) {
+    const int v = v0 + q, mi = v >> 4, r = v & 15;
+    hb[acc_row(mi, r, lane) * kLdH + hcol] = (bf16)gelu_as(h2[mi][0][r], bv);
+  }
+}
+
+template <bool UP, int TA, int NCN, int V0 = 0, int NV = 16 * TA>
 __device__ __forceinline__ void up_gelu_nc(f32x16 (&h2n)[TA][1], const f32x16 (&h2)[TA][1],
                                            const bf16* __restrict__ A, u32x4 (&ring)[kRing],
                                            const u32x4* __restrict__ cur,
                                            const u32x4* __restrict__ next, int nstride, float bv,
                                            bf16* __restrict__ hb, int hcol, int lane) {
+  static_assert(NV % kKs == 0, "GELU values spread evenly over the K steps");
   asm volatile("" ::: "memory");
   const bf16* arow = A + (lane & 31) * kLdA + (lane >> 5) * 8;
 #pragma unroll
@@ -423,11 +436,41 @@ __device__ __forceinline__ void up_gelu_nc(f32x16 (&h2n)[TA][1], const f32x16 (&
       for (int mi = 0; mi < TA; ++mi)
         h2n[mi][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[mi], b, h2n[mi][0], 0, 0, 0);
     }
+    gelu_vals<TA, NV / kKs>(h2, V0 + (NV / kKs) * ks, bv, hb, hcol, lane);
+  }
+}
+
+// mfma_phase_nc with the GELU of NV values of h2g (from value V0 on) spread over its K steps
+template <int TM, int NC, int NK, int NCN, bool kNext, int TA, int V0, int NV>
+__device__ __forceinline__ void mfma_gelu_nc(f32x16 (&acc)[TM][NC], const bf16* __restrict__ lds,
+                                             int ld, u32x4 (&ring)[kRing],
+                                             const u32x4* __restrict__ cur, int cstride,
+                                             const u32x4* __restrict__ next, int nstride,
+                                             const f32x16 (&h2g)[TA][1], float bv,
+                                             bf16* __restrict__ hb, int hcol, int lane) {
+  static_assert(NV % NK == 0, "GELU values spread evenly over the K steps");
+  asm volatile("" ::: "memory");
+  constexpr int F = NC * NK;
+  const bf16* arow = lds + (lane & 31) * ld + (lane >> 5) * 8;
 #pragma unroll
-    for (int q = 0; q < TA; ++q) {     // 16 TA values of h2 over the 16 K steps
-      const int v = TA * ks + q, mi = v >> 4, r = v & 15;
-      hb[acc_row(mi, r, lane) * kLdH + hcol] = (bf16)gelu_as(h2[mi][0][r], bv);
+  for (int k = 0; k < NK; ++k) {
+    bf16x8 a[TM];
+#pragma unroll
+    for (int mi = 0; mi < TM; ++mi) a[mi] = *(const bf16x8*)(arow + mi * 32 * ld + k * 16);
+#pragma unroll
+    for (int nj = 0; nj < NC; ++nj) {
+      const int t = k * NC + nj;
+      const bf16x8 b = as_bf16x8(ring[t % kRing]);
+      if (t + kRing < F)
+        ring[t % kRing] = frag_at<NC>(cur, cstride, t + kRing)[lane];
+      else if (kNext)
+        ring[t % kRing] = frag_at<NCN>(next, nstride, t + kRing - F)[lane];
+#pragma unroll
+      for (int mi = 0; mi < TM; ++mi)
+        acc[mi][nj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[mi], b, acc[mi][nj], 0, 0, 0);
     }
+    gelu_vals<TA, NV / NK>(h2g, V0 + (NV / NK) * k, bv, hb, hcol, lane);
+    __builtin_amdgcn_sched_barrier(kKeepLoadsAndMfma);
   }
 }
 
@@ -791,8 +834,13 @@ __global__ __launch_bounds__(kThreads4) __attribute__((amdgpu_waves_per_eu(2))) 
     float bu = b_up[hcol];   // chunk biases one chunk ahead: issued before the chunk's
                              // weight loads, so their wait does not drain the ring
     mfma_phase_nc<TM, 1, kKs, 1, true>(h2[0], A, kLdA, 0, ring, up_c(0), 0, up_c(1), 0, lane);
-    // chunk cc: [up-projection cc+1 | GELU cc] -> barrier -> down-projection cc. Weight stream
-    // order: up 0, up 1, down 0, up 2, down 1, ..., up 7, down 6, down 7.
+    // The GELU of chunk c is done in two halves (values 0-15 and 16-31 of each lane), each
+    // beside matrix work: the first during the down-projection of chunk c-1, the second
+    // during the up-projection of chunk c+1. Chunk 0's first half runs alone.
+    gelu_vals<TM, 16>(h2[0], 0, kGeluU * bu, Hc[0], hcol, lane);
+    // chunk cc: [up-projection cc+1 | GELU cc, second half] -> barrier ->
+    // [down-projection cc | GELU cc+1, first half]. Weight stream order: up 0, up 1, down 0,
+    // up 2, down 1, ..., up 7, down 6, down 7.
 #pragma unroll 1
     for (int c = 0; c < kChunks - 2; c += 2) {
 #pragma unroll
@@ -803,27 +851,27 @@ __global__ __launch_bounds__(kThreads4) __attribute__((amdgpu_waves_per_eu(2))) 
 #pragma unroll
           for (int r = 0; r < 16; ++r) h2[u ^ 1][mi][0][r] = 0.f;
         const float bun = b_up[(cc + 1) * kBH + hcol];
-        up_gelu_nc<true, TM, 2>(h2[u ^ 1], h2[u], A, ring, up_c(cc + 1), dn_c(cc), kDnStride,
-                                kGeluU * bu, Hc[u], hcol, lane);
-        bu = bun;
+        up_gelu_nc<true, TM, 2, 16, 16>(h2[u ^ 1], h2[u], A, ring, up_c(cc + 1), dn_c(cc),
+                                        kDnStride, kGeluU * bu, Hc[u], hcol, lane);
         __syncthreads();
-        mfma_phase_nc<TM, 2, kDnKs, 1, true>(acc, Hc[u], kLdH, 0, ring, dn_c(cc), kDnStride,
-                                             up_c(cc + 2), 0, lane);
+        mfma_gelu_nc<TM, 2, kDnKs, 1, true, TM, 0, 16>(acc, Hc[u], kLdH, ring, dn_c(cc),
+                                                       kDnStride, up_c(cc + 2), 0, h2[u ^ 1],
+                                                       kGeluU * bun, Hc[u ^ 1], hcol, lane);
+        bu = bun;
       }
     }
-    // chunks 6 and 7
+    // chunks 6 and 7: chunk 7's whole GELU beside the down-projection of chunk 6
 #pragma unroll
     for (int mi = 0; mi < TM; ++mi)
 #pragma unroll
       for (int r = 0; r < 16; ++r) h2[1][mi][0][r] = 0.f;
     const float bu7 = b_up[7 * kBH + hcol];
-    up_gelu_nc<true, TM, 2>(h2[1], h2[0], A, ring, up_c(7), dn_c(6), kDnStride,
-                            kGeluU * bu, Hc[0], hcol, lane);
+    up_gelu_nc<true, TM, 2, 16, 16>(h2[1], h2[0], A, ring, up_c(7), dn_c(6), kDnStride,
+                                    kGeluU * bu, Hc[0], hcol, lane);
     __syncthreads();
-    mfma_phase_nc<TM, 2, kDnKs, 2, true>(acc, Hc[0], kLdH, 0, ring, dn_c(6), kDnStride, dn_c(7),
-                                         kDnStride, lane);
-    up_gelu_nc<false, TM, 2>(h2[0], h2[1], A, ring, up_c(7), dn_c(7), kDnStride,
-                             kGeluU * bu7, Hc[1], hcol, lane);
+    mfma_gelu_nc<TM, 2, kDnKs, 2, true, TM, 0, 32>(acc, Hc[0], kLdH, ring, dn_c(6), kDnStride,
+                                                   dn_c(7), kDnStride, h2[1], kGeluU * bu7,
+                                                   Hc[1], hcol, lane);
     __syncthreads();
     if constexpr (QKV) {
 #pragma unroll
