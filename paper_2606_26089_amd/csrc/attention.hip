@@ -215,6 +215,8 @@ FMD_ATTN_KERNEL(k_attn_cross)
 // workgroup, four waves of 16 queries), tuned for gfx950.
 //  - Chunks of 128 keys: most events fit in one, so the load -> barrier -> compute round
 //    trip is paid once. K rows are staged by waves 2-3 and V by waves 0-1, 4 loads each.
+//    A last chunk of at most 96 keys is staged and computed for its first 32, 64 or 96 keys
+//    only (a straight-line form for each, after the loop over full chunks).
 //  - One-dimensional grid over (work item, head), heads fastest: the workgroups that read
 //    the two halves of a K/V cache line run together, so the line is fetched once. (The
 //    work list is sorted longest event first; dealing contiguous ranges of it to the XCDs
@@ -239,6 +241,118 @@ __device__ __forceinline__ int vt_pos(int k) {
   return grp * 32 + 8 * g + 4 * hi + r;
 }
 }  // namespace
+
+// One staged chunk of KB key blocks of 16 for this wave's query tiles: the scores
+// S^T = K Q^T, the online-softmax update of the running max and the output, and
+// O^T += V^T P^T with the row sums of P from the validity row of V^T.
+template <int TPW, int KB>
+__device__ __forceinline__ void attn32_chunk(const bf16* __restrict__ Ks,
+                                             const bf16* __restrict__ Vt,
+                                             const bf16x8 (&qf)[TPW], float (&m_run)[TPW],
+                                             f32x4 (&o)[TPW][3], int nq, int wave, int g, int j,
+                                             float sl2e) {
+  auto qbase = [&](int t) { return (t * 4 + wave) * 16; };
+  // compiler-only barrier: the LDS reads (and so the products) of the forms of this
+  // function are not merged and hoisted above the branches between them
+  asm volatile("" ::: "memory");
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) {
+    if (qbase(t) >= nq) continue;   // wave-uniform
+    // all KB key blocks, also past the event end: no branches, and the zero accumulator
+    // is an inline constant
+    f32x4 s[KB];
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) {
+      const bf16x8 kf = *(const bf16x8*)&Ks[(kb * 16 + j) * kLdK32 + 8 * g];
+      s[kb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kf, qf[t], f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+    }
+    float cmax = -INFINITY;
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) cmax = fmaxf(cmax, s[kb][r]);
+    cmax = fmaxf(cmax, __shfl_xor(cmax, 16, kWave));
+    cmax = fmaxf(cmax, __shfl_xor(cmax, 32, kWave));
+    const float m_new = fmaxf(m_run[t], cmax);    // finite: key c0 < nk is in this chunk
+    const float alpha = __builtin_amdgcn_exp2f((m_run[t] - m_new) * sl2e);
+#pragma unroll
+    for (int db = 0; db < 3; ++db) o[t][db] *= alpha;
+    const float mb = -m_new * sl2e;
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) s[kb][r] = __builtin_amdgcn_exp2f(fmaf(s[kb][r], sl2e, mb));
+    m_run[t] = m_new;
+#pragma unroll
+    for (int c = 0; c < KB / 2; ++c) {
+      bf16x8 pb;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        pb[r] = (bf16)s[2 * c][r];
+        pb[4 + r] = (bf16)s[2 * c + 1][r];
+      }
+#pragma unroll
+      for (int db = 0; db < 2; ++db) {
+        const bf16x8 vf = *(const bf16x8*)&Vt[(db * 16 + j) * kLdV32 + 32 * c + 8 * g];
+        o[t][db] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vf, pb, o[t][db], 0, 0, 0);
+      }
+      const bf16x8 vld = *(const bf16x8*)&Vt[(kH32 + j) * kLdV32 + 32 * c + 8 * g];
+      o[t][2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vld, pb, o[t][2], 0, 0, 0);
+    }
+  }
+}
+
+// Stages keys c0 .. c0 + 16 KB - 1 of the event into Ks and V^T.
+template <int KB>
+__device__ __forceinline__ void attn32_stage(bf16* __restrict__ Ks, bf16* __restrict__ Vt,
+                                             const bf16* __restrict__ Kp,
+                                             const bf16* __restrict__ Vp, int ldkv, int64_t hskv,
+                                             int64_t ks0, int c0, int nk, int h, int tid,
+                                             int wave) {
+  // Keys past the event end are read clamped to its last key: their scores repeat a real
+  // score (the running max is unchanged), and their V rows and validity are zero, so they
+  // add nothing to P V or to the row sums. No per-score masking is needed.
+  const int lim = nk - 1 - c0;
+  if (wave >= 2) {   // K: 16 KB keys x 4 chunks of 16 bytes
+    const char* kc = (const char*)(Kp + (ks0 + c0) * ldkv + h * hskv);
+    const int t2 = tid - 128;
+    u32x4 v[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int idx = t2 + i * 128, row = idx >> 2, ch = idx & 3;
+      if (i < KB / 2) v[i] = *(const u32x4*)(kc + (uint32_t)((min(row, lim) * ldkv + ch * 8) * 2));
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int idx = t2 + i * 128, row = idx >> 2, ch = idx & 3;
+      if (i < KB / 2) *(u32x4*)&Ks[row * kLdK32 + ch * 8] = v[i];
+    }
+  } else if ((tid & 31) < 4 * KB) {   // V^T: thread = (4 consecutive keys, 8 dims)
+    const char* vc = (const char*)(Vp + (ks0 + c0) * ldkv + h * hskv);
+    const int kg = tid & 31, dg = tid >> 5;
+    u32x4 v[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int key = kg * 4 + r;
+      v[r] = *(const u32x4*)(vc + (uint32_t)((min(key, lim) * ldkv + dg * 8) * 2));
+      if (key > lim) v[r] = u32x4{0u, 0u, 0u, 0u};
+    }
+    const int pos = vt_pos(kg * 4);
+    if (dg == 0) {
+      bf16x4 valid;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) valid[r] = (bf16)(kg * 4 + r <= lim ? 1.f : 0.f);
+      *(bf16x4*)&Vt[kH32 * kLdV32 + pos] = valid;
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      bf16x4 w4;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) w4[r] = __builtin_bit_cast(bf16x8, v[r])[i];
+      *(bf16x4*)&Vt[(dg * 8 + i) * kLdV32 + pos] = w4;
+    }
+  }
+}
 
 template <int TPW>
 __device__ __forceinline__ void attention32_body(
@@ -280,97 +394,30 @@ __device__ __forceinline__ void attention32_body(
     for (int db = 0; db < 3; ++db) o[t][db] = f32x4{0.f, 0.f, 0.f, 0.f};
   }
 
-  for (int c0 = 0; c0 < nk; c0 += kKc2) {
-    // Keys past the event end are read clamped to its last key: their scores repeat a real
-    // score (the running max is unchanged), and their V rows and validity are zero, so they
-    // add nothing to P V or to the row sums. No per-score masking is needed.
-    const int lim = nk - 1 - c0;
-    if (wave >= 2) {   // K: 128 keys x 4 chunks of 16 bytes
-      const char* kc = (const char*)(Kp + (ks0 + c0) * ldkv + h * hskv);
-      const int t2 = tid - 128;
-      u32x4 v[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int idx = t2 + i * 128, row = idx >> 2, ch = idx & 3;
-        v[i] = *(const u32x4*)(kc + (uint32_t)((min(row, lim) * ldkv + ch * 8) * 2));
-      }
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int idx = t2 + i * 128, row = idx >> 2, ch = idx & 3;
-        *(u32x4*)&Ks[row * kLdK32 + ch * 8] = v[i];
-      }
-    } else {           // V^T: thread = (4 consecutive keys, 8 consecutive dims)
-      const char* vc = (const char*)(Vp + (ks0 + c0) * ldkv + h * hskv);
-      const int kg = tid & 31, dg = tid >> 5;
-      u32x4 v[4];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int key = kg * 4 + r;
-        v[r] = *(const u32x4*)(vc + (uint32_t)((min(key, lim) * ldkv + dg * 8) * 2));
-        if (key > lim) v[r] = u32x4{0u, 0u, 0u, 0u};
-      }
-      const int pos = vt_pos(kg * 4);
-      if (dg == 0) {
-        bf16x4 valid;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) valid[r] = (bf16)(kg * 4 + r <= lim ? 1.f : 0.f);
-        *(bf16x4*)&Vt[kH32 * kLdV32 + pos] = valid;
-      }
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        bf16x4 w4;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) w4[r] = __builtin_bit_cast(bf16x8, v[r])[i];
-        *(bf16x4*)&Vt[(dg * 8 + i) * kLdV32 + pos] = w4;
-      }
-    }
+  // A last chunk of at most 96 keys is staged and computed for its first 32, 64 or 96 keys
+  // only: the rest are all past the event end (their scores repeat a real score, their
+  // P V and row-sum terms are exact zeros), so the results are the same.
+  const int last = (nk - 1) & (kKc2 - 1);           // last key's position in its chunk
+  const int nfull = last < 96 ? nk - 1 - last : nk;  // keys before the shortened last chunk
+  for (int c0 = 0; c0 < nfull; c0 += kKc2) {
+    attn32_stage<8>(Ks, Vt, Kp, Vp, ldkv, hskv, ks0, c0, nk, h, tid, wave);
     __syncthreads();
-#pragma unroll
-    for (int t = 0; t < TPW; ++t) {
-      if (qbase(t) >= nq) continue;   // wave-uniform
-      // all 8 key blocks, also past the event end: no branches, and the zero accumulator
-      // is an inline constant
-      f32x4 s[8];
-#pragma unroll
-      for (int kb = 0; kb < 8; ++kb) {
-        const bf16x8 kf = *(const bf16x8*)&Ks[(kb * 16 + j) * kLdK32 + 8 * g];
-        s[kb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kf, qf[t], f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
-      }
-      float cmax = -INFINITY;
-#pragma unroll
-      for (int kb = 0; kb < 8; ++kb)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) cmax = fmaxf(cmax, s[kb][r]);
-      cmax = fmaxf(cmax, __shfl_xor(cmax, 16, kWave));
-      cmax = fmaxf(cmax, __shfl_xor(cmax, 32, kWave));
-      const float m_new = fmaxf(m_run[t], cmax);    // finite: key c0 < nk is in this chunk
-      const float alpha = __builtin_amdgcn_exp2f((m_run[t] - m_new) * sl2e);
-#pragma unroll
-      for (int db = 0; db < 3; ++db) o[t][db] *= alpha;
-      const float mb = -m_new * sl2e;
-#pragma unroll
-      for (int kb = 0; kb < 8; ++kb)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) s[kb][r] = __builtin_amdgcn_exp2f(fmaf(s[kb][r], sl2e, mb));
-      m_run[t] = m_new;
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        bf16x8 pb;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          pb[r] = (bf16)s[2 * c][r];
-          pb[4 + r] = (bf16)s[2 * c + 1][r];
-        }
-#pragma unroll
-        for (int db = 0; db < 2; ++db) {
-          const bf16x8 vf = *(const bf16x8*)&Vt[(db * 16 + j) * kLdV32 + 32 * c + 8 * g];
-          o[t][db] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vf, pb, o[t][db], 0, 0, 0);
-        }
-        const bf16x8 vld = *(const bf16x8*)&Vt[(kH32 + j) * kLdV32 + 32 * c + 8 * g];
-        o[t][2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vld, pb, o[t][2], 0, 0, 0);
-      }
-    }
+    attn32_chunk<TPW, 8>(Ks, Vt, qf, m_run, o, nq, wave, g, j, sl2e);
     __syncthreads();
+  }
+  const int rest = nk - nfull;   // 0 .. 96, wave-uniform
+  if (rest > 64) {
+    attn32_stage<6>(Ks, Vt, Kp, Vp, ldkv, hskv, ks0, nfull, nk, h, tid, wave);
+    __syncthreads();
+    attn32_chunk<TPW, 6>(Ks, Vt, qf, m_run, o, nq, wave, g, j, sl2e);
+  } else if (rest > 32) {
+    attn32_stage<4>(Ks, Vt, Kp, Vp, ldkv, hskv, ks0, nfull, nk, h, tid, wave);
+    __syncthreads();
+    attn32_chunk<TPW, 4>(Ks, Vt, qf, m_run, o, nq, wave, g, j, sl2e);
+  } else if (rest > 0) {
+    attn32_stage<2>(Ks, Vt, Kp, Vp, ldkv, hskv, ks0, nfull, nk, h, tid, wave);
+    __syncthreads();
+    attn32_chunk<TPW, 2>(Ks, Vt, qf, m_run, o, nq, wave, g, j, sl2e);
   }
 
 #pragma unroll

@@ -4,7 +4,8 @@ the OQC kernel (64 or 128 rows), keeps the fastest, and
 reports them in the tuning table. Every candidate must give bitwise-identical results, so the
 choice cannot change what is computed: each combination is forced in turn and the sampler's
 output compared bit for bit, on ragged events that span several tiles and key chunks (an event
-of 1, of 64 and 65 queries, one above 128, one of 300)."""
+of 1, of 64 and 65 queries, one above 128, one of 300; last key chunks of every shortened
+length)."""
 
 import dataclasses
 import itertools
@@ -22,7 +23,7 @@ CFG = dataclasses.replace(configs.BASE_MODEL.with_precision(configs.BF16), n_max
 
 def test_candidates_are_tuned_reported_and_bitwise_equal():
     torch, fmd = torch_cuda(), fmd_lib()
-    sizes = [1, 64, 65, 200, 0, 129, 37, 128, 300, 5]
+    sizes = [1, 64, 65, 200, 0, 129, 37, 128, 300, 5, 96, 97, 161, 224]
     off = np.r_[0, np.cumsum(sizes)].astype(np.int64)
     feat = torch.from_numpy(events.particles(np.random.default_rng(6), int(off[-1]))).cuda()
     flat = params.draw(CFG, seed=0, perturbed=True)

@@ -143,6 +143,7 @@ ATTN_CASES = [  # (event sizes, heads, dh)
     ([1], 1, 16), ([2, 31, 32, 33], 4, 16), ([64, 65, 1, 127, 128, 129], 8, 32),
     ([200, 3, 150], 8, 32), ([1000], 2, 32), ([17, 70], 2, 64), ([0, 5, 0, 9], 4, 32),
     ([95, 96, 97, 160, 161, 225, 255, 256, 257], 8, 32),     # 32-key group edges
+    ([31, 32, 33, 63, 192, 193, 224], 8, 32),   # last chunk shortened to 32, 64 or 96 keys
 ]
 
 
