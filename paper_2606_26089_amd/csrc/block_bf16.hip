@@ -127,8 +127,7 @@ __device__ __forceinline__ void load_rows(f32x16 (&acc)[TM], const float* __rest
 }
 
 template <int TM>
-__device__ __forceinline__ void zero(f32x16 (&acc)[TM], const float* __restrict__ bias, int col) {
-  const float bv = bias ? bias[col] : 0.f;
+__device__ __forceinline__ void fill(f32x16 (&acc)[TM], float bv) {
 #pragma unroll
   for (int mi = 0; mi < TM; ++mi)
 #pragma unroll
@@ -277,14 +276,12 @@ __device__ __forceinline__ void row_stats(const f32x16 (&acc)[TM], SharedLn& sl,
   }
 }
 
-// LDS tile A (pitch kLdA) = LayerNorm(acc rows) with gain g and shift s, in BF16.
+// LDS tile A (pitch kLdA) = LayerNorm(acc rows) with gain gv and shift sv of column col, in
+// BF16.
 template <int TM>
 __device__ __forceinline__ void ln_to_lds(const f32x16 (&acc)[TM], const float* __restrict__ mu,
-                                          const float* __restrict__ rs,
-                                          const float* __restrict__ g,
-                                          const float* __restrict__ s, bf16* __restrict__ A,
-                                          int col, int lane) {
-  const float gv = g[col], sv = s[col];
+                                          const float* __restrict__ rs, float gv, float sv,
+                                          bf16* __restrict__ A, int col, int lane) {
 #pragma unroll
   for (int mi = 0; mi < TM; ++mi)
 #pragma unroll
@@ -602,6 +599,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(TM == 
   const int64_t plane = rm.Mp * kDh;   // Mp rows x 32 per head
   const int col = w * 32 + (lane & 31);
   const u32x4* wf = Wf + w * kKs * 64;            // slab s: + s * kWaves * kKs * 64
+  // column parameters first: waiting for them later then does not drain the weight ring
+  const float gv = g[col], sv = s[col];
+  float bcur = bias[col];
   u32x4 ring[kRing];
   if constexpr (!EMBED) ring_fill(ring, wf, lane);
   f32x16 acc[TM];
@@ -634,11 +634,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(TM == 
     load_rows(acc, H, m0, col, nullptr, lane);
   }
   row_stats(acc, sl, nullptr, m0, lane, w);   // barriers: the staged rows are consumed
-  ln_to_lds(acc, sl.mu[w], sl.rs[w], g, s, A, col, lane);
+  ln_to_lds(acc, sl.mu[w], sl.rs[w], gv, sv, A, col, lane);
   __syncthreads();
 #pragma unroll 1
   for (int slab = 0; slab < 3; ++slab) {
-    zero(acc, bias, slab * kD + col);
+    fill(acc, bcur);
+    bcur = bias[(slab < 2 ? slab + 1 : slab) * kD + col];   // the next slab's, ahead of its ring
     const u32x4* cur = wf + slab * kWaves * kKs * 64;
     mfma_phase<TM>(acc, A, kLdA, 0, kKs, ring, cur, slab < 2 ? cur + kWaves * kKs * 64 : cur,
                   lane);
@@ -668,14 +669,16 @@ __global__ __launch_bounds__(kThreads) void k_fused_oqc(
   tile_hm_to_lds<ROWS>(A, att, plane, m0, tid);   // head-major attention output
   f32x16 acc[TM];
   load_rows(acc, H, m0, col, b_o, lane);
+  // column parameters before the weight stream: waiting for them then drains no ring
+  const float gv = g[col], sv = s[col], bq = b_qc[col];
   __syncthreads();
-  mfma_phase<TM, false>(acc, A, kLdA, 0, kKs, ring, wo, wo, lane);
+  // the W_o phase prefetches the first W_qc fragments
+  mfma_phase<TM>(acc, A, kLdA, 0, kKs, ring, wo, wq, lane);
   store_rows_f32(acc, H, m0, col, lane);
   row_stats(acc, sl, nullptr, m0, lane, w);   // barrier: A reads done
-  ring_fill(ring, wq, lane);
-  ln_to_lds(acc, sl.mu[w], sl.rs[w], g, s, A, col, lane);
+  ln_to_lds(acc, sl.mu[w], sl.rs[w], gv, sv, A, col, lane);
   __syncthreads();
-  zero(acc, b_qc, col);
+  fill(acc, bq);
   mfma_phase<TM>(acc, A, kLdA, 0, kKs, ring, wq, wq, lane);
   store_rows_bf16<kDh>(acc, qc + (int64_t)w * plane, m0, lane & 31, lane);   // head-major
 }
@@ -780,7 +783,7 @@ __global__ __launch_bounds__(kThreads4) __attribute__((amdgpu_waves_per_eu(2))) 
   auto dn_c = [&](int c) { return Wf_dn + 2 * w * kDnStride + c * kDnKs * 64; };
   // slab sl of the next block's W_qkv: column blocks 8 sl + 2w, 8 sl + 2w + 1
   auto qkv_c = [&](int slab) { return nq.Wf + (8 * slab + 2 * w) * kOcStride; };
-  float gq[2], sq[2], bq[2];   // next block's LN1 gain / shift and Q bias (BF16, chained)
+  float gq[2], sq[2], bq[2];   // next block's LN1 gain / shift and Q bias (chained form)
   u32x4 ring[kRing];
   ring_fill_nc<2>(ring, woc, kOcStride, lane);
   // head-major attention output [8 heads][Mp][32]
@@ -914,6 +917,8 @@ __global__ __launch_bounds__(kThreads4) __attribute__((amdgpu_waves_per_eu(2))) 
     __syncthreads();
 #pragma unroll 1
     for (int c = 0; c < kChunks; ++c) {
+      // the chunk's GELU scale and bias first: waiting for them then drains no fragment loads
+      const float ui = f8.up_inv[c * kBH + hcol], bu = kGeluU * b_up[c * kBH + hcol];
 #pragma unroll
       for (int nj = 0; nj < 2; ++nj)
 #pragma unroll
@@ -935,7 +940,6 @@ __global__ __launch_bounds__(kThreads4) __attribute__((amdgpu_waves_per_eu(2))) 
         for (int ks = 0; ks < kKs8; ++ks)
           fu[ks] = f8.up[((4 * (c + 1) + w) * kKs8 + ks) * 64 + lane];
       }
-      const float ui = f8.up_inv[c * kBH + hcol], bu = kGeluU * b_up[c * kBH + hcol];
       uint8_t* hb = H8 + (c & 1) * (ROWS * kLdH8);
 #pragma unroll
       for (int mi = 0; mi < TM; ++mi)
@@ -1028,7 +1032,15 @@ __global__ __launch_bounds__(kThreads4) __attribute__((amdgpu_waves_per_eu(2))) 
       }
     }
   } else {
-    if constexpr (F8) ring_fill_nc<2>(ring, qkv_c(0), kOcStride, lane);
+    if constexpr (F8) {   // (the BF16 form loaded these before its last down-projection)
+#pragma unroll
+      for (int nj = 0; nj < 2; ++nj) {
+        gq[nj] = nq.g[col0 + 32 * nj];
+        sq[nj] = nq.s[col0 + 32 * nj];
+        bq[nj] = nq.bias[col0 + 32 * nj];
+      }
+      ring_fill_nc<2>(ring, qkv_c(0), kOcStride, lane);
+    }
     row_stats_nc(acc, sl, stats_out, m0, lane, w);   // barriers: every wave is past its
     {                                                // last read of the LN3 tile A
       const float* mu = sl.mu[w];
@@ -1036,7 +1048,7 @@ __global__ __launch_bounds__(kThreads4) __attribute__((amdgpu_waves_per_eu(2))) 
 #pragma unroll
       for (int nj = 0; nj < 2; ++nj) {
         const int col = col0 + 32 * nj;
-        const float gv = F8 ? nq.g[col] : gq[nj], sv = F8 ? nq.s[col] : sq[nj];
+        const float gv = gq[nj], sv = sq[nj];
 #pragma unroll
         for (int mi = 0; mi < TM; ++mi)
 #pragma unroll
@@ -1050,7 +1062,7 @@ __global__ __launch_bounds__(kThreads4) __attribute__((amdgpu_waves_per_eu(2))) 
     const int64_t plane = rm.Mp * kDh;
     float bcur[2];
 #pragma unroll
-    for (int nj = 0; nj < 2; ++nj) bcur[nj] = F8 ? nq.bias[col0 + 32 * nj] : bq[nj];
+    for (int nj = 0; nj < 2; ++nj) bcur[nj] = bq[nj];
 #pragma unroll 1
     for (int slab = 0; slab < 3; ++slab) {
       float bnext[2];
