@@ -233,6 +233,8 @@ FMD_ATTN_KERNEL(k_attn_cross)
 namespace {
 constexpr int kH32 = 32;
 constexpr int kKc2 = 128;           // keys per chunk
+constexpr int kSchedMfma = 0x008;   // sched_group_barrier instruction classes: MFMA
+constexpr int kSchedDsRead = 0x100; // LDS read
 constexpr int kLdK32 = kH32 + 8;    // Ks pitch (bf16)
 constexpr int kLdV32 = kKc2 + 8;    // Vt pitch (bf16)
 
@@ -261,18 +263,37 @@ __device__ __forceinline__ void attn32_chunk(const bf16* __restrict__ Ks,
     // all KB key blocks, also past the event end: no branches, and the zero accumulator
     // is an inline constant
     f32x4 s[KB];
+    {
+      bf16x8 kf[KB];
 #pragma unroll
-    for (int kb = 0; kb < KB; ++kb) {
-      const bf16x8 kf = *(const bf16x8*)&Ks[(kb * 16 + j) * kLdK32 + 8 * g];
-      s[kb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kf, qf[t], f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+      for (int kb = 0; kb < KB; ++kb) kf[kb] = *(const bf16x8*)&Ks[(kb * 16 + j) * kLdK32 + 8 * g];
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb)
+        s[kb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kf[kb], qf[t], f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+      // the K operand reads kept two ahead of their products (left alone, the compiler reads
+      // each one right before its product into the same registers and waits for it)
+      __builtin_amdgcn_sched_group_barrier(kSchedDsRead, 2, 0);
+#pragma unroll
+      for (int i = 0; i < KB - 2; ++i) {
+        __builtin_amdgcn_sched_group_barrier(kSchedMfma, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(kSchedDsRead, 1, 0);
+      }
+      __builtin_amdgcn_sched_group_barrier(kSchedMfma, 2, 0);
     }
     float cmax = -INFINITY;
 #pragma unroll
     for (int kb = 0; kb < KB; ++kb)
 #pragma unroll
       for (int r = 0; r < 4; ++r) cmax = fmaxf(cmax, s[kb][r]);
-    cmax = fmaxf(cmax, __shfl_xor(cmax, 16, kWave));
-    cmax = fmaxf(cmax, __shfl_xor(cmax, 32, kWave));
+    {   // max over lanes l, l ^ 16, then l, l ^ 32: a row swap and a half swap of the
+        // register with itself, no LDS round trip (max is exact)
+      const auto r16 = __builtin_amdgcn_permlane16_swap(__float_as_uint(cmax),
+                                                        __float_as_uint(cmax), false, false);
+      cmax = fmaxf(__uint_as_float(r16[0]), __uint_as_float(r16[1]));
+      const auto r32 = __builtin_amdgcn_permlane32_swap(__float_as_uint(cmax),
+                                                        __float_as_uint(cmax), false, false);
+      cmax = fmaxf(__uint_as_float(r32[0]), __uint_as_float(r32[1]));
+    }
     const float m_new = fmaxf(m_run[t], cmax);    // finite: key c0 < nk is in this chunk
     const float alpha = __builtin_amdgcn_exp2f((m_run[t] - m_new) * sl2e);
 #pragma unroll
